@@ -1,0 +1,131 @@
+/*
+ * pa.h -- C ABI of the MI355X (gfx950) Toeplitz-hash privacy-amplification
+ * library (libpa.so).
+ *
+ * Operation (paper Sec. 2.1-2.2): privacy amplification publicly applies a
+ * universal hash g: {0,1}^n -> {0,1}^m to the reconciled key; the Toeplitz
+ * family uses an m x n Toeplitz matrix T over GF(2) fixed by its first row
+ * and first column, i.e. by n+m-1 seed bits s, and outputs y = T x mod 2.
+ * Convention: T[i][j] = s[i - j + n - 1] (row 0 = s[n-1], ..., s[0]; column
+ * 0 = s[n-1], ..., s[n+m-2]), so y_i is coefficient n-1+i of the integer
+ * convolution s * x taken mod 2.  The library computes that convolution
+ * exactly with a number-theoretic transform (the exact analogue of the
+ * FFT route of Sec. 2.3 Eq. (4)), so the result is bit-exact.
+ *
+ * Bit arrays: little-endian packed uint64, bit k in word k >> 6 at position
+ * k & 63.  key: ceil(n/64) words; seed: ceil((n+m-1)/64) words; out:
+ * ceil(m/64) words.  Padding bits of key and seed are ignored; padding bits
+ * of out are written as zero.
+ *
+ * Memory: every bit pointer is a DEVICE pointer (HBM of the current HIP
+ * device), 8-byte aligned, owned by the caller, who keeps it alive until
+ * the work enqueued on `stream` has completed.  `out` must not overlap the
+ * inputs.  `stream` is a hipStream_t (NULL = the default stream).  Calls
+ * are asynchronous and stream-ordered; the library owns its workspace
+ * (cached per device and stream) and its transform tables.  Calls on
+ * different streams may run concurrently.
+ *
+ * Errors: argument errors are detected synchronously, before anything is
+ * enqueued, and leave `out` untouched.  PA_ERR_DEVICE reports a HIP runtime
+ * failure; pa_last_error() (thread-local) gives the text of the most recent
+ * failure in the calling thread.
+ */
+#ifndef PA_H_
+#define PA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pa_status {
+    PA_OK = 0,
+    PA_ERR_INVALID_ARG = 1,      /* null pointer, n = 0, m = 0, m > n, bad count */
+    PA_ERR_UNSUPPORTED_SIZE = 2, /* transform length needed exceeds PA_MAX_TRANSFORM_LEN */
+    PA_ERR_OUT_OF_MEMORY = 3,    /* device allocation failed */
+    PA_ERR_DEVICE = 4,           /* HIP runtime error (see pa_last_error) */
+    PA_ERR_BUSY = 5              /* serving queue full / budget cannot admit */
+} pa_status;
+
+/* Largest cyclic-convolution length the arithmetic supports: the prime
+ * modulus 27*2^20+1 admits transform lengths 2^a * 3^b with a <= 20,
+ * b <= 3.  A block needs length >= n - 1 + d + 64*ceil(m/64), where
+ * d = (-(n-1)) mod 64 aligns the output to whole words. */
+#define PA_MAX_TRANSFORM_LEN 28311552ull
+
+/*
+ * y = T x mod 2 for one block (paper Sec. 2.2; the convolution form of
+ * Sec. 2.3 Eq. (4) with the plain, not modified, Toeplitz matrix).
+ * key_bits: n key bits; seed_bits: n+m-1 seed bits; out_bits: m output
+ * bits.  Requires 1 <= m <= n.
+ */
+pa_status pa_toeplitz_hash(const uint64_t *key_bits, uint64_t n,
+                           const uint64_t *seed_bits, uint64_t m,
+                           uint64_t *out_bits, void *stream);
+
+/* One block of a batched call. */
+typedef struct pa_block {
+    const uint64_t *key_bits; /* device, ceil(n/64) words */
+    uint64_t n;
+    const uint64_t *seed_bits; /* device, ceil((n+m-1)/64) words */
+    uint64_t m;
+    uint64_t *out_bits; /* device, ceil(m/64) words */
+} pa_block;
+
+/*
+ * Many independent blocks of uneven (n, m) in one submission.  `blocks` is a
+ * HOST array of `count` descriptors (read during the call only).  Blocks
+ * may share seeds; their outputs must not overlap each other or any input.
+ * A bad block fails the whole call with PA_ERR_INVALID_ARG or
+ * PA_ERR_UNSUPPORTED_SIZE before anything is enqueued; count = 0 is a
+ * no-op.  Results are identical to calling pa_toeplitz_hash per block.
+ */
+pa_status pa_toeplitz_hash_batched(const pa_block *blocks, uint32_t count,
+                                   void *stream);
+
+/*
+ * Seed plans: the transformed seed (spectrum of the seed prefix, scaled by
+ * the inverse length) kept resident in HBM so repeated hashes with one
+ * seed skip the seed transform.  A plan built from seed_len_bits bits with
+ * transform length L serves every (n, m) with n + m - 1 <= seed_len_bits
+ * and required length <= L (seed bits beyond n+m-1 never influence y).
+ * transform_len = 0 picks the smallest supported L covering any n + m - 1
+ * <= seed_len_bits.  The seed buffer may be freed once the plan's stream
+ * work has completed.
+ */
+typedef struct pa_plan_s *pa_plan_t;
+
+pa_status pa_plan_create(const uint64_t *seed_bits, uint64_t seed_len_bits,
+                         uint64_t transform_len, void *stream, pa_plan_t *plan);
+pa_status pa_plan_hash(pa_plan_t plan, const uint64_t *key_bits, uint64_t n,
+                       uint64_t m, uint64_t *out_bits, void *stream);
+/* Transform length of a plan (0 for NULL). */
+uint64_t pa_plan_transform_len(pa_plan_t plan);
+/* Frees the plan's device memory; the caller ensures no work using it is
+ * still in flight. */
+pa_status pa_plan_destroy(pa_plan_t plan);
+
+/* Smallest supported transform length for (n, m); 0 if unsupported or
+ * invalid.  Pure host function. */
+uint64_t pa_transform_len(uint64_t n, uint64_t m);
+
+/* Device bytes of library workspace one in-flight block of (n, m) needs on
+ * the plain path (two length-L residue arrays); 0 if invalid. */
+size_t pa_workspace_bytes(uint64_t n, uint64_t m);
+
+/* Static text for a status code. */
+const char *pa_status_string(pa_status s);
+
+/* Thread-local text of the last failure in the calling thread ("" if none). */
+const char *pa_last_error(void);
+
+/* Library / kernel build identification string. */
+const char *pa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PA_H_ */

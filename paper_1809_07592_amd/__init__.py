@@ -1,1 +1,187 @@
-"""MI355X-native Toeplitz-hash privacy amplification (binding filled in below)."""
+"""MI355X-native Toeplitz-hash privacy amplification.
+
+Thin ctypes binding over ``libpa.so`` (C ABI in ``include/pa.h``): it only
+marshals torch CUDA tensors (device memory) and HIP streams into the C
+calls; every step of the hash runs in the library's gfx950 kernels.  The
+library is built in-tree by ``python -m paper_1809_07592_amd.build``; if it is
+missing, every call raises ``RuntimeError`` (there is no fallback).
+
+Bit tensors are int64 (or uint64) CUDA tensors holding little-endian packed
+bits: bit k in word k >> 6 at position k & 63.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpa.so")
+
+PA_OK = 0
+PA_ERR_INVALID_ARG = 1
+PA_ERR_UNSUPPORTED_SIZE = 2
+PA_ERR_OUT_OF_MEMORY = 3
+PA_ERR_DEVICE = 4
+PA_ERR_BUSY = 5
+MAX_TRANSFORM_LEN = 28311552
+
+_lib = None
+_lock = threading.Lock()
+
+
+class PAError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (status_string(status) if _lib else status, message))
+        self.status = status
+
+
+class _Block(ctypes.Structure):
+    _fields_ = [("key_bits", ctypes.c_void_p), ("n", ctypes.c_uint64), ("seed_bits", ctypes.c_void_p),
+                ("m", ctypes.c_uint64), ("out_bits", ctypes.c_void_p)]
+
+
+def lib():
+    """The loaded libpa.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        with _lock:
+            if _lib is None:
+                if not os.path.exists(LIB_PATH):
+                    raise RuntimeError("libpa.so is not built (run: python -m paper_1809_07592_amd.build); "
+                                       "there is no CPU fallback")
+                L = ctypes.CDLL(LIB_PATH)
+                vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+                st = ctypes.c_int
+                L.pa_toeplitz_hash.argtypes = [vp, u64, vp, u64, vp, vp]
+                L.pa_toeplitz_hash.restype = st
+                L.pa_toeplitz_hash_batched.argtypes = [ctypes.POINTER(_Block), u32, vp]
+                L.pa_toeplitz_hash_batched.restype = st
+                L.pa_plan_create.argtypes = [vp, u64, u64, vp, ctypes.POINTER(vp)]
+                L.pa_plan_create.restype = st
+                L.pa_plan_hash.argtypes = [vp, vp, u64, u64, vp, vp]
+                L.pa_plan_hash.restype = st
+                L.pa_plan_transform_len.argtypes = [vp]
+                L.pa_plan_transform_len.restype = u64
+                L.pa_plan_destroy.argtypes = [vp]
+                L.pa_plan_destroy.restype = st
+                L.pa_transform_len.argtypes = [u64, u64]
+                L.pa_transform_len.restype = u64
+                L.pa_workspace_bytes.argtypes = [u64, u64]
+                L.pa_workspace_bytes.restype = ctypes.c_size_t
+                L.pa_status_string.argtypes = [st]
+                L.pa_status_string.restype = ctypes.c_char_p
+                L.pa_last_error.argtypes = []
+                L.pa_last_error.restype = ctypes.c_char_p
+                L.pa_version.argtypes = []
+                L.pa_version.restype = ctypes.c_char_p
+                _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().pa_status_string(int(status)).decode()
+
+
+def last_error() -> str:
+    return lib().pa_last_error().decode()
+
+
+def version() -> str:
+    return lib().pa_version().decode()
+
+
+def _check(status: int):
+    if status != PA_OK:
+        raise PAError(status, last_error())
+
+
+def words(bits: int) -> int:
+    return (int(bits) + 63) // 64
+
+
+def transform_len(n: int, m: int) -> int:
+    return int(lib().pa_transform_len(int(n), int(m)))
+
+
+def workspace_bytes(n: int, m: int) -> int:
+    return int(lib().pa_workspace_bytes(int(n), int(m)))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptr(t, nwords: int, what: str):
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a device (CUDA/HIP) tensor" % what)
+    if t.dtype not in (torch.int64, getattr(torch, "uint64", torch.int64)):
+        raise ValueError("%s must be int64/uint64 packed bits" % what)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if t.numel() < nwords:
+        raise ValueError("%s has %d words, needs %d" % (what, t.numel(), nwords))
+    return t.data_ptr()
+
+
+def toeplitz_hash(key, n: int, seed, m: int, out=None, stream=None):
+    """y = T x mod 2 (m x n Toeplitz matrix of the n+m-1 seed bits); returns out."""
+    import torch
+    if out is None:
+        out = torch.empty(max(words(m), 1), dtype=torch.int64, device=key.device)
+    _check(lib().pa_toeplitz_hash(_ptr(key, words(n), "key"), int(n), _ptr(seed, words(n + m - 1), "seed"),
+                                  int(m), _ptr(out, words(m), "out"), _stream_handle(stream)))
+    return out
+
+
+def toeplitz_hash_batched(blocks, stream=None):
+    """blocks: sequence of (key, n, seed, m, out) tuples; returns the outs."""
+    arr = (_Block * max(len(blocks), 1))()
+    for i, (key, n, seed, m, out) in enumerate(blocks):
+        arr[i] = _Block(_ptr(key, words(n), "key"), int(n), _ptr(seed, words(n + m - 1), "seed"), int(m),
+                        _ptr(out, words(m), "out"))
+    _check(lib().pa_toeplitz_hash_batched(arr, len(blocks), _stream_handle(stream)))
+    return [b[4] for b in blocks]
+
+
+class Plan:
+    """Seed spectrum resident on the device (pa_plan_*)."""
+
+    def __init__(self, seed, seed_len_bits: int, transform_len: int = 0, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().pa_plan_create(_ptr(seed, words(seed_len_bits), "seed"), int(seed_len_bits),
+                                    int(transform_len), _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self.seed_len_bits = int(seed_len_bits)
+
+    @property
+    def transform_len(self) -> int:
+        return int(lib().pa_plan_transform_len(self._h))
+
+    def hash(self, key, n: int, m: int, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(max(words(m), 1), dtype=torch.int64, device=key.device)
+        _check(lib().pa_plan_hash(self._h, _ptr(key, words(n), "key"), int(n), int(m),
+                                  _ptr(out, words(m), "out"), _stream_handle(stream)))
+        return out
+
+    def destroy(self):
+        if self._h:
+            _check(lib().pa_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+        return False

@@ -1,0 +1,99 @@
+// Internal definitions shared by the host plan code and the gfx950 kernels.
+//
+// Arithmetic: residues modulo the prime P = 27 * 2^20 + 1 (25 bits,
+// P - 1 = 2^20 * 3^3, primitive root 5).  Because P < 2^25, a residue times
+// a twiddle of magnitude <= P/2 is below 2^53 for residues up to ~22 P, so a
+// modular product is three exact FP64 FMAs (full rate on CDNA4) instead of
+// quarter-rate 32-bit integer multiplies:
+//   t1 = fma(a, w/P, 1.5*2^52)      -> 1.5*2^52 + round(a w / P)
+//   qp = fma(t1, P, -1.5*2^52 * P)  -> round(a w / P) * P   (exact)
+//   r  = fma(a, w, -qp)             -> a w - q P             (exact, |r| <= P/2 + 4)
+// Values are kept as exact integers in doubles in registers and as int32 in
+// LDS and HBM; nothing is reduced to [0, P) until the final parity.
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace pa {
+
+constexpr int64_t kP = 28311553;             // 27 * 2^20 + 1
+constexpr int64_t kGen = 5;                   // primitive root mod kP
+constexpr int kMaxPow2 = 20;                  // 2-adic valuation of kP - 1
+constexpr int kMaxPow3 = 3;                   // 3-adic valuation of kP - 1
+constexpr uint64_t kMaxLen = 28311552ull;     // 27 * 2^20
+constexpr uint64_t kMinLen = 4096;            // smallest length used (R = C = 64)
+
+constexpr double kPd = 28311553.0;
+constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
+constexpr double kNegMagicP = -(6755399441055744.0 * 28311553.0);  // exact: 3*2^51*(27*2^20+1)
+constexpr double kPinv = 1.0 / 28311553.0;
+
+constexpr uint64_t cpowmod(uint64_t b, uint64_t e) {
+    uint64_t r = 1;
+    b %= (uint64_t)kP;
+    while (e) {
+        if (e & 1) r = r * b % (uint64_t)kP;
+        b = b * b % (uint64_t)kP;
+        e >>= 1;
+    }
+    return r;
+}
+constexpr int64_t csym(uint64_t w) { return w > (uint64_t)kP / 2 ? (int64_t)w - kP : (int64_t)w; }
+
+// Primitive cube roots of unity used by the radix-3 butterflies (the same
+// root omega_N^(N/3) for every N, since omega_N = 5^((P-1)/N)).
+constexpr double kW3 = (double)csym(cpowmod(kGen, (kP - 1) / 3));
+constexpr double kW3p = kW3 / kPd;
+constexpr double kW3i = (double)csym(cpowmod(kGen, 2 * ((kP - 1) / 3)));
+constexpr double kW3ip = kW3i / kPd;
+
+// Round kinds: a round is a group of consecutive elementary stages applied
+// in registers to RHO = 3^n3 * 2^n2 elements.  All radix-3 stages of a
+// transform come first (so later strides are powers of two).
+constexpr int kNumKinds = 12;
+// (n3, n2) per kind
+constexpr int kKindN3[kNumKinds] = {0, 0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 3};
+constexpr int kKindN2[kNumKinds] = {1, 2, 3, 4, 5, 0, 1, 2, 3, 0, 1, 0};
+
+constexpr int kMaxRounds = 6;
+constexpr int kMaxStages = 24;
+
+struct RoundDesc {
+    int kind;        // index into kKind*
+    int s0;          // first elementary stage of the round
+    int jl_log2;     // log2 of J_last (stride of the round's last stage)
+    int M;           // block size at the round's first stage = RHO * J_last
+    int ngroups;     // N / RHO
+};
+
+// One 1-D transform of length N = 3^n3 * 2^n2 (radix-3 stages first).
+struct XDesc {
+    int N;
+    int nstages;
+    int nrounds;
+    int pad_;
+    RoundDesc round[kMaxRounds];
+    int fwd_off[kMaxStages];  // offset (in twiddle pairs) of stage s in the forward table
+    int inv_off[kMaxStages];  // offset of stage s in the inverse table
+    const double2 *fwd_tw;    // device: forward CT twiddles (w, w/P)
+    const double2 *inv_tw;    // device: inverse DIT twiddles (w, w/P)
+};
+
+// Four-step layout of one transform length L = R * C (R = 2^a rows,
+// C = 3^b * 2^c columns, row-major R x C view of the length-L sequence).
+struct LenPlan {
+    uint64_t L;
+    int R, C;
+    int log2R;
+    int W;                   // column-tile width of the column passes (power of two, <= 64)
+    XDesc col;               // length-R transform (column passes)
+    XDesc row;               // length-C transform (row pass)
+    const double2 *twist_lo; // omega_L^i, i < 4096
+    const double2 *twist_hi; // omega_L^(4096 i), i < ceil(L / 4096)
+    double Linv;             // L^{-1} mod P, symmetric representative
+    double Linv_p;           // Linv / P
+};
+
+}  // namespace pa

@@ -1,0 +1,29 @@
+// Host-side transform plans (see pa_plan.cpp).
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "pa_internal.h"
+
+namespace pa {
+
+uint64_t powmod_u(uint64_t b, uint64_t e);
+uint64_t root_of_unity(uint64_t N);
+
+// Lengths 2^k 3^j (7 <= k <= 20, j <= 3) between kMinLen and kMaxLen, ascending.
+const std::vector<uint64_t> &supported_lengths();
+
+// Convolution length a block (n, m) needs: n-1 rounded up to a multiple of
+// 64 (the key shift that word-aligns the output) plus m rounded up to 64.
+uint64_t required_len(uint64_t n, uint64_t m);
+
+// Smallest supported length >= req (0 if none).
+uint64_t choose_len(uint64_t req);
+
+// Cached per-device plan for length L; log2R_override > 0 forces the split.
+// Throws std::bad_alloc / std::runtime_error on failure.
+const LenPlan *get_len_plan(uint64_t L, int log2R_override = 0);
+
+}  // namespace pa

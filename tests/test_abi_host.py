@@ -1,0 +1,133 @@
+"""Host-only checks of the C ABI (no GPU needed).
+
+The library must load, export every function include/pa.h declares, and
+reject bad arguments synchronously before any HIP call.  Length selection
+is checked against an independent computation of the smallest 2^k 3^j.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1809_07592_amd as pa
+from paper_1809_07592_amd import build as pa_build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pa.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pa.LIB_PATH):
+        pa_build.build()
+    return pa.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pa_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "pa_toeplitz_hash" in names and "pa_toeplitz_hash_batched" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", pa.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (pa_[a-z_]+)\b", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(lib, n)
+
+
+FAKE = 0x10000  # non-null, never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("key,n,seed,m,out,status", [
+    (None, 10, FAKE, 5, FAKE, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 10, None, 5, FAKE, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 10, FAKE, 5, None, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 0, FAKE, 1, FAKE, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 10, FAKE, 0, FAKE, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 10, FAKE, 11, FAKE, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 30_000_000, FAKE, 1, FAKE, pa.PA_ERR_UNSUPPORTED_SIZE),
+    (FAKE, 20_000_000, FAKE, 9_000_000, FAKE, pa.PA_ERR_UNSUPPORTED_SIZE),
+])
+def test_rejects_before_device_work(lib, key, n, seed, m, out, status):
+    assert lib.pa_toeplitz_hash(key, n, seed, m, out, None) == status
+    assert len(pa.last_error()) > 0
+
+
+def test_batched_validation(lib):
+    blocks = (pa._Block * 2)()
+    blocks[0] = pa._Block(FAKE, 100, FAKE, 10, FAKE)
+    blocks[1] = pa._Block(FAKE, 100, FAKE, 101, FAKE)
+    assert lib.pa_toeplitz_hash_batched(blocks, 2, None) == pa.PA_ERR_INVALID_ARG
+    assert "block 1" in pa.last_error()
+    assert lib.pa_toeplitz_hash_batched(blocks, 0, None) == pa.PA_OK
+    assert lib.pa_toeplitz_hash_batched(None, 3, None) == pa.PA_ERR_INVALID_ARG
+
+
+def test_plan_validation(lib):
+    h = ctypes.c_void_p()
+    assert lib.pa_plan_create(None, 100, 0, None, ctypes.byref(h)) == pa.PA_ERR_INVALID_ARG
+    assert lib.pa_plan_create(FAKE, 0, 0, None, ctypes.byref(h)) == pa.PA_ERR_INVALID_ARG
+    assert lib.pa_plan_create(FAKE, 100, 5000, None, ctypes.byref(h)) == pa.PA_ERR_INVALID_ARG
+    assert lib.pa_plan_create(FAKE, 40_000_000, 0, None, ctypes.byref(h)) == pa.PA_ERR_UNSUPPORTED_SIZE
+    assert lib.pa_plan_hash(None, FAKE, 10, 5, FAKE, None) == pa.PA_ERR_INVALID_ARG
+    assert lib.pa_plan_destroy(None) == pa.PA_OK
+    assert lib.pa_plan_transform_len(None) == 0
+
+
+def smallest_len(req):
+    best = None
+    for k in range(7, 21):
+        for j in range(4):
+            L = 2**k * 3**j
+            if 4096 <= L <= 27 * 2**20 and L >= req and (best is None or L < best):
+                best = L
+    return best or 0
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (64, 64), (65, 1), (262_144, 65_536), (1_000_000, 250_000),
+                                 (12_800_000, 1_280_000), (4096, 4096), (24_000_000, 4_300_000)])
+def test_transform_length_choice(lib, n, m):
+    req = 64 * ((n - 1 + 63) // 64 + (m + 63) // 64)
+    assert pa.transform_len(n, m) == smallest_len(req)
+    assert pa.workspace_bytes(n, m) == 8 * smallest_len(req)
+
+
+def test_paper_config_lengths(lib):
+    # mixed-radix lengths cut the padding of the power-of-two choice
+    assert pa.transform_len(1_000_000, 250_000) == 3 * 2**19
+    assert pa.transform_len(12_800_000, 1_280_000) == 27 * 2**19
+    assert pa.transform_len(262_144, 65_536) == 3 * 2**17
+
+
+def test_status_strings(lib):
+    for code, name in [(0, "PA_OK"), (1, "PA_ERR_INVALID_ARG"), (2, "PA_ERR_UNSUPPORTED_SIZE"),
+                       (3, "PA_ERR_OUT_OF_MEMORY"), (4, "PA_ERR_DEVICE"), (5, "PA_ERR_BUSY")]:
+        assert pa.status_string(code) == name
+    assert "gfx950" in pa.version()
+
+
+def test_modulus_facts():
+    # P = 27*2^20 + 1 is prime with primitive root 5; P > every supported length
+    from sympy import isprime, n_order
+    P = 27 * 2**20 + 1
+    assert isprime(P) and n_order(5, P) == P - 1
+    assert P > pa.MAX_TRANSFORM_LEN
+    # 3-FMA product exactness needs |a w| < 2^53 for |a| <= 22 P, |w| <= P/2
+    assert 22 * P * (P // 2) < 2**53
+
+
+def test_product_never_touches_oracle():
+    pkg = os.path.join(ROOT, "paper_1809_07592_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "toeplitz_oracle" not in text and "liboracle" not in text, f

@@ -1,0 +1,186 @@
+"""Bit-exact parity of the gfx950 path against the CPU oracle (needs a GPU).
+
+Every case calls the C ABI (through the ctypes binding) on seeded synthetic
+Bernoulli(0.5) blocks and compares the packed output with the oracle word
+for word.  Full-size blocks beyond what the oracle finishes in seconds are
+checked on sampled output bits (computed one by one by the oracle) plus
+properties that hold at any size (linearity in the key, zero tail).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1809_07592_amd as pa
+from paper_1809_07592_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def host(t) -> np.ndarray:
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+def gpu_hash(key, n, seed, m):
+    out = pa.toeplitz_hash(dev(key), n, dev(seed), m)
+    return host(out)[: wl.words(m)]
+
+
+def check_full(n, m, cfg=10, idx=0, garbage=False):
+    key, seed = wl.key_and_seed(cfg, n, m, idx, garbage_tail=garbage)
+    got = gpu_hash(key, n, seed, m)
+    want = oracle.toeplitz_hash(key, n, seed, m)
+    assert np.array_equal(got, want), "n=%d m=%d: %d words differ" % (n, m, int(np.sum(got != want)))
+    return key, seed, got
+
+
+def require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _gpu():
+    require_gpu()
+    oracle.build()
+    yield
+
+
+EDGE = [(1, 1), (2, 1), (2, 2), (63, 1), (64, 64), (65, 65), (65, 1), (127, 64), (128, 128), (129, 1),
+        (1000, 1), (1000, 999), (1000, 1000), (4095, 1), (4096, 1), (4097, 2048), (4033, 64), (4034, 64),
+        (3000, 1000), (5000, 2500), (4609, 4608)]
+
+
+@pytest.mark.parametrize("n,m", EDGE)
+def test_edge_shapes(n, m):
+    check_full(n, m, cfg=11, idx=n * 7 + m)
+
+
+@pytest.mark.parametrize("n,m", [(262_144, 65_536), (100_003, 31_337), (65_536, 65_536), (300_000, 27_001)])
+def test_multi_tile_ragged(n, m):
+    check_full(n, m, cfg=12)
+
+
+def test_garbage_padding_is_ignored():
+    n, m = 100_001, 20_003
+    k1, s1, y1 = check_full(n, m, cfg=13, garbage=False)
+    _, _, y2 = check_full(n, m, cfg=13, garbage=True)
+    assert np.array_equal(y1, y2)
+
+
+def test_length_boundaries():
+    # shapes whose required length sits exactly on / just past supported lengths
+    for L in [4096, 4608, 6144, 8192, 3 * 2**17, 2**18]:
+        m = 64
+        n_exact = L - 64 + 1          # required_len = (n-1 rounded to 64) + 64 = L
+        assert pa.transform_len(n_exact, m) == L and pa.transform_len(n_exact + 1, m) > L
+        for n in (n_exact, n_exact + 1):
+            check_full(n, m, cfg=14, idx=n)
+
+
+def test_paper_finite_size_block():
+    # n = 10^6, m = 250,000 (Sec. 2.1: blocks of at least 10^6 bits), full oracle
+    check_full(1_000_000, 250_000, cfg=2)
+
+
+def sampled_indices(m, count, gen):
+    fixed = [0, 1, 63, 64, 65, m // 2, m - 65, m - 64, m - 63, m - 2, m - 1]
+    rnd = gen.integers(0, m, size=count)
+    return np.unique(np.clip(np.array(fixed + list(rnd), dtype=np.int64), 0, m - 1))
+
+
+def test_large_block_sampled_and_linear():
+    n, m = 12_800_000, 1_280_000
+    key, seed = wl.key_and_seed(3, n, m, 0)
+    key2 = wl.random_bits(n, wl.rng(3, wl.ROLE_KEY, 1))
+    y = gpu_hash(key, n, seed, m)
+    y2 = gpu_hash(key2, n, seed, m)
+    y12 = gpu_hash(key ^ key2, n, seed, m)
+    assert np.array_equal(y12, y ^ y2), "linearity in the key"
+    if m % 64:
+        assert int(y[-1]) >> (m % 64) == 0
+    idx = sampled_indices(m, 400, np.random.default_rng(5))
+    want = oracle.toeplitz_bits(key, n, seed, m, idx)
+    got = ((y[idx >> 6] >> (idx & 63).astype(np.uint64)) & np.uint64(1)).astype(np.uint8)
+    assert np.array_equal(got, want)
+
+
+def test_largest_supported_block_sampled():
+    n, m = 24_000_000, 4_300_000
+    assert pa.transform_len(n, m) == 27 * 2**20
+    key, seed = wl.key_and_seed(15, n, m, 0)
+    y = gpu_hash(key, n, seed, m)
+    idx = sampled_indices(m, 150, np.random.default_rng(6))
+    want = oracle.toeplitz_bits(key, n, seed, m, idx)
+    got = ((y[idx >> 6] >> (idx & 63).astype(np.uint64)) & np.uint64(1)).astype(np.uint8)
+    assert np.array_equal(got, want)
+
+
+def test_all_ones_extremes():
+    # c[k] reaches n (largest convolution value) with all-ones key and seed
+    n, m = 200_000, 50_000
+    key = np.full(wl.words(n), np.uint64(2**64 - 1), dtype=np.uint64)
+    seed = np.full(wl.words(n + m - 1), np.uint64(2**64 - 1), dtype=np.uint64)
+    got = gpu_hash(key, n, seed, m)
+    want = oracle.toeplitz_hash(key, n, seed, m)
+    assert np.array_equal(got, want)
+
+
+def test_plan_matches_plain_and_is_length_invariant():
+    S = 400_000
+    seed = wl.random_bits(S, wl.rng(16, wl.ROLE_SEED, 0))
+    dseed = dev(seed)
+    shapes = [(300_000, 99_999), (200_000, 50_000), (1000, 1000), (399_000, 1001)]
+    with pa.Plan(dseed, S) as plan, pa.Plan(dseed, S, transform_len=2**20) as big:
+        assert big.transform_len == 2**20 and plan.transform_len < 2**20
+        for i, (n, m) in enumerate(shapes):
+            key = wl.random_bits(n, wl.rng(16, wl.ROLE_KEY, i))
+            want = oracle.toeplitz_hash(key, n, seed, m)
+            a = host(plan.hash(dev(key), n, m))[: wl.words(m)]
+            b = host(big.hash(dev(key), n, m))[: wl.words(m)]
+            assert np.array_equal(a, want) and np.array_equal(b, want), (n, m)
+        with pytest.raises(pa.PAError):
+            plan.hash(dev(wl.random_bits(S, wl.rng(16, 1, 9))), S, 2)
+
+
+def test_batched_matches_oracle():
+    shapes = [(262_144, 13_000), (100_000, 50_000), (4096, 1), (777_777, 200_001), (65, 65), (300_001, 30_001)]
+    blocks, refs = [], []
+    shared_seed = None
+    for i, (n, m) in enumerate(shapes):
+        key, seed = wl.key_and_seed(17, n, m, i)
+        if i == 5:  # reuse an earlier seed buffer (shared seeds are allowed)
+            seed = shared_seed
+        if i == 3:
+            shared_seed = seed
+        blocks.append((dev(key), n, dev(seed), m, torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")))
+        refs.append(oracle.toeplitz_hash(key, n, seed, m))
+    outs = pa.toeplitz_hash_batched(blocks)
+    for o, r in zip(outs, refs):
+        assert np.array_equal(host(o)[: r.size], r)
+
+
+def test_deterministic_repeats():
+    n, m = 300_000, 70_000
+    key, seed = wl.key_and_seed(18, n, m, 0)
+    dk, ds = dev(key), dev(seed)
+    first = host(pa.toeplitz_hash(dk, n, ds, m))
+    for _ in range(20):
+        assert np.array_equal(host(pa.toeplitz_hash(dk, n, ds, m)), first)
+
+
+def test_stream_ordering_on_side_stream():
+    n, m = 500_000, 100_000
+    key, seed = wl.key_and_seed(19, n, m, 0)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        dk, ds = dev(key), dev(seed)
+        out = pa.toeplitz_hash(dk, n, ds, m, stream=s)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint64)[: wl.words(m)], oracle.toeplitz_hash(key, n, seed, m))

@@ -111,6 +111,34 @@ pa_status pa_plan_destroy(pa_plan_t plan);
  * invalid.  Pure host function. */
 uint64_t pa_transform_len(uint64_t n, uint64_t m);
 
+/*
+ * Launch geometry of the four-step transform of length transform_len
+ * (introspection and tuning; pure host function, no device work).  The
+ * length-L cyclic convolution is laid out as an R x C row-major matrix: the
+ * column passes run length-R transforms on W-column tiles, the row pass
+ * length-C transforms (cf. the 2-D long transform of Sec. 3.1, Alg. 1, with
+ * the transposes removed as in Sec. 3.3, Alg. 2).  log2_rows = 0 and
+ * tile_width = 0 select the defaults.  PA_ERR_UNSUPPORTED_SIZE if the
+ * length is not supported, PA_ERR_INVALID_ARG for an impossible split.
+ */
+typedef struct pa_plan_info {
+    uint64_t transform_len;
+    uint32_t rows;             /* R */
+    uint32_t cols;             /* C */
+    uint32_t tile_width;       /* W */
+    uint32_t col_tiles;        /* C / W: workgroups of a column pass */
+    uint32_t col_threads;      /* workgroup size of the column passes */
+    uint32_t row_threads;      /* workgroup size of the row pass */
+    uint32_t col_lds_bytes;    /* LDS of one column tile */
+    uint32_t row_lds_bytes;    /* LDS of the row pass on the plain path (two rows when they fit) */
+    uint32_t col_rounds;       /* register rounds of the length-R transform */
+    uint32_t row_rounds;       /* register rounds of the length-C transform */
+    uint32_t col_round_size[6];
+    uint32_t row_round_size[6];
+} pa_plan_info;
+
+pa_status pa_plan_describe(uint64_t transform_len, uint32_t log2_rows, uint32_t tile_width, pa_plan_info *info);
+
 /* Device bytes of library workspace one in-flight block of (n, m) needs on
  * the plain path (two length-L residue arrays); 0 if invalid. */
 size_t pa_workspace_bytes(uint64_t n, uint64_t m);

@@ -36,6 +36,20 @@ class PAError(RuntimeError):
         self.status = status
 
 
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("transform_len", ctypes.c_uint64), ("rows", ctypes.c_uint32), ("cols", ctypes.c_uint32),
+                ("tile_width", ctypes.c_uint32), ("col_tiles", ctypes.c_uint32), ("col_threads", ctypes.c_uint32),
+                ("row_threads", ctypes.c_uint32), ("col_lds_bytes", ctypes.c_uint32),
+                ("row_lds_bytes", ctypes.c_uint32), ("col_rounds", ctypes.c_uint32), ("row_rounds", ctypes.c_uint32),
+                ("col_round_size", ctypes.c_uint32 * 6), ("row_round_size", ctypes.c_uint32 * 6)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["col_round_size"] = list(self.col_round_size)[: self.col_rounds]
+        d["row_round_size"] = list(self.row_round_size)[: self.row_rounds]
+        return d
+
+
 class _Block(ctypes.Structure):
     _fields_ = [("key_bits", ctypes.c_void_p), ("n", ctypes.c_uint64), ("seed_bits", ctypes.c_void_p),
                 ("m", ctypes.c_uint64), ("out_bits", ctypes.c_void_p)]
@@ -67,6 +81,8 @@ def lib():
                 L.pa_plan_destroy.restype = st
                 L.pa_transform_len.argtypes = [u64, u64]
                 L.pa_transform_len.restype = u64
+                L.pa_plan_describe.argtypes = [u64, u32, u32, ctypes.POINTER(PlanInfo)]
+                L.pa_plan_describe.restype = st
                 L.pa_workspace_bytes.argtypes = [u64, u64]
                 L.pa_workspace_bytes.restype = ctypes.c_size_t
                 L.pa_status_string.argtypes = [st]
@@ -102,6 +118,23 @@ def words(bits: int) -> int:
 
 def transform_len(n: int, m: int) -> int:
     return int(lib().pa_transform_len(int(n), int(m)))
+
+
+def plan_info(transform_len: int, log2_rows: int = 0, tile_width: int = 0) -> dict:
+    """Launch geometry of a transform length (no device work)."""
+    info = PlanInfo()
+    _check(lib().pa_plan_describe(int(transform_len), int(log2_rows), int(tile_width), ctypes.byref(info)))
+    return info.as_dict()
+
+
+def supported_lengths():
+    out = []
+    for k in range(7, 21):
+        for j in range(4):
+            L = 2**k * 3**j
+            if 4096 <= L <= MAX_TRANSFORM_LEN:
+                out.append(L)
+    return sorted(out)
 
 
 def workspace_bytes(n: int, m: int) -> int:

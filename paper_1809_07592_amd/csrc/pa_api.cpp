@@ -88,7 +88,7 @@ pa_status get_workspace(hipStream_t s, size_t bytes, void **out) {
     return PA_OK;
 }
 
-pa_status plan_for(uint64_t L, const pa::LenPlan **lp) {
+pa_status plan_for(uint64_t L, pa::PlanRef *lp) {
     try {
         *lp = pa::get_len_plan(L);
     } catch (const std::bad_alloc &) {
@@ -102,32 +102,54 @@ pa_status plan_for(uint64_t L, const pa::LenPlan **lp) {
 inline uint64_t out_offset(uint64_t n) { return 64 * ((n - 1 + 63) / 64); }
 
 // Key path against a ready spectrum: P1 (key), P2 (convolve), P3 (extract).
-pa_status run_key_path(const pa::LenPlan &lp, const uint64_t *key, uint64_t n, uint64_t m, const int32_t *Shat,
+pa_status run_key_path(const pa::PlanRef &p, const uint64_t *key, uint64_t n, uint64_t m, const int32_t *Shat,
                        int32_t *A, uint64_t *out, hipStream_t s) {
     const uint64_t off0 = out_offset(n);
-    PA_HIP(pa::launch_colfwd_bits(lp, key, n, (int)(off0 - (n - 1)), A, s), "launch P1");
-    PA_HIP(pa::launch_rowconv(lp, A, Shat, 0, s), "launch P2");
-    PA_HIP(pa::launch_colinv_bits(lp, A, out, off0, m, s), "launch P3");
+    const uint64_t *bits[2] = {key, nullptr};
+    const uint64_t nb[2] = {n, 0};
+    const int64_t sh[2] = {(int64_t)(off0 - (n - 1)), 0};
+    int32_t *dst[2] = {A, nullptr};
+    PA_HIP(pa::launch_colfwd(*p.host, p.dev, 1, bits, nb, sh, dst, s), "launch P1");
+    PA_HIP(pa::launch_rowconv(*p.host, p.dev, A, Shat, nullptr, 0, s), "launch P2");
+    PA_HIP(pa::launch_colinv(*p.host, p.dev, A, out, off0, m, s), "launch P3");
     return PA_OK;
 }
 
 // Seed spectrum of the first nbits seed bits into S (length L residues).
-pa_status run_seed_path(const pa::LenPlan &lp, const uint64_t *seed, uint64_t nbits, int32_t *S, hipStream_t s) {
-    PA_HIP(pa::launch_colfwd_bits(lp, seed, nbits, 0, S, s), "launch P1 (seed)");
-    PA_HIP(pa::launch_rowconv(lp, S, nullptr, 1, s), "launch P2 (seed)");
+pa_status run_seed_path(const pa::PlanRef &p, const uint64_t *seed, uint64_t nbits, int32_t *S, hipStream_t s) {
+    const uint64_t *bits[2] = {seed, nullptr};
+    const uint64_t nb[2] = {nbits, 0};
+    const int64_t sh[2] = {0, 0};
+    int32_t *dst[2] = {S, nullptr};
+    PA_HIP(pa::launch_colfwd(*p.host, p.dev, 1, bits, nb, sh, dst, s), "launch P1 (seed)");
+    PA_HIP(pa::launch_rowconv(*p.host, p.dev, S, nullptr, nullptr, 1, s), "launch P2 (seed)");
     return PA_OK;
 }
 
+// Plain path: key and seed column transforms in one launch, both row
+// transforms and the product in one launch, then the extraction.
 pa_status hash_one(const uint64_t *key, uint64_t n, const uint64_t *seed, uint64_t m, uint64_t *out, uint64_t L,
                    hipStream_t s) {
-    const pa::LenPlan *lp = nullptr;
-    PA_TRY(plan_for(L, &lp));
+    pa::PlanRef p{};
+    PA_TRY(plan_for(L, &p));
     void *ws = nullptr;
     PA_TRY(get_workspace(s, (size_t)(8 * L), &ws));
     int32_t *A = (int32_t *)ws;
     int32_t *S = A + L;
-    PA_TRY(run_seed_path(*lp, seed, n + m - 1, S, s));
-    return run_key_path(*lp, key, n, m, S, A, out, s);
+    if (!p.host->fused_ok) {
+        // rows too long for two in LDS: seed spectrum through HBM first
+        PA_TRY(run_seed_path(p, seed, n + m - 1, S, s));
+        return run_key_path(p, key, n, m, S, A, out, s);
+    }
+    const uint64_t off0 = out_offset(n);
+    const uint64_t *bits[2] = {key, seed};
+    const uint64_t nb[2] = {n, n + m - 1};
+    const int64_t sh[2] = {(int64_t)(off0 - (n - 1)), 0};
+    int32_t *dst[2] = {A, S};
+    PA_HIP(pa::launch_colfwd(*p.host, p.dev, 2, bits, nb, sh, dst, s), "launch P1");
+    PA_HIP(pa::launch_rowconv(*p.host, p.dev, A, nullptr, S, 2, s), "launch P2");
+    PA_HIP(pa::launch_colinv(*p.host, p.dev, A, out, off0, m, s), "launch P3");
+    return PA_OK;
 }
 
 }  // namespace
@@ -137,7 +159,7 @@ struct pa_plan_s {
     uint64_t L = 0;
     uint64_t seed_len = 0;
     int32_t *Shat = nullptr;
-    const pa::LenPlan *lp = nullptr;
+    pa::PlanRef lp{};
 };
 
 extern "C" {
@@ -161,6 +183,37 @@ const char *pa_version(void) { return "pa-mi355x 0.1 (gfx950; NTT mod 27*2^20+1,
 uint64_t pa_transform_len(uint64_t n, uint64_t m) {
     if (n == 0 || m == 0 || m > n || n > pa::kMaxLen) return 0;
     return pa::choose_len(pa::required_len(n, m));
+}
+
+pa_status pa_plan_describe(uint64_t transform_len, uint32_t log2_rows, uint32_t tile_width, pa_plan_info *info) {
+    if (!info) return fail(PA_ERR_INVALID_ARG, "null info pointer");
+    const auto &lens = pa::supported_lengths();
+    if (std::find(lens.begin(), lens.end(), transform_len) == lens.end())
+        return fail(PA_ERR_UNSUPPORTED_SIZE, "transform length " + std::to_string(transform_len) + " not supported");
+    pa::LenPlan lp;
+    try {
+        pa::plan_geometry(transform_len, (int)log2_rows, (int)tile_width, lp);
+    } catch (const std::exception &e) {
+        return fail(PA_ERR_INVALID_ARG, e.what());
+    }
+    pa_plan_info r{};
+    r.transform_len = lp.L;
+    r.rows = (uint32_t)lp.R;
+    r.cols = (uint32_t)lp.C;
+    r.tile_width = (uint32_t)lp.W;
+    r.col_tiles = (uint32_t)lp.ntiles;
+    r.col_threads = (uint32_t)lp.col_threads;
+    r.row_threads = (uint32_t)lp.row_threads;
+    r.col_lds_bytes = (uint32_t)lp.col_lds * 4;
+    r.row_lds_bytes = (uint32_t)lp.row_lds * 4 * (lp.fused_ok ? 2 : 1);
+    r.col_rounds = (uint32_t)lp.col.nrounds;
+    r.row_rounds = (uint32_t)lp.row.nrounds;
+    for (int i = 0; i < lp.col.nrounds; ++i)
+        r.col_round_size[i] = (uint32_t)(lp.col.round[i].M >> lp.col.round[i].jl_log2);
+    for (int i = 0; i < lp.row.nrounds; ++i)
+        r.row_round_size[i] = (uint32_t)(lp.row.round[i].M >> lp.row.round[i].jl_log2);
+    *info = r;
+    return PA_OK;
 }
 
 size_t pa_workspace_bytes(uint64_t n, uint64_t m) {
@@ -206,7 +259,7 @@ pa_status pa_plan_create(const uint64_t *seed_bits, uint64_t seed_len_bits, uint
         if (std::find(lens.begin(), lens.end(), L) == lens.end())
             return fail(PA_ERR_INVALID_ARG, "transform_len " + std::to_string(L) + " is not a supported length");
     }
-    const pa::LenPlan *lp = nullptr;
+    pa::PlanRef lp{};
     PA_TRY(plan_for(L, &lp));
     pa_plan_s *p = new (std::nothrow) pa_plan_s();
     if (!p) return fail(PA_ERR_OUT_OF_MEMORY, "host allocation");
@@ -219,7 +272,7 @@ pa_status pa_plan_create(const uint64_t *seed_bits, uint64_t seed_len_bits, uint
     p->L = L;
     p->seed_len = seed_len_bits;
     p->lp = lp;
-    pa_status st = run_seed_path(*lp, seed_bits, std::min(seed_len_bits, L), p->Shat, (hipStream_t)stream);
+    pa_status st = run_seed_path(lp, seed_bits, std::min(seed_len_bits, L), p->Shat, (hipStream_t)stream);
     if (st != PA_OK) {
         (void)hipFree(p->Shat);
         delete p;
@@ -241,7 +294,7 @@ pa_status pa_plan_hash(pa_plan_t plan, const uint64_t *key_bits, uint64_t n, uin
     if (pa::required_len(n, m) > plan->L) return fail(PA_ERR_INVALID_ARG, "block needs a longer transform than the plan");
     void *ws = nullptr;
     PA_TRY(get_workspace((hipStream_t)stream, (size_t)(4 * plan->L), &ws));
-    return run_key_path(*plan->lp, key_bits, n, m, plan->Shat, (int32_t *)ws, out_bits, (hipStream_t)stream);
+    return run_key_path(plan->lp, key_bits, n, m, plan->Shat, (int32_t *)ws, out_bits, (hipStream_t)stream);
 }
 
 pa_status pa_plan_destroy(pa_plan_t plan) {

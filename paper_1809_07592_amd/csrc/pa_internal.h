@@ -51,11 +51,14 @@ constexpr double kW3ip = kW3i / kPd;
 
 // Round kinds: a round is a group of consecutive elementary stages applied
 // in registers to RHO = 3^n3 * 2^n2 elements.  All radix-3 stages of a
-// transform come first (so later strides are powers of two).
-constexpr int kNumKinds = 12;
-// (n3, n2) per kind
-constexpr int kKindN3[kNumKinds] = {0, 0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 3};
-constexpr int kKindN2[kNumKinds] = {1, 2, 3, 4, 5, 0, 1, 2, 3, 0, 1, 0};
+// transform sit in its first round (so later strides are powers of two);
+// every later round is pure radix-2 with at most 16 elements (larger
+// register groups make the compiler keep a whole round's twiddles live).
+constexpr int kNumKinds = 11;
+// (n3, n2) per kind; kinds 0..3 are the pure radix-2 ones
+constexpr int kKindN3[kNumKinds] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3, 1};
+constexpr int kKindN2[kNumKinds] = {1, 2, 3, 4, 0, 1, 2, 0, 1, 0, 3};
+constexpr int kNumPow2Kinds = 4;
 
 constexpr int kMaxRounds = 6;
 constexpr int kMaxStages = 24;
@@ -73,7 +76,7 @@ struct XDesc {
     int N;
     int nstages;
     int nrounds;
-    int pad_;
+    int lgpad;       // LDS index of position q is q + (q >> lgpad) (per column)
     RoundDesc round[kMaxRounds];
     int fwd_off[kMaxStages];  // offset (in twiddle pairs) of stage s in the forward table
     int inv_off[kMaxStages];  // offset of stage s in the inverse table
@@ -83,17 +86,25 @@ struct XDesc {
 
 // Four-step layout of one transform length L = R * C (R = 2^a rows,
 // C = 3^b * 2^c columns, row-major R x C view of the length-L sequence).
+// Lives in device memory; kernels read it through a pointer.
 struct LenPlan {
     uint64_t L;
     int R, C;
     int log2R;
-    int W;                   // column-tile width of the column passes (power of two, <= 64)
+    int W;                   // column-tile width of the column passes (power of two, 16..64)
+    int ntiles;              // C / W
+    int col_threads;         // workgroup size of the column passes
+    int row_threads;         // workgroup size of the row pass
+    int col_lds;             // LDS ints of one column tile (padded)
+    int row_lds;             // LDS ints of one row (padded)
+    int fused_ok;            // two rows fit in LDS: the plain path runs seed and key in one row pass
+    int rho0;                // size of the row transform's first round
     XDesc col;               // length-R transform (column passes)
     XDesc row;               // length-C transform (row pass)
     const double2 *twist_lo; // omega_L^i, i < 4096
     const double2 *twist_hi; // omega_L^(4096 i), i < ceil(L / 4096)
-    double Linv;             // L^{-1} mod P, symmetric representative
-    double Linv_p;           // Linv / P
+    const double2 *alpha_f;  // [k1][u] = omega_L^(k1 * (C/rho0) * u)
+    const double2 *alpha_i;  // [k1][u] = omega_L^(-k1 * (C/rho0) * u) / L
 };
 
 }  // namespace pa

@@ -9,18 +9,21 @@
 
 namespace pa {
 
-// P1: column-forward NTT of the bit string (bit q of the transform input is
-// bit q - shift of `bits` when inside [0, nbits)).  out: L int32 residues.
-hipError_t launch_colfwd_bits(const LenPlan &lp, const uint64_t *bits, uint64_t nbits, int shift, int32_t *out,
-                              hipStream_t s);
+// P1: column-forward NTT of nsrc (1 or 2) bit strings in one launch.  For
+// source i, transform input position p holds bit p - shift[i] of bits[i]
+// when inside [0, nbits[i]); out[i] receives L int32 residues.
+hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const uint64_t *const bits[2],
+                         const uint64_t nbits[2], const int64_t shift[2], int32_t *const out[2], hipStream_t s);
 
-// P2: mode 0 = twist, row NTT, product with Shat, inverse row NTT, inverse
-// twist (in place on A); mode 1 = seed spectrum (A <- twist, row NTT, 1/L).
-hipError_t launch_rowconv(const LenPlan &lp, int32_t *A, const int32_t *Shat, int mode, hipStream_t s);
+// P2: mode 0 = A <- conv(A, Shat) with the spectrum Shat in HBM; mode 1 =
+// A <- spectrum of A (for plans); mode 2 = A <- conv(A, spectrum of S)
+// (plain path, S = column-transformed seed).  In place on A.
+hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int32_t *A, const int32_t *Shat, const int32_t *S,
+                          int mode, hipStream_t s);
 
 // P3: inverse column NTT, parity of convolution positions [off0, off0+m),
 // packed into out (ceil(m/64) words, tail zero).
-hipError_t launch_colinv_bits(const LenPlan &lp, const int32_t *A, uint64_t *out, uint64_t off0, uint64_t m,
-                              hipStream_t s);
+hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const int32_t *A, uint64_t *out, uint64_t off0,
+                         uint64_t m, hipStream_t s);
 
 }  // namespace pa

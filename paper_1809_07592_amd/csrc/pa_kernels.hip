@@ -52,10 +52,43 @@ __device__ __forceinline__ double reduce_sym(double a) {
     return a - qp;
 }
 
-// ------------------------------------------------------------ round shapes
+// Raw buffer access: base and size in an SGPR resource, 32-bit byte offset
+// per lane (one VGPR instead of a 64-bit address), hardware range check
+// (out-of-range loads return 0, stores are dropped).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ int ld32(rsrc_t r, int byte_off) {
+    return (int)__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0);
+}
+__device__ __forceinline__ void st32(rsrc_t r, int byte_off, int v) {
+    __builtin_amdgcn_raw_buffer_store_b32((unsigned)v, r, byte_off, 0, 0);
+}
+__device__ __forceinline__ void st16(rsrc_t r, int byte_off, unsigned v) {
+    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, byte_off, 0, 0);
+}
+__device__ __forceinline__ void st64(rsrc_t r, int byte_off, uint64_t v) {
+    __builtin_amdgcn_raw_buffer_store_b32((unsigned)v, r, byte_off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32((unsigned)(v >> 32), r, byte_off + 4, 0, 0);
+}
 
-template <int N3, int N2>
-struct Shape;
+// omega_L^e for 0 <= e < L from the two-level table, with its quotient.
+__device__ __forceinline__ double2 twist_factor(const LenPlan &lp, uint32_t e) {
+    const double2 lo = lp.twist_lo[e & 4095u];
+    const double2 hi = lp.twist_hi[e >> 12];
+    const double w = mulmod(hi.x, lo.x, lo.y);
+    return make_double2(w, w * kPinv);
+}
+__device__ __forceinline__ double2 ld_tw(rsrc_t r, int index) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, index * 16, 0, 0);
+    double2 d;
+    __builtin_memcpy(&d, &v, sizeof(d));
+    return d;
+}
+
+// ------------------------------------------------------------ round shapes
 
 template <int N3, int N2>
 struct Shape {
@@ -84,15 +117,14 @@ using RegArr = double[(N3 == 0 ? 1 : N3 == 1 ? 3 : N3 == 2 ? 9 : 27) << N2];
 // Forward Cooley-Tukey stage K of a round: block index b_full = b*before+sb,
 // input u multiplied by gamma^u (table entry), then r-point DFT.
 template <int N3, int N2, int K>
-__device__ __forceinline__ void fwd_stage(RegArr<N3, N2> &v, int b,
-                                          const double2 *__restrict__ tw, int off) {
+__device__ __forceinline__ void fwd_stage(RegArr<N3, N2> &v, int b, rsrc_t tw, int off) {
     using S = Shape<N3, N2>;
     constexpr int r = S::radix(K), rb = S::before(K), ra = S::after(K);
 #pragma unroll
     for (int sb = 0; sb < rb; ++sb) {
-        const double2 *t = tw + off + (b * rb + sb) * (r - 1);
+        const int t = off + (b * rb + sb) * (r - 1);
         if constexpr (r == 2) {
-            const double2 w = t[0];
+            const double2 w = ld_tw(tw, t);
 #pragma unroll
             for (int x = 0; x < ra; ++x) {
                 const int i0 = sb * 2 * ra + x, i1 = i0 + ra;
@@ -102,7 +134,7 @@ __device__ __forceinline__ void fwd_stage(RegArr<N3, N2> &v, int b,
                 v[i1] = a - mm;
             }
         } else {
-            const double2 w1 = t[0], w2 = t[1];
+            const double2 w1 = ld_tw(tw, t), w2 = ld_tw(tw, t + 1);
 #pragma unroll
             for (int x = 0; x < ra; ++x) {
                 const int i0 = sb * 3 * ra + x, i1 = i0 + ra, i2 = i1 + ra;
@@ -121,15 +153,14 @@ __device__ __forceinline__ void fwd_stage(RegArr<N3, N2> &v, int b,
 // Inverse (decimation in time) stage K of a round: input i of the r-point
 // inverse DFT multiplied by omega_M^(-j' i), j' = x*J_last + jj.
 template <int N3, int N2, int K>
-__device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast,
-                                          const double2 *__restrict__ tw, int off) {
+__device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, rsrc_t tw, int off) {
     using S = Shape<N3, N2>;
     constexpr int r = S::radix(K), rb = S::before(K), ra = S::after(K);
 #pragma unroll
     for (int x = 0; x < ra; ++x) {
-        const double2 *t = tw + off + (x * jlast + jj) * (r - 1);
+        const int t = off + (x * jlast + jj) * (r - 1);
         if constexpr (r == 2) {
-            const double2 w = t[0];
+            const double2 w = ld_tw(tw, t);
 #pragma unroll
             for (int sb = 0; sb < rb; ++sb) {
                 const int i0 = sb * 2 * ra + x, i1 = i0 + ra;
@@ -139,7 +170,7 @@ __device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast,
                 v[i1] = a - mm;
             }
         } else {
-            const double2 w1 = t[0], w2 = t[1];
+            const double2 w1 = ld_tw(tw, t), w2 = ld_tw(tw, t + 1);
 #pragma unroll
             for (int sb = 0; sb < rb; ++sb) {
                 const int i0 = sb * 3 * ra + x, i1 = i0 + ra, i2 = i1 + ra;
@@ -158,7 +189,10 @@ __device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast,
 template <int N3, int N2, int K>
 __device__ __forceinline__ void fwd_stages(RegArr<N3, N2> &v, int b, const XDesc &xd, int s0) {
     if constexpr (K < Shape<N3, N2>::Q) {
-        fwd_stage<N3, N2, K>(v, b, xd.fwd_tw, xd.fwd_off[s0 + K]);
+        fwd_stage<N3, N2, K>(v, b, make_rsrc(xd.fwd_tw, 0x7fffffff), xd.fwd_off[s0 + K]);
+        // keep the next stage's twiddle loads from being hoisted above this
+        // stage (otherwise all of a round's twiddles are live at once)
+        __builtin_amdgcn_sched_barrier(0);
         fwd_stages<N3, N2, K + 1>(v, b, xd, s0);
     }
 }
@@ -167,191 +201,338 @@ template <int N3, int N2, int K>
 __device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast, const XDesc &xd,
                                            int s0) {
     if constexpr (K >= 0) {
-        inv_stage<N3, N2, K>(v, jj, jlast, xd.inv_tw, xd.inv_off[s0 + K]);
+        inv_stage<N3, N2, K>(v, jj, jlast, make_rsrc(xd.inv_tw, 0x7fffffff), xd.inv_off[s0 + K]);
+        __builtin_amdgcn_sched_barrier(0);
         inv_stages<N3, N2, K - 1>(v, jj, jlast, xd, s0);
     }
 }
 
-// One round over an LDS tile: transform positions run down the tile with
-// element (pos, column c) at lds[pos * W + c]; W = 1 << wsh columns.
-template <bool FWD, int N3, int N2>
-__device__ void run_round(int *lds, int wsh, const RoundDesc &rd, const XDesc &xd) {
-    using S = Shape<N3, N2>;
-    constexpr int RHO = S::RHO;
+// ------------------------------------------------------------ round driver
+//
+// A round visits work items (group g of tile column c).  Each item builds a
+// context with pre(c, b, jj), loads its RHO elements with load(ctx, G, l),
+// runs the round's stages and hands the group to store(ctx, v, G).
+// Element l of the group is transform position G.q0 + (l << G.jl) of tile
+// column G.c; in the padded LDS tile it is at G.lbase + l * G.lstep (the
+// padding q + (q >> lgpad) is affine in l: the stride of every round but
+// the last is a multiple of 2^lgpad, and the last round's block is exactly
+// 2^lgpad long).  MODE_CONV runs the forward stages, mid(ctx, v, G) (the
+// pointwise product) and the inverse stages of the same group in registers.
+// FIRST (the transform's first round: one block, b = 0) and LAST (unit
+// stride, jj = 0) are compile-time so that the twiddles of the first
+// forward round and of the first inverse round are wave-uniform.
+
+enum { MODE_FWD = 0, MODE_INV = 1, MODE_CONV = 2 };
+
+struct Geo {
+    int q0, jl, c, lbase, lstep;
+};
+
+// Opaque copy: stops the compiler from keeping every element address of a
+// group live from the loads to the stores (it recomputes them instead).
+__device__ __forceinline__ Geo launder(Geo g) {
+    asm volatile("" : "+v"(g.q0), "+v"(g.lbase));
+    return g;
+}
+
+template <int MODE, int N3, int N2, bool FIRST, bool LAST, class Pre, class Load, class Mid, class Store>
+__device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, int wsh, Pre &pre, Load &load,
+                                         Mid &mid, Store &store) {
+    constexpr int RHO = Shape<N3, N2>::RHO;
     const int W = 1 << wsh;
     const int items = rd.ngroups << wsh;
-    const int jl = rd.jl_log2;
-    const int T = blockDim.x;
-    for (int item = threadIdx.x; item < items; item += T) {
+    const int jl = LAST ? 0 : rd.jl_log2;
+    const int lgp = xd.lgpad;
+    const int J = 1 << jl;
+    const int lstep = LAST ? W : ((J + (J >> lgp)) << wsh);
+    for (int item = threadIdx.x; item < items; item += blockDim.x) {
         const int c = item & (W - 1);
         const int g = item >> wsh;
-        const int b = g >> jl;
-        const int jj = g & ((1 << jl) - 1);
-        const int base = b * rd.M + jj;
-        double v[RHO];
+        const int b = FIRST ? 0 : (g >> jl);
+        const int jj = LAST ? 0 : (g & (J - 1));
+        const int q0 = FIRST ? jj : (b * rd.M + jj);
+        Geo G{q0, jl, c, ((q0 + (q0 >> lgp)) << wsh) + c, lstep};
+        auto ctx = pre(c, b, jj);
+        RegArr<N3, N2> v;
 #pragma unroll
-        for (int l = 0; l < RHO; ++l) v[l] = (double)lds[((base + (l << jl)) << wsh) + c];
-        if constexpr (FWD)
-            fwd_stages<N3, N2, 0>(v, b, xd, rd.s0);
-        else
-            inv_stages<N3, N2, S::Q - 1>(v, jj, 1 << jl, xd, rd.s0);
-#pragma unroll
-        for (int l = 0; l < RHO; ++l) lds[((base + (l << jl)) << wsh) + c] = (int)v[l];
+        for (int l = 0; l < RHO; ++l) v[l] = load(ctx, G, l);
+        if constexpr (MODE == MODE_FWD || MODE == MODE_CONV) fwd_stages<N3, N2, 0>(v, b, xd, rd.s0);
+        if constexpr (MODE == MODE_CONV) mid(ctx, v, launder(G));
+        if constexpr (MODE == MODE_INV || MODE == MODE_CONV)
+            inv_stages<N3, N2, Shape<N3, N2>::Q - 1>(v, jj, J, xd, rd.s0);
+        store(ctx, v, launder(G));
     }
 }
 
-template <bool FWD>
-__device__ void round_dispatch(int *lds, int wsh, const RoundDesc &rd, const XDesc &xd) {
+// Round r of a transform whose rounds are pure radix-2 (kinds 0..3).
+template <int MODE, bool FIRST, bool LAST, class Pre, class Load, class Mid, class Store>
+__device__ __forceinline__ void round_p2(const XDesc &xd, int r, int wsh, Pre &pre, Load &load, Mid &mid,
+                                         Store &store) {
+    const RoundDesc &rd = xd.round[r];
     switch (rd.kind) {
-        case 0: run_round<FWD, 0, 1>(lds, wsh, rd, xd); break;
-        case 1: run_round<FWD, 0, 2>(lds, wsh, rd, xd); break;
-        case 2: run_round<FWD, 0, 3>(lds, wsh, rd, xd); break;
-        case 3: run_round<FWD, 0, 4>(lds, wsh, rd, xd); break;
-        case 4: run_round<FWD, 0, 5>(lds, wsh, rd, xd); break;
-        case 5: run_round<FWD, 1, 0>(lds, wsh, rd, xd); break;
-        case 6: run_round<FWD, 1, 1>(lds, wsh, rd, xd); break;
-        case 7: run_round<FWD, 1, 2>(lds, wsh, rd, xd); break;
-        case 8: run_round<FWD, 1, 3>(lds, wsh, rd, xd); break;
-        case 9: run_round<FWD, 2, 0>(lds, wsh, rd, xd); break;
-        case 10: run_round<FWD, 2, 1>(lds, wsh, rd, xd); break;
-        case 11: run_round<FWD, 3, 0>(lds, wsh, rd, xd); break;
+        case 0: round_io<MODE, 0, 1, FIRST, LAST>(rd, xd, wsh, pre, load, mid, store); break;
+        case 1: round_io<MODE, 0, 2, FIRST, LAST>(rd, xd, wsh, pre, load, mid, store); break;
+        case 2: round_io<MODE, 0, 3, FIRST, LAST>(rd, xd, wsh, pre, load, mid, store); break;
+        case 3: round_io<MODE, 0, 4, FIRST, LAST>(rd, xd, wsh, pre, load, mid, store); break;
         default: break;
     }
 }
 
-__device__ void fwd_transform(int *lds, int wsh, const XDesc &xd) {
-    for (int r = 0; r < xd.nrounds; ++r) {
-        round_dispatch<true>(lds, wsh, xd.round[r], xd);
-        __syncthreads();
-    }
+// Round 0 of a transform whose first round has the compile-time kind FK.
+template <int MODE, int FK, bool LAST, class Pre, class Load, class Mid, class Store>
+__device__ __forceinline__ void round_fk(const XDesc &xd, int wsh, Pre &pre, Load &load, Mid &mid, Store &store) {
+    round_io<MODE, kKindN3[FK], kKindN2[FK], true, LAST>(xd.round[0], xd, wsh, pre, load, mid, store);
 }
 
-__device__ void inv_transform(int *lds, int wsh, const XDesc &xd) {
-    for (int r = xd.nrounds - 1; r >= 0; --r) {
-        round_dispatch<false>(lds, wsh, xd.round[r], xd);
-        __syncthreads();
-    }
+template <class V>
+__device__ __forceinline__ constexpr int group_size(const V &v) {
+    return (int)(sizeof(v) / sizeof(v[0]));
 }
 
-// omega_L^e for 0 <= e < L from the two-level table.
-__device__ __forceinline__ double2 twist_factor(const LenPlan &lp, uint32_t e) {
-    const double2 lo = lp.twist_lo[e & 4095u];
-    const double2 hi = lp.twist_hi[e >> 12];
-    const double w = mulmod(hi.x, lo.x, lo.y);
-    return make_double2(w, w * kPinv);
-}
+struct NoCtx {};
+
 
 // ------------------------------------------------------------------ kernels
 
 extern __shared__ int pa_lds[];
 
-// P1: bit q of the (shifted) input is bit q - shift of `bits` if it lies in
-// [0, nbits), else 0.  Tile t covers columns [t*W, t*W + W).
-__global__ void __launch_bounds__(256) k_colfwd_bits(const uint64_t *__restrict__ bits, uint64_t nbits,
-                                                     int shift, int32_t *__restrict__ out, LenPlan lp) {
-    int *lds = pa_lds;
-    const int W = lp.W, wsh = __builtin_ctz((unsigned)W);
-    const uint64_t C = (uint64_t)lp.C;
-    const uint64_t c0 = (uint64_t)blockIdx.x * (uint64_t)W;
-    const int total = lp.R << wsh;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const uint64_t r = (uint64_t)(e >> wsh);
-        const uint64_t q = r * C + c0 + (uint64_t)(e & (W - 1));
-        int bit = 0;
-        if (q >= (uint64_t)shift) {
-            const uint64_t src = q - (uint64_t)shift;
-            if (src < nbits) bit = (int)((bits[src >> 6] >> (src & 63)) & 1u);
-        }
-        lds[e] = bit;
-    }
-    __syncthreads();
-    fwd_transform(lds, wsh, lp.col);
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const uint64_t r = (uint64_t)(e >> wsh);
-        out[r * C + c0 + (uint64_t)(e & (W - 1))] = lds[e];
-    }
-}
+// P1: forward column NTT of one W-column tile of a bit string.  Transform
+// input position p = q*C + c0 + c holds bit p - shift of `bits` when that
+// index lies in [0, nbits), else 0.  blockIdx.y selects one of two sources
+// (key and seed of the plain path run in one launch).
+struct P1Arg {
+    const uint64_t *bits[2];
+    uint64_t nbits[2];
+    int64_t shift[2];
+    int32_t *out[2];
+};
 
-// P2.  mode 0: full row convolution in place on A, using the spectrum Shat.
-//      mode 1: seed spectrum: A <- (1/L) * forward(row), reduced.
-__global__ void __launch_bounds__(256) k_rowconv(int32_t *__restrict__ A, const int32_t *__restrict__ Shat,
-                                                 LenPlan lp, int mode) {
+#define PA_INLINE __attribute__((always_inline))
+
+__global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan, P1Arg a) {
+    const LenPlan &lp = *plan;
+    const XDesc &xd = lp.col;
+    const int src = blockIdx.y;
+    const int nbits = (int)a.nbits[src];
+    const int shift = (int)a.shift[src];
+    const rsrc_t bits = make_rsrc(a.bits[src], (uint32_t)((a.nbits[src] + 31) / 32 * 4));
+    const rsrc_t out = make_rsrc(a.out[src], (uint32_t)(lp.L * 4));
+    const int W = lp.W, wsh = __builtin_ctz((unsigned)W), C = lp.C;
+    const int c0 = blockIdx.x * W;
     int *lds = pa_lds;
-    const int C = lp.C;
-    const uint32_t row = blockIdx.x;
-    const uint32_t k1 = __builtin_bitreverse32(row) >> (32 - lp.log2R);
-    int32_t *arow = A + (size_t)row * (size_t)C;
-    for (int j = threadIdx.x; j < C; j += blockDim.x) {
-        const double2 tw = twist_factor(lp, (uint32_t)j * k1);
-        lds[j] = (int)mulmod((double)arow[j], tw.x, tw.y);
-    }
-    __syncthreads();
-    fwd_transform(lds, 0, lp.row);
-    if (mode == 1) {
-        for (int j = threadIdx.x; j < C; j += blockDim.x)
-            arow[j] = (int)mulmod((double)lds[j], lp.Linv, lp.Linv_p);
+    auto pre = [&](int, int, int) PA_INLINE { return NoCtx{}; };
+    auto mid = [&](NoCtx, auto &, Geo) PA_INLINE {};
+    auto load_bits = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double {
+        const int p = (g.q0 + (l << g.jl)) * C + c0 + g.c - shift;
+        if (p < 0 || p >= nbits) return 0.0;
+        return (double)(((unsigned)ld32(bits, (p >> 5) * 4) >> (p & 31)) & 1u);
+    };
+    auto load_lds = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double {
+        return (double)lds[g.lbase + l * g.lstep];
+    };
+    auto store_lds = [&](NoCtx, auto &v, Geo g) PA_INLINE {
+#pragma unroll
+        for (int l = 0; l < group_size(v); ++l) lds[g.lbase + l * g.lstep] = (int)v[l];
+    };
+    auto store_glb = [&](NoCtx, auto &v, Geo g) PA_INLINE {
+#pragma unroll
+        for (int l = 0; l < group_size(v); ++l) st32(out, ((g.q0 + (l << g.jl)) * C + c0 + g.c) * 4, (int)v[l]);
+    };
+    const int nr = xd.nrounds;
+    if (nr == 1) {
+        round_p2<MODE_FWD, true, true>(xd, 0, wsh, pre, load_bits, mid, store_glb);
         return;
     }
-    const int32_t *srow = Shat + (size_t)row * (size_t)C;
-    for (int j = threadIdx.x; j < C; j += blockDim.x) {
-        const double s = (double)srow[j];
-        lds[j] = (int)mulmod((double)lds[j], s, s * kPinv);
-    }
+    round_p2<MODE_FWD, true, false>(xd, 0, wsh, pre, load_bits, mid, store_lds);
     __syncthreads();
-    inv_transform(lds, 0, lp.row);
-    const uint32_t L = (uint32_t)lp.L;
-    for (int j = threadIdx.x; j < C; j += blockDim.x) {
-        const uint32_t e = (uint32_t)j * k1;
-        const double2 tw = twist_factor(lp, e == 0 ? 0u : L - e);
-        arow[j] = (int)mulmod((double)lds[j], tw.x, tw.y);
+    for (int r = 1; r < nr - 1; ++r) {
+        round_p2<MODE_FWD, false, false>(xd, r, wsh, pre, load_lds, mid, store_lds);
+        __syncthreads();
     }
+    round_p2<MODE_FWD, false, true>(xd, nr - 1, wsh, pre, load_lds, mid, store_glb);
 }
 
-// P3: output bit i is convolution position off0 + i, off0 = n-1 rounded up
-// to a multiple of 64 (the key was shifted by off0 - (n-1)).  Chunks of W
-// output bits are written whole for i < 64*ceil(m/64); bits >= m are zero.
-__global__ void __launch_bounds__(256) k_colinv_bits(const int32_t *__restrict__ A, uint64_t *__restrict__ out,
-                                                     uint64_t off0, uint64_t m, LenPlan lp) {
-    int *lds = pa_lds;
-    const int W = lp.W, wsh = __builtin_ctz((unsigned)W);
-    const uint64_t C = (uint64_t)lp.C;
-    const uint64_t c0 = (uint64_t)blockIdx.x * (uint64_t)W;
-    const int total = lp.R << wsh;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const uint64_t r = (uint64_t)(e >> wsh);
-        lds[e] = A[r * C + c0 + (uint64_t)(e & (W - 1))];
-    }
-    __syncthreads();
-    inv_transform(lds, wsh, lp.col);
-    const uint64_t olim = 64 * ((m + 63) / 64);
-    const int lane = threadIdx.x & 63;
-    // total is a multiple of 64 and blockDim a multiple of 64: whole waves
-    // run the same iterations, so the ballot sees every lane.
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const int c = e & (W - 1);
-        const uint64_t q = (uint64_t)(e >> wsh) * C + c0 + (uint64_t)c;
-        const int64_t pos = (int64_t)q - (int64_t)off0;
-        const double cv = canonical((double)lds[e]);
-        const int bit = (int)((int64_t)cv & 1);
-        const bool set = bit && pos >= 0 && pos < (int64_t)m;
-        const uint64_t mask = __ballot(set);
-        if (c == 0 && pos >= 0 && (uint64_t)pos < olim) {
-            const uint64_t chunk = W == 64 ? mask : (mask >> (lane & ~(W - 1))) & ((1ull << W) - 1);
-            if (W == 64)
-                out[pos >> 6] = chunk;
-            else if (W == 32)
-                reinterpret_cast<uint32_t *>(out)[pos >> 5] = (uint32_t)chunk;
-            else
-                reinterpret_cast<uint16_t *>(out)[pos >> 4] = (uint16_t)chunk;
+// P2: one row (index blockIdx.x, column-spectrum index k1 = bitrev(row)).
+// Spectra are stored reduced (|s| <= P/2 + 4) so that a product of an
+// unreduced transform value (<= ~8 P) with them stays exact.
+//   mode 0: A <- twist^-1 . INTT_C( NTT_C(twist . A) * Shat )      (plan path)
+//   mode 1: A <- NTT_C(twist . A)                                   (seed spectrum)
+//   mode 2: as mode 0 with Shat = NTT_C(twist . S) computed here    (plain path)
+// The inverse twist carries the 1/L of the inverse transform.  Round 0's
+// group is q = jj + l*J0 (J0 = C/rho0), twisted by beta(jj) * alpha(l).
+struct P2Arg {
+    int32_t *A;
+    const int32_t *Shat;
+    const int32_t *S;
+    int mode;
+};
+
+struct TwCtx {
+    double2 beta;
+};
+
+template <int FK>
+__global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ plan, P2Arg a) {
+    const LenPlan &lp = *plan;
+    const XDesc &xd = lp.row;
+    const int C = lp.C, nr = xd.nrounds;
+    const uint32_t row = blockIdx.x;
+    const uint32_t k1 = __builtin_bitreverse32(row) >> (32 - lp.log2R);
+    const uint32_t L = (uint32_t)lp.L;
+    const size_t rbase = (size_t)row * (size_t)C;
+    const rsrc_t rowA = make_rsrc(a.A + rbase, (uint32_t)C * 4);
+    const rsrc_t rowS = make_rsrc(a.S ? a.S + rbase : a.A, (uint32_t)C * 4);
+    const rsrc_t rowH = make_rsrc(a.Shat ? a.Shat + rbase : a.A, (uint32_t)C * 4);
+    int *lds_a = pa_lds;
+    int *lds_s = pa_lds + lp.row_lds;
+    const double2 *__restrict__ af = lp.alpha_f + (size_t)k1 * lp.rho0;
+    const double2 *__restrict__ ai = lp.alpha_i + (size_t)k1 * lp.rho0;
+
+    auto pre_none = [&](int, int, int) PA_INLINE { return NoCtx{}; };
+    auto pre_fwd = [&](int, int, int jj) PA_INLINE { return TwCtx{twist_factor(lp, k1 * (uint32_t)jj)}; };
+    auto pre_inv = [&](int, int, int jj) PA_INLINE {
+        const uint32_t e = k1 * (uint32_t)jj;
+        return TwCtx{twist_factor(lp, e == 0 ? 0u : L - e)};
+    };
+    auto mid_none = [&](auto, auto &, Geo) PA_INLINE {};
+
+    // forward transform of one row: round 0 from HBM with the twist, rounds
+    // 1 .. last-1 in LDS; the last round is left to the caller.
+    auto forward_head = [&](rsrc_t src, int *lds) PA_INLINE {
+        auto load_tw = [&](TwCtx t, const Geo &g, int l) PA_INLINE -> double {
+            const double x = (double)ld32(src, (g.q0 + (l << g.jl)) * 4);
+            const double y = mulmod(x, t.beta.x, t.beta.y);
+            const double2 al = af[l];
+            return mulmod(y, al.x, al.y);
+        };
+        auto store_l = [&](auto, auto &v, Geo g) PA_INLINE {
+#pragma unroll
+            for (int l = 0; l < group_size(v); ++l) lds[g.lbase + l * g.lstep] = (int)v[l];
+        };
+        auto load_l = [&](auto, const Geo &g, int l) PA_INLINE -> double { return (double)lds[g.lbase + l * g.lstep]; };
+        round_fk<MODE_FWD, FK, false>(xd, 0, pre_fwd, load_tw, mid_none, store_l);
+        __syncthreads();
+        for (int r = 1; r < nr - 1; ++r) {
+            round_p2<MODE_FWD, false, false>(xd, r, 0, pre_none, load_l, mid_none, store_l);
+            __syncthreads();
         }
+    };
+    auto load_la = [&](auto, const Geo &g, int l) PA_INLINE -> double { return (double)lds_a[g.lbase + l * g.lstep]; };
+    auto store_la = [&](auto, auto &v, Geo g) PA_INLINE {
+#pragma unroll
+        for (int l = 0; l < group_size(v); ++l) lds_a[g.lbase + l * g.lstep] = (int)v[l];
+    };
+
+    if (a.mode == 1) {
+        forward_head(rowA, lds_a);
+        auto store_g = [&](NoCtx, auto &v, Geo g) PA_INLINE {
+#pragma unroll
+            for (int l = 0; l < group_size(v); ++l) st32(rowA, (g.q0 + (l << g.jl)) * 4, (int)reduce_sym(v[l]));
+        };
+        round_p2<MODE_FWD, false, true>(xd, nr - 1, 0, pre_none, load_la, mid_none, store_g);
+        return;
     }
+    if (a.mode == 2) {
+        forward_head(rowS, lds_s);
+        auto load_ls = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double { return (double)lds_s[g.lbase + l * g.lstep]; };
+        auto store_ls = [&](NoCtx, auto &v, Geo g) PA_INLINE {
+#pragma unroll
+            for (int l = 0; l < group_size(v); ++l) lds_s[g.lbase + l * g.lstep] = (int)reduce_sym(v[l]);
+        };
+        round_p2<MODE_FWD, false, true>(xd, nr - 1, 0, pre_none, load_ls, mid_none, store_ls);
+        // the key's last forward round reads the seed spectrum from LDS; the
+        // barrier at the end of the key's round 0 orders the two.
+    }
+    forward_head(rowA, lds_a);
+    const bool from_lds = a.mode == 2;
+    auto mid_mul = [&](NoCtx, auto &v, Geo g) PA_INLINE {
+#pragma unroll
+        for (int l = 0; l < group_size(v); ++l) {
+            const double s = (double)(from_lds ? lds_s[g.lbase + l * g.lstep] : ld32(rowH, (g.q0 + (l << g.jl)) * 4));
+            v[l] = mulmod(v[l], s, s * kPinv);
+        }
+    };
+    round_p2<MODE_CONV, false, true>(xd, nr - 1, 0, pre_none, load_la, mid_mul, store_la);
+    __syncthreads();
+    for (int r = nr - 2; r >= 1; --r) {
+        round_p2<MODE_INV, false, false>(xd, r, 0, pre_none, load_la, mid_none, store_la);
+        __syncthreads();
+    }
+    auto store_tw = [&](TwCtx t, auto &v, Geo g) PA_INLINE {
+#pragma unroll
+        for (int l = 0; l < group_size(v); ++l) {
+            const double2 al = ai[l];
+            const double y = mulmod(v[l], al.x, al.y);
+            st32(rowA, (g.q0 + (l << g.jl)) * 4, (int)mulmod(y, t.beta.x, t.beta.y));
+        }
+    };
+    round_fk<MODE_INV, FK, false>(xd, 0, pre_inv, load_la, mid_none, store_tw);
+}
+
+// P3: inverse column NTT of one tile, then the output window.  Output bit i
+// is convolution position off0 + i (off0 = n-1 rounded up to a multiple of
+// 64, matching the key shift of P1).  Chunks of W bits are written whole
+// for i < 64*ceil(m/64); bits >= m are zero.
+__global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan, const int32_t *__restrict__ A,
+                                                uint64_t *__restrict__ out, uint64_t off0, uint64_t m) {
+    const LenPlan &lp = *plan;
+    const XDesc &xd = lp.col;
+    const int W = lp.W, wsh = __builtin_ctz((unsigned)W), C = lp.C, nr = xd.nrounds;
+    const int c0 = blockIdx.x * W;
+    int *lds = pa_lds;
+    const rsrc_t ain = make_rsrc(A, (uint32_t)(lp.L * 4));
+    const rsrc_t obuf = make_rsrc(out, (uint32_t)((m + 63) / 64 * 8));
+    auto pre = [&](int, int, int) PA_INLINE { return NoCtx{}; };
+    auto mid = [&](NoCtx, auto &, Geo) PA_INLINE {};
+    auto load_glb = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double {
+        return (double)ld32(ain, ((g.q0 + (l << g.jl)) * C + c0 + g.c) * 4);
+    };
+    auto load_lds = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double { return (double)lds[g.lbase + l * g.lstep]; };
+    auto store_lds = [&](NoCtx, auto &v, Geo g) PA_INLINE {
+#pragma unroll
+        for (int l = 0; l < group_size(v); ++l) lds[g.lbase + l * g.lstep] = (int)v[l];
+    };
+    const int olim = (int)(64 * ((m + 63) / 64));
+    const int mm = (int)m, off = (int)off0;
+    const int lane = threadIdx.x & 63;
+    // Every wave runs whole iterations of the item loop (items and blockDim
+    // are multiples of 64), so each ballot sees all 64 lanes.
+    auto store_bits = [&](NoCtx, auto &v, Geo g) PA_INLINE {
+        uint32_t par = 0;  // parity of the exact convolution values of this group
+#pragma unroll
+        for (int l = 0; l < group_size(v); ++l) par |= ((uint32_t)(int)canonical(v[l]) & 1u) << l;
+#pragma unroll
+        for (int l = 0; l < group_size(v); ++l) {
+            const int pos = (g.q0 + (l << g.jl)) * C + c0 + g.c - off;
+            const uint64_t mask = __ballot(((par >> l) & 1u) && pos >= 0 && pos < mm);
+            if (g.c == 0 && pos >= 0 && pos < olim) {
+                if (W == 64)
+                    st64(obuf, (pos >> 6) * 8, mask);
+                else if (W == 32)
+                    st32(obuf, (pos >> 5) * 4, (int)(uint32_t)(mask >> (lane & 32)));
+                else
+                    st16(obuf, (pos >> 4) * 2, (unsigned)(mask >> (lane & 48)) & 0xFFFFu);
+            }
+        }
+    };
+    if (nr == 1) {
+        round_p2<MODE_INV, true, true>(xd, 0, wsh, pre, load_glb, mid, store_bits);
+        return;
+    }
+    round_p2<MODE_INV, false, true>(xd, nr - 1, wsh, pre, load_glb, mid, store_lds);
+    __syncthreads();
+    for (int r = nr - 2; r >= 1; --r) {
+        round_p2<MODE_INV, false, false>(xd, r, wsh, pre, load_lds, mid, store_lds);
+        __syncthreads();
+    }
+    round_p2<MODE_INV, true, false>(xd, 0, wsh, pre, load_lds, mid, store_bits);
 }
 
 // ----------------------------------------------------------------- launchers
 
 static int g_lds_limit[64];
 
-// Opt the three kernels into the device's full per-workgroup LDS (160 KiB on
+// Opt the kernels into the device's full per-workgroup LDS (160 KiB on
 // gfx950) once per device; returns the limit in *limit.
 static hipError_t set_lds_limits(int *limit) {
     int dev = 0;
@@ -366,50 +547,68 @@ static hipError_t set_lds_limits(int *limit) {
             if (e != hipSuccess) return e;
         }
         const int maxb = optin < 160 * 1024 ? optin : 160 * 1024;
-        e = hipFuncSetAttribute((const void *)k_rowconv, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void *)k_colfwd_bits, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void *)k_colinv_bits, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
-        if (e != hipSuccess) return e;
+        const void *fns[] = {(const void *)k_rowconv<0>, (const void *)k_rowconv<1>, (const void *)k_rowconv<2>,
+                             (const void *)k_rowconv<3>, (const void *)k_rowconv<4>, (const void *)k_rowconv<5>,
+                             (const void *)k_rowconv<6>, (const void *)k_rowconv<7>, (const void *)k_rowconv<8>,
+                             (const void *)k_rowconv<9>, (const void *)k_rowconv<10>, (const void *)k_colfwd,
+                             (const void *)k_colinv};
+        for (const void *f : fns) {
+            e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
+            if (e != hipSuccess) return e;
+        }
         g_lds_limit[dev] = maxb;
     }
     *limit = g_lds_limit[dev];
     return hipSuccess;
 }
 
-static const int kThreads = 256;
-
-hipError_t launch_colfwd_bits(const LenPlan &lp, const uint64_t *bits, uint64_t nbits, int shift, int32_t *out,
-                              hipStream_t s) {
+hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const uint64_t *const bits[2],
+                         const uint64_t nbits[2], const int64_t shift[2], int32_t *const out[2], hipStream_t s) {
     int limit = 0;
     hipError_t e = set_lds_limits(&limit);
     if (e != hipSuccess) return e;
-    const size_t lds = (size_t)lp.R * (size_t)lp.W * sizeof(int);
-    if (lds > (size_t)limit) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_colfwd_bits, dim3((unsigned)(lp.C / lp.W)), dim3(kThreads), lds, s, bits, nbits, shift,
-                       out, lp);
+    const size_t lds = (size_t)hp.col_lds * sizeof(int);
+    if (lds > (size_t)limit || nsrc < 1 || nsrc > 2) return hipErrorInvalidConfiguration;
+    P1Arg a{};
+    for (int i = 0; i < nsrc; ++i) {
+        a.bits[i] = bits[i];
+        a.nbits[i] = nbits[i];
+        a.shift[i] = shift[i];
+        a.out[i] = out[i];
+    }
+    hipLaunchKernelGGL(k_colfwd, dim3((unsigned)hp.ntiles, (unsigned)nsrc), dim3((unsigned)hp.col_threads), lds, s,
+                       dp, a);
     return hipGetLastError();
 }
 
-hipError_t launch_rowconv(const LenPlan &lp, int32_t *A, const int32_t *Shat, int mode, hipStream_t s) {
+hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int32_t *A, const int32_t *Shat, const int32_t *S,
+                          int mode, hipStream_t s) {
     int limit = 0;
     hipError_t e = set_lds_limits(&limit);
     if (e != hipSuccess) return e;
-    const size_t lds = (size_t)lp.C * sizeof(int);
+    const size_t lds = (size_t)hp.row_lds * sizeof(int) * (mode == 2 ? 2 : 1);
     if (lds > (size_t)limit) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_rowconv, dim3((unsigned)lp.R), dim3(kThreads), lds, s, A, Shat, lp, mode);
+    P2Arg a{A, Shat, S, mode};
+    const dim3 grid((unsigned)hp.R), block((unsigned)hp.row_threads);
+    switch (hp.row.round[0].kind) {
+#define PA_FK(K) \
+    case K: hipLaunchKernelGGL(k_rowconv<K>, grid, block, lds, s, dp, a); break;
+        PA_FK(0) PA_FK(1) PA_FK(2) PA_FK(3) PA_FK(4) PA_FK(5) PA_FK(6) PA_FK(7) PA_FK(8) PA_FK(9) PA_FK(10)
+#undef PA_FK
+        default: return hipErrorInvalidConfiguration;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_colinv_bits(const LenPlan &lp, const int32_t *A, uint64_t *out, uint64_t off0, uint64_t m,
-                              hipStream_t s) {
+hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const int32_t *A, uint64_t *out, uint64_t off0,
+                         uint64_t m, hipStream_t s) {
     int limit = 0;
     hipError_t e = set_lds_limits(&limit);
     if (e != hipSuccess) return e;
-    const size_t lds = (size_t)lp.R * (size_t)lp.W * sizeof(int);
+    const size_t lds = (size_t)hp.col_lds * sizeof(int);
     if (lds > (size_t)limit) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_colinv_bits, dim3((unsigned)(lp.C / lp.W)), dim3(kThreads), lds, s, A, out, off0, m, lp);
+    hipLaunchKernelGGL(k_colinv, dim3((unsigned)hp.ntiles), dim3((unsigned)hp.col_threads), lds, s, dp, A, out,
+                       off0, m);
     return hipGetLastError();
 }
 

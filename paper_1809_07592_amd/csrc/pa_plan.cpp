@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -94,35 +95,32 @@ static int kind_of(int n3, int n2) {
     throw std::runtime_error("no round kind for this shape");
 }
 
-// Split n3 radix-3 and n2 radix-2 stages into rounds: all radix-3 stages in
-// the first round, every round holding at most 32 elements.
-static std::vector<std::pair<int, int>> split_rounds(int n3, int n2, int max2 = 5) {
-    static const int cap1[4] = {5, 3, 1, 0};
-    int c1 = std::min(cap1[n3], max2);
-    std::vector<std::pair<int, int>> rounds;
-    if (n2 <= c1) {
-        rounds.push_back({n3, n2});
-        return rounds;
-    }
-    int nr = 1 + (n2 - c1 + max2 - 1) / max2;
-    if (n3 == 0) {
-        // balance nr rounds of 2-stages
-        for (int r = 0; r < nr; ++r) {
-            int take = (n2 - (int)0) / nr + (r < n2 % nr ? 1 : 0);
-            rounds.push_back({0, take});
+// Split n3 radix-3 and n2 radix-2 stages into register rounds: all radix-3
+// stages in the first round (with at most 2, 1, 0 radix-2 stages for n3 =
+// 1, 2, 3), later rounds pure radix-2 with at most 4 stages; the fewest
+// rounds, and among those the split whose smallest round is largest (fewest
+// idle threads when a work item is one group).
+static std::vector<std::pair<int, int>> split_rounds(int n3, int n2) {
+    static const int cap1[4] = {4, 3, 1, 0};
+    const int c1 = cap1[n3];
+    if (n2 <= c1 && (n3 > 0 || n2 > 0)) return {{n3, n2}};
+    const int nr = 1 + (n2 - c1 + 3) / 4;
+    std::vector<std::pair<int, int>> best;
+    double best_min = -1;
+    for (int first = (n3 == 0 ? 1 : 0); first <= c1; ++first) {
+        const int rem = n2 - first, rest = nr - 1;
+        if (rem < rest || rem > 4 * rest) continue;
+        std::vector<std::pair<int, int>> cand{{n3, first}};
+        for (int r = 0; r < rest; ++r) cand.push_back({0, rem / rest + (r < rem % rest ? 1 : 0)});
+        double mn = 1e30;
+        for (auto &c : cand) mn = std::min(mn, std::pow(3.0, c.first) * std::pow(2.0, c.second));
+        if (mn > best_min) {
+            best_min = mn;
+            best = cand;
         }
-        return rounds;
     }
-    int rest_rounds = nr - 1;
-    int first = std::max(n2 - max2 * rest_rounds, 0);
-    first = std::min(first, c1);
-    rounds.push_back({n3, first});
-    int rem = n2 - first;
-    for (int r = 0; r < rest_rounds; ++r) {
-        int take = rem / rest_rounds + (r < rem % rest_rounds ? 1 : 0);
-        rounds.push_back({0, take});
-    }
-    return rounds;
+    if (best.empty()) throw std::runtime_error("no round split");
+    return best;
 }
 
 struct DeviceTables {
@@ -142,8 +140,13 @@ static const double2 *upload(DeviceTables &dt, const std::vector<double2> &v) {
     return (const double2 *)d;
 }
 
-// Build the descriptor and twiddle tables of a length-N transform.
-static XDesc build_xdesc(DeviceTables &dt, int N, int max2 = 5) {
+struct XTables {
+    std::vector<double2> fwd, inv;
+};
+
+// Descriptor and (optionally) twiddle tables of a length-N transform; pure
+// host code.
+static XDesc describe_xdesc(int N, XTables *tabs) {
     XDesc x{};
     x.N = N;
     uint64_t tmp = (uint64_t)N;
@@ -155,7 +158,7 @@ static XDesc build_xdesc(DeviceTables &dt, int N, int max2 = 5) {
     x.nstages = (int)radix.size();
     if (x.nstages > kMaxStages) throw std::runtime_error("too many stages");
 
-    auto rounds = split_rounds(k3, k2, max2);
+    auto rounds = split_rounds(k3, k2);
     if ((int)rounds.size() > kMaxRounds) throw std::runtime_error("too many rounds");
     x.nrounds = (int)rounds.size();
     int s = 0;
@@ -176,13 +179,35 @@ static XDesc build_xdesc(DeviceTables &dt, int N, int max2 = 5) {
         s += n3 + n2;
         P *= (uint64_t)rho;
     }
+    {
+        const RoundDesc &last = x.round[x.nrounds - 1];
+        int rho_last = last.M >> last.jl_log2;
+        x.lgpad = __builtin_ctz((unsigned)rho_last);
+        if (rho_last & (rho_last - 1)) x.lgpad = 4;  // single mixed round: any pad works
+    }
 
+    if (!tabs) {
+        uint64_t Ps = 1;
+        int fo = 0, io = 0;
+        for (int st = 0; st < x.nstages; ++st) {
+            const int r = radix[(size_t)st];
+            const uint64_t J = (uint64_t)N / (Ps * (uint64_t)r);
+            x.fwd_off[st] = fo;
+            x.inv_off[st] = io;
+            fo += (int)(Ps * (uint64_t)(r - 1));
+            io += (int)(J * (uint64_t)(r - 1));
+            Ps *= (uint64_t)r;
+        }
+        return x;
+    }
     const uint64_t w = root_of_unity((uint64_t)N);
     std::vector<uint64_t> pw((size_t)N);
     pw[0] = 1;
     for (int i = 1; i < N; ++i) pw[(size_t)i] = mulmod_u(pw[(size_t)i - 1], w);
 
-    std::vector<double2> fwd, inv;
+    std::vector<double2> &fwd = tabs->fwd, &inv = tabs->inv;
+    fwd.clear();
+    inv.clear();
     uint64_t Ps = 1;
     for (int st = 0; st < x.nstages; ++st) {
         const int r = radix[(size_t)st];
@@ -211,46 +236,101 @@ static XDesc build_xdesc(DeviceTables &dt, int N, int max2 = 5) {
             }
         Ps *= (uint64_t)r;
     }
-    x.fwd_tw = upload(dt, fwd);
-    x.inv_tw = upload(dt, inv);
     return x;
 }
 
 struct PlanEntry {
     DeviceTables tables;
-    LenPlan plan{};
+    LenPlan plan{};          // host copy (pointers refer to device memory)
+    LenPlan *dplan = nullptr; // device copy read by the kernels
 };
 
 static int choose_log2R(uint64_t L) {
     int k, j;
     factor_len(L, k, j);
-    int a = std::min(10, (k + 1) / 2);
-    a = std::min(a, k - 6);
+    // R^2 ~ L/16 balances the column-tile count (C/16) with the row count.
+    const double lg = std::log2((double)L);
+    int a = (int)std::lround((lg - 4.0) / 2.0);
+    a = std::min(a, std::min(10, k - 6));
     return std::max(a, 1);
+}
+
+static int round_items(const RoundDesc &rd, int W) { return rd.ngroups * W; }
+
+static int threads_for(const XDesc &x, int W) {
+    int mx = 0;
+    for (int r = 0; r < x.nrounds; ++r) mx = std::max(mx, round_items(x.round[r], W));
+    int t = std::min(512, mx);
+    t = (t + 63) / 64 * 64;
+    return std::max(t, 64);
 }
 
 static std::mutex g_mu;
 static std::map<std::pair<int, uint64_t>, std::unique_ptr<PlanEntry>> g_plans;
 
-const LenPlan *get_len_plan(uint64_t L, int log2R_override) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) throw std::runtime_error("hipGetDevice failed");
-    int a = log2R_override > 0 ? log2R_override : choose_log2R(L);
-    uint64_t key_len = L | ((uint64_t)a << 56);
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_plans.find({dev, key_len});
-    if (it != g_plans.end()) return &it->second->plan;
-
-    auto e = std::make_unique<PlanEntry>();
-    LenPlan &lp = e->plan;
+// Launch geometry of length L (pure host code; throws on invalid choices).
+// log2R = 0 / W = 0 pick the defaults.
+void plan_geometry(uint64_t L, int log2R, int Wreq, LenPlan &lp, XTables *ct, XTables *rt) {
+    int k, j;
+    factor_len(L, k, j);
+    if (L < kMinLen || L > kMaxLen || k < 7 || k > kMaxPow2 || j > kMaxPow3)
+        throw std::runtime_error("unsupported transform length");
+    const int a = log2R > 0 ? log2R : choose_log2R(L);
+    if (a < 1 || a > 10 || a > k - 6) throw std::runtime_error("invalid row count for this length");
+    lp = LenPlan{};
     lp.L = L;
     lp.log2R = a;
     lp.R = 1 << a;
     lp.C = (int)(L >> a);
     if ((uint64_t)lp.R * (uint64_t)lp.C != L || lp.C % 64) throw std::runtime_error("bad four-step split");
-    lp.W = std::min(64, 16384 / lp.R);
-    lp.col = build_xdesc(e->tables, lp.R);
-    lp.row = build_xdesc(e->tables, lp.C);
+    lp.col = describe_xdesc(lp.R, ct);
+    lp.row = describe_xdesc(lp.C, rt);
+    if (lp.row.nrounds < 2) throw std::runtime_error("row transform needs at least two rounds");
+    const int rho_c0 = lp.col.round[0].M >> lp.col.round[0].jl_log2;
+    // Column tile width: the extraction ballots need whole waves per item
+    // of the first column round (W * R / rho_c0 >= 64); beyond that as wide
+    // as possible while leaving >= 256 tiles and <= 16K elements per tile.
+    const int wmin = std::max(16, 64 * rho_c0 / lp.R);
+    int W = wmin;
+    for (int w : {64, 32}) {
+        if (w >= wmin && lp.C / w >= 256 && lp.R * w <= 16384) {
+            W = w;
+            break;
+        }
+    }
+    if (Wreq) {
+        if (Wreq < wmin) throw std::runtime_error("tile width too small for this row count");
+        W = Wreq;
+    }
+    if (W != 16 && W != 32 && W != 64) throw std::runtime_error("tile width must be 16, 32 or 64");
+    lp.W = W;
+    lp.ntiles = lp.C / W;
+    lp.col_threads = threads_for(lp.col, W);
+    lp.row_threads = threads_for(lp.row, 1);
+    if (round_items(lp.col.round[0], W) % 64) throw std::runtime_error("column round not a multiple of 64 items");
+    lp.col_lds = (lp.R + (lp.R >> lp.col.lgpad)) * W;
+    lp.row_lds = lp.C + (lp.C >> lp.row.lgpad);
+    if (lp.col_lds * 4 > 160 * 1024 || lp.row_lds * 4 > 160 * 1024) throw std::runtime_error("tile does not fit in LDS");
+    lp.fused_ok = 2 * lp.row_lds * 4 <= 160 * 1024;
+    lp.rho0 = lp.row.round[0].M >> lp.row.round[0].jl_log2;
+}
+
+PlanRef get_len_plan(uint64_t L, int log2R_override, int W_override) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) throw std::runtime_error("hipGetDevice failed");
+    const uint64_t key_len = L | ((uint64_t)log2R_override << 40) | ((uint64_t)W_override << 48);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find({dev, key_len});
+    if (it != g_plans.end()) return {&it->second->plan, it->second->dplan};
+
+    auto e = std::make_unique<PlanEntry>();
+    LenPlan &lp = e->plan;
+    XTables ct, rt;
+    plan_geometry(L, log2R_override, W_override, lp, &ct, &rt);
+    lp.col.fwd_tw = upload(e->tables, ct.fwd);
+    lp.col.inv_tw = upload(e->tables, ct.inv);
+    lp.row.fwd_tw = upload(e->tables, rt.fwd);
+    lp.row.inv_tw = upload(e->tables, rt.inv);
 
     const uint64_t wL = root_of_unity(L);
     std::vector<double2> lo(4096), hi((size_t)((L + 4095) / 4096));
@@ -261,11 +341,30 @@ const LenPlan *get_len_plan(uint64_t L, int log2R_override) {
     for (size_t i = 0; i < hi.size(); ++i) { hi[i] = tw_pair(v); v = mulmod_u(v, w4096); }
     lp.twist_lo = upload(e->tables, lo);
     lp.twist_hi = upload(e->tables, hi);
-    double2 li = tw_pair(powmod_u(L % (uint64_t)kP, (uint64_t)kP - 2));
-    lp.Linv = li.x;
-    lp.Linv_p = li.y;
 
-    const LenPlan *out = &e->plan;
+    // alpha tables for the row pass twist: element q = jj + l*J0 of round 0
+    // is multiplied by omega_L^(k1 jj) * omega_L^(k1 J0 l) (forward) and by
+    // omega_L^(-k1 jj) * omega_L^(-k1 J0 l) / L (inverse).
+    const uint64_t J0 = (uint64_t)lp.C / (uint64_t)lp.rho0;
+    const uint64_t Linv = powmod_u(L % (uint64_t)kP, (uint64_t)kP - 2);
+    std::vector<double2> af((size_t)lp.R * lp.rho0), ai((size_t)lp.R * lp.rho0);
+    for (uint64_t k1 = 0; k1 < (uint64_t)lp.R; ++k1)
+        for (uint64_t u = 0; u < (uint64_t)lp.rho0; ++u) {
+            const uint64_t ex = (k1 * J0 * u) % L;
+            af[(size_t)(k1 * lp.rho0 + u)] = tw_pair(powmod_u(wL, ex));
+            ai[(size_t)(k1 * lp.rho0 + u)] = tw_pair(mulmod_u(powmod_u(wL, (L - ex) % L), Linv));
+        }
+    lp.alpha_f = upload(e->tables, af);
+    lp.alpha_i = upload(e->tables, ai);
+
+    void *d = nullptr;
+    if (hipMalloc(&d, sizeof(LenPlan)) != hipSuccess) throw std::bad_alloc();
+    e->tables.allocs.push_back(d);
+    if (hipMemcpy(d, &lp, sizeof(LenPlan), hipMemcpyHostToDevice) != hipSuccess)
+        throw std::runtime_error("hipMemcpy of plan failed");
+    e->dplan = (LenPlan *)d;
+
+    PlanRef out{&e->plan, e->dplan};
     g_plans[{dev, key_len}] = std::move(e);
     return out;
 }

@@ -22,8 +22,21 @@ uint64_t required_len(uint64_t n, uint64_t m);
 // Smallest supported length >= req (0 if none).
 uint64_t choose_len(uint64_t req);
 
-// Cached per-device plan for length L; log2R_override > 0 forces the split.
-// Throws std::bad_alloc / std::runtime_error on failure.
-const LenPlan *get_len_plan(uint64_t L, int log2R_override = 0);
+struct XTables;
+
+// Launch geometry of length L without touching the device (throws
+// std::runtime_error for invalid choices); table pointers are left null.
+void plan_geometry(uint64_t L, int log2R, int W, LenPlan &lp, XTables *ct = nullptr, XTables *rt = nullptr);
+
+// A plan: host copy (for launch geometry) and the device copy the kernels read.
+struct PlanRef {
+    const LenPlan *host;
+    const LenPlan *dev;
+};
+
+// Cached per-device plan for length L; log2R_override > 0 forces R = 2^a,
+// W_override > 0 forces the column tile width.  Throws std::bad_alloc /
+// std::runtime_error on failure.
+PlanRef get_len_plan(uint64_t L, int log2R_override = 0, int W_override = 0);
 
 }  // namespace pa

@@ -131,3 +131,35 @@ def test_product_never_touches_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "toeplitz_oracle" not in text and "liboracle" not in text, f
+
+
+def test_every_supported_length_has_a_valid_launch_geometry(lib):
+    for L in pa.supported_lengths():
+        d = pa.plan_info(L)
+        R, C, W = d["rows"], d["cols"], d["tile_width"]
+        assert R * C == L and C % 64 == 0 and W in (16, 32, 64) and C % W == 0
+        assert 1 <= d["col_threads"] <= 512 and d["col_threads"] % 64 == 0
+        assert 1 <= d["row_threads"] <= 512 and d["row_threads"] % 64 == 0
+        assert d["col_lds_bytes"] <= 160 * 1024 and d["row_lds_bytes"] <= 160 * 1024
+        prod = 1
+        for r in d["col_round_size"]:
+            assert r in (2, 4, 8, 16)
+            prod *= r
+        assert prod == R
+        prod = 1
+        for i, r in enumerate(d["row_round_size"]):
+            assert r <= 27 and (i == 0 or r in (2, 4, 8, 16))
+            prod *= r
+        assert prod == C and d["row_rounds"] >= 2
+        # the output-packing ballots need the first column round to cover
+        # whole 64-lane waves
+        assert (R // d["col_round_size"][0]) * W % 64 == 0
+
+
+def test_geometry_overrides(lib):
+    d = pa.plan_info(3 * 2**19, log2_rows=9, tile_width=32)
+    assert (d["rows"], d["cols"], d["tile_width"]) == (512, 3072, 32)
+    with pytest.raises(pa.PAError):
+        pa.plan_info(3 * 2**19, log2_rows=16)
+    with pytest.raises(pa.PAError):
+        pa.plan_info(12345)

@@ -1,0 +1,208 @@
+"""Benchmark of the Toeplitz-hash privacy-amplification hot path on one GPU.
+
+Default workload (the value line): one privacy-amplification block at the
+finite-size scale, n = 10^6 key bits, m = 250,000 output bits, i.i.d.
+Bernoulli(0.5) key and seed bits (seeded, synthetic), plain path: each step
+is one pa_toeplitz_hash call = seed and key column transforms, the fused
+row pass (both row transforms, product, inverse), and the inverse column
+pass with parity extraction.  Inputs are resident in HBM before timing.
+
+Also reported on the same JSON line:
+  * batched: 256 blocks of the same shape in one pa_toeplitz_hash_batched
+    call (aggregate input Gb/s);
+  * roofline of the dominant kernel, from HIP events the library records
+    around each launch on its own stream (algorithmic bytes and fp64
+    operations per launch / average duration);
+  * cpu_baseline: the CPU oracle (packed AND + popcount parity) timed on
+    this host's cores on full blocks of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "PA input Gb/s at n=10^6 plain vs batched; p50/p99 latency of serving loop"
+HBM_PEAK_GBS = 8000.0                          # MI355X HBM3E, vendor figure
+FP64_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # CUs x SIMDs x lanes x clock: fp64 FMA/add issue rate
+N_BITS, M_BITS = 1_000_000, 250_000
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("pa_kernels.hip", "pa_internal.h"):
+        with open(os.path.join(ROOT, "paper_1809_07592_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 PMC runs, if they were
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def cpu_baseline(key, seed, n, m, budget_s=12.0):
+    import oracle
+    oracle.build()
+    threads = oracle.max_threads()
+    oracle.toeplitz_hash(key, n, seed, m, threads=threads)  # warm the allocator/threads
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.toeplitz_hash(key, n, seed, m, threads=threads)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 200:
+            break
+    return {"value": n * reps / el / 1e9, "unit": "Gb/s", "cores": threads, "kind": "oracle",
+            "sample": "%d full blocks of n=%d, m=%d (all %d outputs each), %.1f s" % (reps, n, m, m, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only (independent blocks shard by routing whole blocks to "
+              "GPUs; no collective is involved); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1809_07592_amd as pa
+    from paper_1809_07592_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    pa.lib()  # fails loudly if the HIP library is missing
+    torch.cuda.set_device(0)
+    n, m = N_BITS, M_BITS
+    key, seed = wl.key_and_seed(2, n, m, 0)
+    dk = torch.from_numpy(key.view(np.int64)).cuda()
+    ds = torch.from_numpy(seed.view(np.int64)).cuda()
+    out = torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        pa.toeplitz_hash(dk, n, ds, m, out, stream=stream)
+
+    ms, wall = time_steps(step, args.steps, args.warmup, torch)
+    value = n / (ms * 1e-3) / 1e9
+
+    # per-kernel timing of the same steps (separate, profiled pass)
+    pa.profile_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = pa.profile_collect()
+    pa.profile_enable(False)
+    kernels = {}
+    for name, st in prof.items():
+        avg_s = st["avg_ms"] * 1e-3
+        b = st["alg_bytes"] / st["launches"]
+        o = st["alg_ops"] / st["launches"]
+        kernels[name] = {"avg_us": st["avg_ms"] * 1e3, "alg_bytes_per_launch": b, "alg_ops_per_launch": o,
+                         "hbm_GBs": b / avg_s / 1e9, "hbm_frac": b / avg_s / 1e9 / HBM_PEAK_GBS,
+                         "fp64_Tops": o / avg_s / 1e12, "alu_frac": o / avg_s / 1e12 / FP64_VALU_PEAK_TOPS,
+                         "share_of_step": st["total_ms"] / st["launches"] / ms}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
+    kd = kernels[dom]
+    bound = "alu" if kd["alu_frac"] >= kd["hbm_frac"] else "hbm"
+    traffic = load_traffic(dom)
+    if bound == "alu":
+        roofline = {"bound": "alu", "kernel": dom, "achieved": kd["fp64_Tops"], "peak": FP64_VALU_PEAK_TOPS,
+                    "unit": "Tops/s (fp64 FMA/add)", "frac": kd["alu_frac"], "traffic": traffic}
+    else:
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": kd["hbm_GBs"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": kd["hbm_frac"], "traffic": traffic}
+    roofline_hbm = {"kernel": dom, "achieved": kd["hbm_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": kd["hbm_frac"]}
+
+    # batched: args.batch blocks of the same shape in one submission
+    batched = None
+    if args.batch > 0:
+        blocks = []
+        for i in range(args.batch):
+            k_i, s_i = wl.key_and_seed(4, n, m, i)
+            blocks.append((torch.from_numpy(k_i.view(np.int64)).cuda(), n, torch.from_numpy(s_i.view(np.int64)).cuda(),
+                           m, torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")))
+
+        def bstep():
+            pa.toeplitz_hash_batched(blocks, stream=stream)
+
+        bsteps = max(3, args.steps // 40)
+        bms, _ = time_steps(bstep, bsteps, 2, torch)
+        pa.profile_enable(True)
+        bstep()
+        torch.cuda.synchronize()
+        bprof = pa.profile_collect()
+        pa.profile_enable(False)
+        bk = {}
+        for name, st in bprof.items():
+            avg_s = st["avg_ms"] * 1e-3
+            bk[name] = {"avg_us": st["avg_ms"] * 1e3,
+                        "hbm_frac": st["alg_bytes"] / st["launches"] / avg_s / 1e9 / HBM_PEAK_GBS,
+                        "alu_frac": st["alg_ops"] / st["launches"] / avg_s / 1e12 / FP64_VALU_PEAK_TOPS}
+        batched = {"value": args.batch * n / (bms * 1e-3) / 1e9, "unit": "Gb/s", "blocks": args.batch,
+                   "ms_per_batch": bms, "kernels": bk,
+                   "speedup_vs_plain": args.batch * n / (bms * 1e-3) / 1e9 / value}
+        del blocks
+
+    cpu = None if args.no_cpu else cpu_baseline(key, seed, n, m)
+    line = {
+        "metric": METRIC, "value": value, "unit": "Gb/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "single PA block, plain path: n=1000000 key bits, m=250000 output bits, "
+                               "Bernoulli(0.5) key and seed bits, packed uint64", "n": n, "m": m,
+                   "transform_len": pa.transform_len(n, m)},
+        "wall_s_timed_region": wall,
+        "roofline": roofline, "roofline_hbm": roofline_hbm, "kernels": kernels,
+        "batched": batched, "serving": None, "cpu_baseline": cpu,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -92,8 +92,10 @@ pa_status pa_toeplitz_hash_batched(const pa_block *blocks, uint32_t count,
  * transform length L serves every (n, m) with n + m - 1 <= seed_len_bits
  * and required length <= L (seed bits beyond n+m-1 never influence y).
  * transform_len = 0 picks the smallest supported L covering any n + m - 1
- * <= seed_len_bits.  The seed buffer may be freed once the plan's stream
- * work has completed.
+ * <= seed_len_bits.  The plan belongs to the device current at creation;
+ * its spectrum is built on `stream`, so hashes on other streams must be
+ * ordered after that work.  The seed buffer may be freed once the plan's
+ * stream work has completed.
  */
 typedef struct pa_plan_s *pa_plan_t;
 
@@ -142,6 +144,29 @@ pa_status pa_plan_describe(uint64_t transform_len, uint32_t log2_rows, uint32_t 
 /* Device bytes of library workspace one in-flight block of (n, m) needs on
  * the plain path (two length-L residue arrays); 0 if invalid. */
 size_t pa_workspace_bytes(uint64_t n, uint64_t m);
+
+/*
+ * Kernel timing (tracing).  While enabled, the library brackets every
+ * kernel it launches with a pair of HIP events recorded on the launch's
+ * own stream, and notes the launch's algorithmic HBM bytes (what the
+ * method must read and write: packed bits, residue arrays, spectra) and
+ * algorithmic fp64 operations (butterflies, twists, products, reductions;
+ * an FMA or an add counts as one operation).  pa_profile_collect waits for
+ * the recorded events, aggregates them per kernel name into `stats`
+ * (capacity entries; *count receives the number of kernel names) and
+ * clears the record.  Timing adds one event pair per launch; leave it off
+ * for throughput runs.
+ */
+typedef struct pa_kernel_stat {
+    char name[32];
+    uint64_t launches;
+    double total_ms;   /* sum of event-measured durations */
+    double alg_bytes;  /* sum over launches */
+    double alg_ops;    /* sum over launches */
+} pa_kernel_stat;
+
+pa_status pa_profile_enable(int on);
+pa_status pa_profile_collect(pa_kernel_stat *stats, uint32_t capacity, uint32_t *count);
 
 /* Static text for a status code. */
 const char *pa_status_string(pa_status s);

@@ -50,6 +50,11 @@ class PlanInfo(ctypes.Structure):
         return d
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double), ("alg_ops", ctypes.c_double)]
+
+
 class _Block(ctypes.Structure):
     _fields_ = [("key_bits", ctypes.c_void_p), ("n", ctypes.c_uint64), ("seed_bits", ctypes.c_void_p),
                 ("m", ctypes.c_uint64), ("out_bits", ctypes.c_void_p)]
@@ -83,6 +88,10 @@ def lib():
                 L.pa_transform_len.restype = u64
                 L.pa_plan_describe.argtypes = [u64, u32, u32, ctypes.POINTER(PlanInfo)]
                 L.pa_plan_describe.restype = st
+                L.pa_profile_enable.argtypes = [ctypes.c_int]
+                L.pa_profile_enable.restype = st
+                L.pa_profile_collect.argtypes = [ctypes.POINTER(KernelStat), u32, ctypes.POINTER(u32)]
+                L.pa_profile_collect.restype = st
                 L.pa_workspace_bytes.argtypes = [u64, u64]
                 L.pa_workspace_bytes.restype = ctypes.c_size_t
                 L.pa_status_string.argtypes = [st]
@@ -125,6 +134,26 @@ def plan_info(transform_len: int, log2_rows: int = 0, tile_width: int = 0) -> di
     info = PlanInfo()
     _check(lib().pa_plan_describe(int(transform_len), int(log2_rows), int(tile_width), ctypes.byref(info)))
     return info.as_dict()
+
+
+def profile_enable(on: bool = True):
+    """Bracket every library kernel launch with HIP events on its stream."""
+    _check(lib().pa_profile_enable(1 if on else 0))
+
+
+def profile_collect() -> dict:
+    """{kernel: {launches, total_ms, avg_ms, alg_bytes, alg_ops}}; clears the record."""
+    cap = 32
+    arr = (KernelStat * cap)()
+    n = ctypes.c_uint32()
+    _check(lib().pa_profile_collect(arr, cap, ctypes.byref(n)))
+    out = {}
+    for i in range(min(n.value, cap)):
+        k = arr[i]
+        out[k.name.decode()] = {"launches": int(k.launches), "total_ms": k.total_ms,
+                                "avg_ms": k.total_ms / max(int(k.launches), 1),
+                                "alg_bytes": k.alg_bytes, "alg_ops": k.alg_ops}
+    return out
 
 
 def supported_lengths():

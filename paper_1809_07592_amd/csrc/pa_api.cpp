@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
@@ -62,6 +64,9 @@ pa_status check_block(const uint64_t *key, uint64_t n, const uint64_t *seed, uin
 struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
+    void *pinned = nullptr;       // host staging for job tables
+    size_t pinned_bytes = 0;
+    hipEvent_t staged = nullptr;  // recorded after the last copy out of `pinned`
 };
 std::mutex g_ws_mu;
 std::map<std::pair<int, void *>, Workspace> g_ws;
@@ -88,6 +93,162 @@ pa_status get_workspace(hipStream_t s, size_t bytes, void **out) {
     return PA_OK;
 }
 
+// Copy `bytes` of host data to device address `dst` on stream s through
+// the stream's pinned staging buffer (waits until the previous copy out of
+// the staging buffer has completed before overwriting it).
+pa_status stage_upload(hipStream_t s, void *dst, const void *src, size_t bytes) {
+    int dev = 0;
+    PA_HIP(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[{dev, (void *)s}];
+    if (w.staged) PA_HIP(hipEventSynchronize(w.staged), "hipEventSynchronize");
+    if (w.pinned_bytes < bytes) {
+        if (w.pinned) PA_HIP(hipHostFree(w.pinned), "hipHostFree");
+        w.pinned = nullptr;
+        w.pinned_bytes = 0;
+        const size_t alloc = std::max(bytes, (size_t)64 << 10);
+        PA_HIP(hipHostMalloc(&w.pinned, alloc, hipHostMallocDefault), "hipHostMalloc");
+        w.pinned_bytes = alloc;
+    }
+    if (!w.staged) PA_HIP(hipEventCreateWithFlags(&w.staged, hipEventDisableTiming), "hipEventCreate");
+    memcpy(w.pinned, src, bytes);
+    PA_HIP(hipMemcpyAsync(dst, w.pinned, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    PA_HIP(hipEventRecord(w.staged, s), "hipEventRecord");
+    return PA_OK;
+}
+
+// ------------------------------------------------------------ kernel timing
+
+struct ProfRec {
+    const char *name;
+    hipEvent_t start, stop;
+    double bytes, ops;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t pool_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Algorithmic fp64 operations of one length-N transform (either
+// direction): a radix-2 butterfly is one modular product (3 FMAs) and two
+// adds, a radix-3 butterfly three products and seven adds.
+double xform_ops(const pa::XDesc &x) {
+    double ops = 0;
+    for (int r = 0; r < x.nrounds; ++r) {
+        const int k = x.round[r].kind;
+        for (int i = 0; i < pa::kKindN3[k]; ++i) ops += (double)x.N / 3.0 * 16.0;
+        for (int i = 0; i < pa::kKindN2[k]; ++i) ops += (double)x.N / 2.0 * 5.0;
+    }
+    return ops;
+}
+
+// Launch `fn` (returning hipError_t), timed when profiling is on.
+template <class F>
+hipError_t timed(const char *name, hipStream_t s, double bytes, double ops, F &&fn) {
+    hipEvent_t a = nullptr, b = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (g_prof_on) {
+            a = pool_event();
+            b = pool_event();
+        }
+    }
+    if (a && b) {
+        hipError_t e = hipEventRecord(a, s);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = fn();
+    if (e != hipSuccess) return e;
+    if (a && b) {
+        e = hipEventRecord(b, s);
+        if (e != hipSuccess) return e;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof.push_back({name, a, b, bytes, ops});
+    }
+    return hipSuccess;
+}
+
+double words8(uint64_t bits) { return (double)((bits + 63) / 64) * 8.0; }
+
+// P1 over nsrc sources of njobs jobs (bits read: the packed inputs).
+hipError_t p1(const pa::PlanRef &p, int nsrc, const pa::JobArgs &ja, int njobs, double in_bytes, hipStream_t s) {
+    const double L = (double)p.host->L;
+    const double bytes = in_bytes + 4.0 * L * nsrc * njobs;
+    const double ops = (double)nsrc * njobs * xform_ops(p.host->col) * p.host->C;
+    return timed("colfwd", s, bytes, ops, [&] { return pa::launch_colfwd(*p.host, p.dev, nsrc, ja, njobs, s); });
+}
+
+// P2 in the given mode (0 plan, 1 seed spectrum, 2 fused plain path).
+hipError_t p2(const pa::PlanRef &p, int mode, const pa::JobArgs &ja, int njobs, hipStream_t s) {
+    const double L = (double)p.host->L;
+    const double xf = xform_ops(p.host->row) * p.host->R;
+    double bytes = 0, ops = 0;
+    if (mode == 1) {
+        bytes = 8.0 * L;               // read residues, write spectrum
+        ops = xf + 6.0 * L + 3.0 * L;  // transform, twist, reduction
+    } else {
+        bytes = 12.0 * L;              // read A and the spectrum (or S), write A
+        ops = 2.0 * xf + 12.0 * L + 4.0 * L;  // forward + inverse, two twists, product
+        if (mode == 2) ops += xf + 6.0 * L + 3.0 * L;
+    }
+    return timed(mode == 1 ? "rowspec" : "rowconv", s, bytes * njobs, ops * njobs,
+                 [&] { return pa::launch_rowconv(*p.host, p.dev, mode, ja, njobs, s); });
+}
+
+// P3 of njobs jobs (out_bytes: the packed outputs).
+hipError_t p3(const pa::PlanRef &p, const pa::JobArgs &ja, int njobs, double out_bytes, hipStream_t s) {
+    const double L = (double)p.host->L;
+    const double bytes = 4.0 * L * njobs + out_bytes;
+    const double ops = njobs * (xform_ops(p.host->col) * p.host->C + 4.0 * L);
+    return timed("colinv", s, bytes, ops, [&] { return pa::launch_colinv(*p.host, p.dev, ja, njobs, s); });
+}
+
+inline uint64_t out_offset(uint64_t n) { return 64 * ((n - 1 + 63) / 64); }
+
+// Descriptor of a plain-path block with workspace A, S.
+pa::JobDesc plain_job(const uint64_t *key, uint64_t n, const uint64_t *seed, uint64_t m, uint64_t *out, int32_t *A,
+                      int32_t *S) {
+    pa::JobDesc j{};
+    j.key = key;
+    j.seed = seed;
+    j.out = out;
+    j.A = A;
+    j.S = S;
+    j.Shat = S;
+    j.n = (uint32_t)n;
+    j.seed_bits = (uint32_t)(n + m - 1);
+    j.m = (uint32_t)m;
+    j.off0 = (uint32_t)out_offset(n);
+    j.shift = (uint32_t)(out_offset(n) - (n - 1));
+    return j;
+}
+
+// The plain-path pass sequence for njobs jobs of one length: fused (two
+// rows in LDS) when they fit, else the seed spectrum goes through HBM.
+pa_status run_plain(const pa::PlanRef &p, const pa::JobArgs &ja, int njobs, double in_bytes, double out_bytes,
+                    hipStream_t s) {
+    PA_HIP(p1(p, 2, ja, njobs, in_bytes, s), "launch P1");
+    if (p.host->fused_ok) {
+        PA_HIP(p2(p, 2, ja, njobs, s), "launch P2");
+    } else {
+        PA_HIP(p2(p, 1, ja, njobs, s), "launch P2 (seed)");
+        PA_HIP(p2(p, 0, ja, njobs, s), "launch P2");
+    }
+    PA_HIP(p3(p, ja, njobs, out_bytes, s), "launch P3");
+    return PA_OK;
+}
+
 pa_status plan_for(uint64_t L, pa::PlanRef *lp) {
     try {
         *lp = pa::get_len_plan(L);
@@ -99,57 +260,40 @@ pa_status plan_for(uint64_t L, pa::PlanRef *lp) {
     return PA_OK;
 }
 
-inline uint64_t out_offset(uint64_t n) { return 64 * ((n - 1 + 63) / 64); }
-
-// Key path against a ready spectrum: P1 (key), P2 (convolve), P3 (extract).
+// Key path against a ready spectrum Shat: P1 (key), P2 (convolve), P3.
 pa_status run_key_path(const pa::PlanRef &p, const uint64_t *key, uint64_t n, uint64_t m, const int32_t *Shat,
                        int32_t *A, uint64_t *out, hipStream_t s) {
-    const uint64_t off0 = out_offset(n);
-    const uint64_t *bits[2] = {key, nullptr};
-    const uint64_t nb[2] = {n, 0};
-    const int64_t sh[2] = {(int64_t)(off0 - (n - 1)), 0};
-    int32_t *dst[2] = {A, nullptr};
-    PA_HIP(pa::launch_colfwd(*p.host, p.dev, 1, bits, nb, sh, dst, s), "launch P1");
-    PA_HIP(pa::launch_rowconv(*p.host, p.dev, A, Shat, nullptr, 0, s), "launch P2");
-    PA_HIP(pa::launch_colinv(*p.host, p.dev, A, out, off0, m, s), "launch P3");
+    pa::JobArgs ja{};
+    ja.one = plain_job(key, n, nullptr, m, out, A, nullptr);
+    ja.one.Shat = Shat;
+    PA_HIP(p1(p, 1, ja, 1, words8(n), s), "launch P1");
+    PA_HIP(p2(p, 0, ja, 1, s), "launch P2");
+    PA_HIP(p3(p, ja, 1, words8(m), s), "launch P3");
     return PA_OK;
 }
 
 // Seed spectrum of the first nbits seed bits into S (length L residues).
 pa_status run_seed_path(const pa::PlanRef &p, const uint64_t *seed, uint64_t nbits, int32_t *S, hipStream_t s) {
-    const uint64_t *bits[2] = {seed, nullptr};
-    const uint64_t nb[2] = {nbits, 0};
-    const int64_t sh[2] = {0, 0};
-    int32_t *dst[2] = {S, nullptr};
-    PA_HIP(pa::launch_colfwd(*p.host, p.dev, 1, bits, nb, sh, dst, s), "launch P1 (seed)");
-    PA_HIP(pa::launch_rowconv(*p.host, p.dev, S, nullptr, nullptr, 1, s), "launch P2 (seed)");
+    pa::JobArgs ja{};
+    ja.one.key = seed;
+    ja.one.n = (uint32_t)nbits;
+    ja.one.shift = 0;
+    ja.one.A = S;
+    ja.one.S = S;
+    PA_HIP(p1(p, 1, ja, 1, words8(nbits), s), "launch P1 (seed)");
+    PA_HIP(p2(p, 1, ja, 1, s), "launch P2 (seed)");
     return PA_OK;
 }
 
-// Plain path: key and seed column transforms in one launch, both row
-// transforms and the product in one launch, then the extraction.
 pa_status hash_one(const uint64_t *key, uint64_t n, const uint64_t *seed, uint64_t m, uint64_t *out, uint64_t L,
                    hipStream_t s) {
     pa::PlanRef p{};
     PA_TRY(plan_for(L, &p));
     void *ws = nullptr;
     PA_TRY(get_workspace(s, (size_t)(8 * L), &ws));
-    int32_t *A = (int32_t *)ws;
-    int32_t *S = A + L;
-    if (!p.host->fused_ok) {
-        // rows too long for two in LDS: seed spectrum through HBM first
-        PA_TRY(run_seed_path(p, seed, n + m - 1, S, s));
-        return run_key_path(p, key, n, m, S, A, out, s);
-    }
-    const uint64_t off0 = out_offset(n);
-    const uint64_t *bits[2] = {key, seed};
-    const uint64_t nb[2] = {n, n + m - 1};
-    const int64_t sh[2] = {(int64_t)(off0 - (n - 1)), 0};
-    int32_t *dst[2] = {A, S};
-    PA_HIP(pa::launch_colfwd(*p.host, p.dev, 2, bits, nb, sh, dst, s), "launch P1");
-    PA_HIP(pa::launch_rowconv(*p.host, p.dev, A, nullptr, S, 2, s), "launch P2");
-    PA_HIP(pa::launch_colinv(*p.host, p.dev, A, out, off0, m, s), "launch P3");
-    return PA_OK;
+    pa::JobArgs ja{};
+    ja.one = plain_job(key, n, seed, m, out, (int32_t *)ws, (int32_t *)ws + L);
+    return run_plain(p, ja, 1, words8(n) + words8(n + m - 1), words8(m), s);
 }
 
 }  // namespace
@@ -177,6 +321,51 @@ const char *pa_status_string(pa_status s) {
 }
 
 const char *pa_last_error(void) { return g_last_error.c_str(); }
+
+pa_status pa_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return PA_OK;
+}
+
+pa_status pa_profile_collect(pa_kernel_stat *stats, uint32_t capacity, uint32_t *count) {
+    if (!count || (capacity && !stats)) return fail(PA_ERR_INVALID_ARG, "null output pointer");
+    std::vector<ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        recs.swap(g_prof);
+    }
+    std::vector<pa_kernel_stat> agg;
+    hipError_t err = hipSuccess;
+    for (const ProfRec &r : recs) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(r.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
+        if (e != hipSuccess && err == hipSuccess) err = e;
+        pa_kernel_stat *st = nullptr;
+        for (auto &a : agg)
+            if (std::string(a.name) == r.name) st = &a;
+        if (!st) {
+            agg.push_back(pa_kernel_stat{});
+            st = &agg.back();
+            snprintf(st->name, sizeof(st->name), "%s", r.name);
+        }
+        st->launches += 1;
+        st->total_ms += (double)ms;
+        st->alg_bytes += r.bytes;
+        st->alg_ops += r.ops;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        for (const ProfRec &r : recs) {
+            g_event_pool.push_back(r.start);
+            g_event_pool.push_back(r.stop);
+        }
+    }
+    *count = (uint32_t)agg.size();
+    for (uint32_t i = 0; i < capacity && i < agg.size(); ++i) stats[i] = agg[i];
+    return from_hip(err, "profile events");
+}
 
 const char *pa_version(void) { return "pa-mi355x 0.1 (gfx950; NTT mod 27*2^20+1, fp64 modmul)"; }
 
@@ -231,15 +420,60 @@ pa_status pa_toeplitz_hash(const uint64_t *key_bits, uint64_t n, const uint64_t 
 pa_status pa_toeplitz_hash_batched(const pa_block *blocks, uint32_t count, void *stream) {
     if (count == 0) return PA_OK;
     if (!blocks) return fail(PA_ERR_INVALID_ARG, "null block array");
+    hipStream_t s = (hipStream_t)stream;
     std::vector<uint64_t> lens(count);
     for (uint32_t i = 0; i < count; ++i) {
         const pa_block &b = blocks[i];
         pa_status st = check_block(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, &lens[i]);
         if (st != PA_OK) return fail(st, "block " + std::to_string(i) + ": " + g_last_error);
     }
-    for (uint32_t i = 0; i < count; ++i) {
-        const pa_block &b = blocks[i];
-        PA_TRY(hash_one(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, lens[i], (hipStream_t)stream));
+    // Group blocks by transform length: one pass sequence per length class.
+    std::map<uint64_t, std::vector<uint32_t>> groups;
+    for (uint32_t i = 0; i < count; ++i) groups[lens[i]].push_back(i);
+    std::vector<std::pair<uint64_t, pa::PlanRef>> plans;
+    for (auto &g : groups) {
+        pa::PlanRef p{};
+        PA_TRY(plan_for(g.first, &p));
+        plans.push_back({g.first, p});
+    }
+    // Workspace: the job table, then 8L bytes (A and S) per block.
+    const size_t table_bytes = ((size_t)count * sizeof(pa::JobDesc) + 255) / 256 * 256;
+    size_t total = table_bytes;
+    for (uint32_t i = 0; i < count; ++i) total += (size_t)(8 * lens[i]);
+    void *ws = nullptr;
+    PA_TRY(get_workspace(s, total, &ws));
+    pa::JobDesc *dtable = (pa::JobDesc *)ws;
+    int32_t *next = (int32_t *)((char *)ws + table_bytes);
+    std::vector<pa::JobDesc> table;
+    table.reserve(count);
+    std::vector<std::pair<size_t, size_t>> spans;  // [first, count) per group, in table order
+    for (auto &g : groups) {
+        spans.push_back({table.size(), g.second.size()});
+        for (uint32_t i : g.second) {
+            const pa_block &b = blocks[i];
+            const uint64_t L = g.first;
+            table.push_back(plain_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, next, next + L));
+            next += 2 * L;
+        }
+    }
+    PA_TRY(stage_upload(s, dtable, table.data(), table.size() * sizeof(pa::JobDesc)));
+    size_t gi = 0;
+    for (auto &g : groups) {
+        const pa::PlanRef &p = plans[gi].second;
+        const size_t first = spans[gi].first, n = spans[gi].second;
+        for (size_t off = 0; off < n; off += 65535) {
+            const int nj = (int)std::min<size_t>(65535, n - off);
+            pa::JobArgs ja{};
+            ja.table = dtable + first + off;
+            double in_b = 0, out_b = 0;
+            for (size_t k = first + off; k < first + off + (size_t)nj; ++k) {
+                in_b += words8(table[k].n) + words8(table[k].seed_bits);
+                out_b += words8(table[k].m);
+            }
+            PA_TRY(run_plain(p, ja, nj, in_b, out_b, s));
+        }
+        (void)g;
+        ++gi;
     }
     return PA_OK;
 }
@@ -292,6 +526,9 @@ pa_status pa_plan_hash(pa_plan_t plan, const uint64_t *key_bits, uint64_t n, uin
     if (m > n) return fail(PA_ERR_INVALID_ARG, "m > n: the hash must compress (m <= n)");
     if (n + m - 1 > plan->seed_len) return fail(PA_ERR_INVALID_ARG, "plan seed shorter than n + m - 1");
     if (pa::required_len(n, m) > plan->L) return fail(PA_ERR_INVALID_ARG, "block needs a longer transform than the plan");
+    int dev = 0;
+    PA_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != plan->device) return fail(PA_ERR_INVALID_ARG, "plan belongs to another device");
     void *ws = nullptr;
     PA_TRY(get_workspace((hipStream_t)stream, (size_t)(4 * plan->L), &ws));
     return run_key_path(plan->lp, key_bits, n, m, plan->Shat, (int32_t *)ws, out_bits, (hipStream_t)stream);

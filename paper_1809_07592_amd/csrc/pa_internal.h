@@ -107,4 +107,28 @@ struct LenPlan {
     const double2 *alpha_i;  // [k1][u] = omega_L^(-k1 * (C/rho0) * u) / L
 };
 
+// One block of work for the pass kernels (a plain hash, a plan hash, or a
+// seed-spectrum build).  Bit counts fit in 32 bits (<= the largest length).
+struct JobDesc {
+    const uint64_t *key;   // P1 source 0 (key bits, or seed bits for a spectrum build)
+    const uint64_t *seed;  // P1 source 1 (seed bits; plain path)
+    uint64_t *out;         // P3 output words
+    int32_t *A;            // residues of source 0 (L int32)
+    int32_t *S;            // residues of source 1 / spectrum being built (L int32)
+    const int32_t *Shat;   // ready spectrum for P2 mode 0
+    uint32_t n;            // bits of source 0
+    uint32_t seed_bits;    // bits of source 1
+    uint32_t m;            // output bits
+    uint32_t off0;         // first convolution position of the output window
+    uint32_t shift;        // shift of source 0 (off0 - (n - 1)); source 1 is unshifted
+    uint32_t pad_;
+};
+
+// Jobs of a launch: either one descriptor passed inline in the kernel
+// arguments, or a device table indexed by a grid dimension.
+struct JobArgs {
+    const JobDesc *table;
+    JobDesc one;
+};
+
 }  // namespace pa

@@ -9,21 +9,22 @@
 
 namespace pa {
 
-// P1: column-forward NTT of nsrc (1 or 2) bit strings in one launch.  For
-// source i, transform input position p holds bit p - shift[i] of bits[i]
-// when inside [0, nbits[i]); out[i] receives L int32 residues.
-hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const uint64_t *const bits[2],
-                         const uint64_t nbits[2], const int64_t shift[2], int32_t *const out[2], hipStream_t s);
+// All launchers run `njobs` jobs (ja.table != null: device table of njobs
+// descriptors; else the single inline descriptor ja.one) of one length.
+
+// P1: column-forward NTT of the jobs' bit strings: source 0 (key, shifted)
+// into job.A, and with nsrc = 2 also source 1 (seed) into job.S.
+hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const JobArgs &ja, int njobs,
+                         hipStream_t s);
 
 // P2: mode 0 = A <- conv(A, Shat) with the spectrum Shat in HBM; mode 1 =
-// A <- spectrum of A (for plans); mode 2 = A <- conv(A, spectrum of S)
-// (plain path, S = column-transformed seed).  In place on A.
-hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int32_t *A, const int32_t *Shat, const int32_t *S,
-                          int mode, hipStream_t s);
+// S <- spectrum of S (for plans); mode 2 = A <- conv(A, spectrum of S)
+// (plain path, needs hp.fused_ok).
+hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int mode, const JobArgs &ja, int njobs,
+                          hipStream_t s);
 
-// P3: inverse column NTT, parity of convolution positions [off0, off0+m),
-// packed into out (ceil(m/64) words, tail zero).
-hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const int32_t *A, uint64_t *out, uint64_t off0,
-                         uint64_t m, hipStream_t s);
+// P3: inverse column NTT of job.A, parity of convolution positions
+// [off0, off0+m), packed into job.out (ceil(m/64) words, tail zero).
+hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const JobArgs &ja, int njobs, hipStream_t s);
 
 }  // namespace pa

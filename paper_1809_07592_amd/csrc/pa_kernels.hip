@@ -73,19 +73,31 @@ __device__ __forceinline__ void st64(rsrc_t r, int byte_off, uint64_t v) {
     __builtin_amdgcn_raw_buffer_store_b32((unsigned)(v >> 32), r, byte_off + 4, 0, 0);
 }
 
-// omega_L^e for 0 <= e < L from the two-level table, with its quotient.
-__device__ __forceinline__ double2 twist_factor(const LenPlan &lp, uint32_t e) {
-    const double2 lo = lp.twist_lo[e & 4095u];
-    const double2 hi = lp.twist_hi[e >> 12];
-    const double w = mulmod(hi.x, lo.x, lo.y);
-    return make_double2(w, w * kPinv);
-}
 __device__ __forceinline__ double2 ld_tw(rsrc_t r, int index) {
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, index * 16, 0, 0);
     double2 d;
     __builtin_memcpy(&d, &v, sizeof(d));
     return d;
+}
+
+// Wave-uniform copies (SGPRs) of values the compiler cannot prove uniform;
+// buffer resources built from them need no waterfall loop.
+template <class T>
+__device__ __forceinline__ T *uni(T *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T *)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// omega_L^e for 0 <= e < L from the two-level table, with its quotient.
+__device__ __forceinline__ double2 twist_factor(rsrc_t lo_t, rsrc_t hi_t, uint32_t e) {
+    const double2 lo = ld_tw(lo_t, (int)(e & 4095u));
+    const double2 hi = ld_tw(hi_t, (int)(e >> 12));
+    const double w = mulmod(hi.x, lo.x, lo.y);
+    return make_double2(w, w * kPinv);
 }
 
 // ------------------------------------------------------------ round shapes
@@ -189,7 +201,7 @@ __device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, 
 template <int N3, int N2, int K>
 __device__ __forceinline__ void fwd_stages(RegArr<N3, N2> &v, int b, const XDesc &xd, int s0) {
     if constexpr (K < Shape<N3, N2>::Q) {
-        fwd_stage<N3, N2, K>(v, b, make_rsrc(xd.fwd_tw, 0x7fffffff), xd.fwd_off[s0 + K]);
+        fwd_stage<N3, N2, K>(v, b, make_rsrc(uni(xd.fwd_tw), 0x7fffffff), xd.fwd_off[s0 + K]);
         // keep the next stage's twiddle loads from being hoisted above this
         // stage (otherwise all of a round's twiddles are live at once)
         __builtin_amdgcn_sched_barrier(0);
@@ -201,7 +213,7 @@ template <int N3, int N2, int K>
 __device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast, const XDesc &xd,
                                            int s0) {
     if constexpr (K >= 0) {
-        inv_stage<N3, N2, K>(v, jj, jlast, make_rsrc(xd.inv_tw, 0x7fffffff), xd.inv_off[s0 + K]);
+        inv_stage<N3, N2, K>(v, jj, jlast, make_rsrc(uni(xd.inv_tw), 0x7fffffff), xd.inv_off[s0 + K]);
         __builtin_amdgcn_sched_barrier(0);
         inv_stages<N3, N2, K - 1>(v, jj, jlast, xd, s0);
     }
@@ -297,35 +309,49 @@ struct NoCtx {};
 extern __shared__ int pa_lds[];
 
 // P1: forward column NTT of one W-column tile of a bit string.  Transform
-// input position p = q*C + c0 + c holds bit p - shift of `bits` when that
-// index lies in [0, nbits), else 0.  blockIdx.y selects one of two sources
-// (key and seed of the plain path run in one launch).
-struct P1Arg {
-    const uint64_t *bits[2];
-    uint64_t nbits[2];
-    int64_t shift[2];
-    int32_t *out[2];
-};
-
+// input position p = q*C + c0 + c holds bit p - shift of the source when
+// that index lies in [0, nbits), else 0.  blockIdx.y selects the source
+// (0: job.key shifted by job.shift into job.A; 1: job.seed into job.S) and
+// blockIdx.z the job.
 #define PA_INLINE __attribute__((always_inline))
 
-__global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan, P1Arg a) {
+// The job's descriptor (every field wave-uniform).
+__device__ __forceinline__ JobDesc job_of(const JobArgs &ja, unsigned idx) {
+    JobDesc j = ja.table ? ja.table[idx] : ja.one;
+    j.key = uni(j.key);
+    j.seed = uni(j.seed);
+    j.out = uni(j.out);
+    j.A = uni(j.A);
+    j.S = uni(j.S);
+    j.Shat = uni(j.Shat);
+    j.n = uni(j.n);
+    j.seed_bits = uni(j.seed_bits);
+    j.m = uni(j.m);
+    j.off0 = uni(j.off0);
+    j.shift = uni(j.shift);
+    return j;
+}
+
+__global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan, JobArgs ja) {
     const LenPlan &lp = *plan;
     const XDesc &xd = lp.col;
-    const int src = blockIdx.y;
-    const int nbits = (int)a.nbits[src];
-    const int shift = (int)a.shift[src];
-    const rsrc_t bits = make_rsrc(a.bits[src], (uint32_t)((a.nbits[src] + 31) / 32 * 4));
-    const rsrc_t out = make_rsrc(a.out[src], (uint32_t)(lp.L * 4));
+    const JobDesc job = job_of(ja, blockIdx.z);
+    const bool src = blockIdx.y != 0;
+    const int nbits = (int)(src ? job.seed_bits : job.n);
+    const int shift = src ? 0 : (int)job.shift;
+    const rsrc_t bits = make_rsrc(src ? job.seed : job.key, (uint32_t)(((uint32_t)nbits + 31) / 32 * 4));
+    const rsrc_t out = make_rsrc(src ? job.S : job.A, (uint32_t)(lp.L * 4));
     const int W = lp.W, wsh = __builtin_ctz((unsigned)W), C = lp.C;
     const int c0 = blockIdx.x * W;
     int *lds = pa_lds;
     auto pre = [&](int, int, int) PA_INLINE { return NoCtx{}; };
     auto mid = [&](NoCtx, auto &, Geo) PA_INLINE {};
     auto load_bits = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double {
+        // branch-free: a negative p reads out of range (0); bits >= nbits are masked
         const int p = (g.q0 + (l << g.jl)) * C + c0 + g.c - shift;
-        if (p < 0 || p >= nbits) return 0.0;
-        return (double)(((unsigned)ld32(bits, (p >> 5) * 4) >> (p & 31)) & 1u);
+        const unsigned w = (unsigned)ld32(bits, (p >> 5) * 4);
+        const unsigned bit = (w >> (p & 31)) & ((unsigned)p < (unsigned)nbits ? 1u : 0u);
+        return (double)bit;
     };
     auto load_lds = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double {
         return (double)lds[g.lbase + l * g.lstep];
@@ -356,43 +382,40 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
 // Spectra are stored reduced (|s| <= P/2 + 4) so that a product of an
 // unreduced transform value (<= ~8 P) with them stays exact.
 //   mode 0: A <- twist^-1 . INTT_C( NTT_C(twist . A) * Shat )      (plan path)
-//   mode 1: A <- NTT_C(twist . A)                                   (seed spectrum)
+//   mode 1: S <- NTT_C(twist . S)                                   (seed spectrum)
 //   mode 2: as mode 0 with Shat = NTT_C(twist . S) computed here    (plain path)
+// blockIdx.y selects the job.
 // The inverse twist carries the 1/L of the inverse transform.  Round 0's
 // group is q = jj + l*J0 (J0 = C/rho0), twisted by beta(jj) * alpha(l).
-struct P2Arg {
-    int32_t *A;
-    const int32_t *Shat;
-    const int32_t *S;
-    int mode;
-};
-
 struct TwCtx {
     double2 beta;
 };
 
 template <int FK>
-__global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ plan, P2Arg a) {
+__global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ plan, JobArgs ja, int mode) {
     const LenPlan &lp = *plan;
     const XDesc &xd = lp.row;
+    const JobDesc job = job_of(ja, blockIdx.y);
     const int C = lp.C, nr = xd.nrounds;
     const uint32_t row = blockIdx.x;
     const uint32_t k1 = __builtin_bitreverse32(row) >> (32 - lp.log2R);
     const uint32_t L = (uint32_t)lp.L;
     const size_t rbase = (size_t)row * (size_t)C;
-    const rsrc_t rowA = make_rsrc(a.A + rbase, (uint32_t)C * 4);
-    const rsrc_t rowS = make_rsrc(a.S ? a.S + rbase : a.A, (uint32_t)C * 4);
-    const rsrc_t rowH = make_rsrc(a.Shat ? a.Shat + rbase : a.A, (uint32_t)C * 4);
+    const rsrc_t rowA = make_rsrc(job.A + rbase, (uint32_t)C * 4);
+    const rsrc_t rowS = make_rsrc(job.S + rbase, (uint32_t)C * 4);
+    const rsrc_t rowH = make_rsrc(job.Shat + rbase, (uint32_t)C * 4);
     int *lds_a = pa_lds;
     int *lds_s = pa_lds + lp.row_lds;
-    const double2 *__restrict__ af = lp.alpha_f + (size_t)k1 * lp.rho0;
-    const double2 *__restrict__ ai = lp.alpha_i + (size_t)k1 * lp.rho0;
+    const rsrc_t rs_af = make_rsrc(uni(lp.alpha_f) + (size_t)k1 * lp.rho0, (uint32_t)lp.rho0 * 16);
+    const rsrc_t rs_ai = make_rsrc(uni(lp.alpha_i) + (size_t)k1 * lp.rho0, (uint32_t)lp.rho0 * 16);
+    const rsrc_t rs_lo = make_rsrc(uni(lp.twist_lo), 4096 * 16);
+    const rsrc_t rs_hi = make_rsrc(uni(lp.twist_hi), (uint32_t)((lp.L + 4095) / 4096) * 16);
 
     auto pre_none = [&](int, int, int) PA_INLINE { return NoCtx{}; };
-    auto pre_fwd = [&](int, int, int jj) PA_INLINE { return TwCtx{twist_factor(lp, k1 * (uint32_t)jj)}; };
+    auto pre_fwd = [&](int, int, int jj) PA_INLINE { return TwCtx{twist_factor(rs_lo, rs_hi, k1 * (uint32_t)jj)}; };
     auto pre_inv = [&](int, int, int jj) PA_INLINE {
         const uint32_t e = k1 * (uint32_t)jj;
-        return TwCtx{twist_factor(lp, e == 0 ? 0u : L - e)};
+        return TwCtx{twist_factor(rs_lo, rs_hi, e == 0 ? 0u : L - e)};
     };
     auto mid_none = [&](auto, auto &, Geo) PA_INLINE {};
 
@@ -402,7 +425,7 @@ __global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ pla
         auto load_tw = [&](TwCtx t, const Geo &g, int l) PA_INLINE -> double {
             const double x = (double)ld32(src, (g.q0 + (l << g.jl)) * 4);
             const double y = mulmod(x, t.beta.x, t.beta.y);
-            const double2 al = af[l];
+            const double2 al = ld_tw(rs_af, l);
             return mulmod(y, al.x, al.y);
         };
         auto store_l = [&](auto, auto &v, Geo g) PA_INLINE {
@@ -423,16 +446,16 @@ __global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ pla
         for (int l = 0; l < group_size(v); ++l) lds_a[g.lbase + l * g.lstep] = (int)v[l];
     };
 
-    if (a.mode == 1) {
-        forward_head(rowA, lds_a);
+    if (mode == 1) {
+        forward_head(rowS, lds_a);
         auto store_g = [&](NoCtx, auto &v, Geo g) PA_INLINE {
 #pragma unroll
-            for (int l = 0; l < group_size(v); ++l) st32(rowA, (g.q0 + (l << g.jl)) * 4, (int)reduce_sym(v[l]));
+            for (int l = 0; l < group_size(v); ++l) st32(rowS, (g.q0 + (l << g.jl)) * 4, (int)reduce_sym(v[l]));
         };
         round_p2<MODE_FWD, false, true>(xd, nr - 1, 0, pre_none, load_la, mid_none, store_g);
         return;
     }
-    if (a.mode == 2) {
+    if (mode == 2) {
         forward_head(rowS, lds_s);
         auto load_ls = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double { return (double)lds_s[g.lbase + l * g.lstep]; };
         auto store_ls = [&](NoCtx, auto &v, Geo g) PA_INLINE {
@@ -444,7 +467,7 @@ __global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ pla
         // barrier at the end of the key's round 0 orders the two.
     }
     forward_head(rowA, lds_a);
-    const bool from_lds = a.mode == 2;
+    const bool from_lds = mode == 2;
     auto mid_mul = [&](NoCtx, auto &v, Geo g) PA_INLINE {
 #pragma unroll
         for (int l = 0; l < group_size(v); ++l) {
@@ -461,7 +484,7 @@ __global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ pla
     auto store_tw = [&](TwCtx t, auto &v, Geo g) PA_INLINE {
 #pragma unroll
         for (int l = 0; l < group_size(v); ++l) {
-            const double2 al = ai[l];
+            const double2 al = ld_tw(rs_ai, l);
             const double y = mulmod(v[l], al.x, al.y);
             st32(rowA, (g.q0 + (l << g.jl)) * 4, (int)mulmod(y, t.beta.x, t.beta.y));
         }
@@ -469,14 +492,18 @@ __global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ pla
     round_fk<MODE_INV, FK, false>(xd, 0, pre_inv, load_la, mid_none, store_tw);
 }
 
-// P3: inverse column NTT of one tile, then the output window.  Output bit i
-// is convolution position off0 + i (off0 = n-1 rounded up to a multiple of
-// 64, matching the key shift of P1).  Chunks of W bits are written whole
-// for i < 64*ceil(m/64); bits >= m are zero.
-__global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan, const int32_t *__restrict__ A,
-                                                uint64_t *__restrict__ out, uint64_t off0, uint64_t m) {
+// P3: inverse column NTT of one tile of job.A, then the output window.
+// Output bit i is convolution position off0 + i (off0 = n-1 rounded up to a
+// multiple of 64, matching the key shift of P1).  Chunks of W bits are
+// written whole for i < 64*ceil(m/64); bits >= m are zero.  blockIdx.y
+// selects the job.
+__global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan, JobArgs ja) {
     const LenPlan &lp = *plan;
     const XDesc &xd = lp.col;
+    const JobDesc job = job_of(ja, blockIdx.y);
+    const int32_t *A = job.A;
+    uint64_t *out = job.out;
+    const uint32_t off0 = job.off0, m = job.m;
     const int W = lp.W, wsh = __builtin_ctz((unsigned)W), C = lp.C, nr = xd.nrounds;
     const int c0 = blockIdx.x * W;
     int *lds = pa_lds;
@@ -562,37 +589,30 @@ static hipError_t set_lds_limits(int *limit) {
     return hipSuccess;
 }
 
-hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const uint64_t *const bits[2],
-                         const uint64_t nbits[2], const int64_t shift[2], int32_t *const out[2], hipStream_t s) {
+hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const JobArgs &ja, int njobs,
+                         hipStream_t s) {
     int limit = 0;
     hipError_t e = set_lds_limits(&limit);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)hp.col_lds * sizeof(int);
-    if (lds > (size_t)limit || nsrc < 1 || nsrc > 2) return hipErrorInvalidConfiguration;
-    P1Arg a{};
-    for (int i = 0; i < nsrc; ++i) {
-        a.bits[i] = bits[i];
-        a.nbits[i] = nbits[i];
-        a.shift[i] = shift[i];
-        a.out[i] = out[i];
-    }
-    hipLaunchKernelGGL(k_colfwd, dim3((unsigned)hp.ntiles, (unsigned)nsrc), dim3((unsigned)hp.col_threads), lds, s,
-                       dp, a);
+    if (lds > (size_t)limit || nsrc < 1 || nsrc > 2 || njobs < 1 || njobs > 65535) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_colfwd, dim3((unsigned)hp.ntiles, (unsigned)nsrc, (unsigned)njobs),
+                       dim3((unsigned)hp.col_threads), lds, s, dp, ja);
     return hipGetLastError();
 }
 
-hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int32_t *A, const int32_t *Shat, const int32_t *S,
-                          int mode, hipStream_t s) {
+hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int mode, const JobArgs &ja, int njobs,
+                          hipStream_t s) {
     int limit = 0;
     hipError_t e = set_lds_limits(&limit);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)hp.row_lds * sizeof(int) * (mode == 2 ? 2 : 1);
-    if (lds > (size_t)limit) return hipErrorInvalidConfiguration;
-    P2Arg a{A, Shat, S, mode};
-    const dim3 grid((unsigned)hp.R), block((unsigned)hp.row_threads);
+    if (lds > (size_t)limit || njobs < 1 || njobs > 65535 || (mode == 2 && !hp.fused_ok))
+        return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)hp.R, (unsigned)njobs), block((unsigned)hp.row_threads);
     switch (hp.row.round[0].kind) {
 #define PA_FK(K) \
-    case K: hipLaunchKernelGGL(k_rowconv<K>, grid, block, lds, s, dp, a); break;
+    case K: hipLaunchKernelGGL(k_rowconv<K>, grid, block, lds, s, dp, ja, mode); break;
         PA_FK(0) PA_FK(1) PA_FK(2) PA_FK(3) PA_FK(4) PA_FK(5) PA_FK(6) PA_FK(7) PA_FK(8) PA_FK(9) PA_FK(10)
 #undef PA_FK
         default: return hipErrorInvalidConfiguration;
@@ -600,15 +620,14 @@ hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int32_t *A, cons
     return hipGetLastError();
 }
 
-hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const int32_t *A, uint64_t *out, uint64_t off0,
-                         uint64_t m, hipStream_t s) {
+hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const JobArgs &ja, int njobs, hipStream_t s) {
     int limit = 0;
     hipError_t e = set_lds_limits(&limit);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)hp.col_lds * sizeof(int);
-    if (lds > (size_t)limit) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_colinv, dim3((unsigned)hp.ntiles), dim3((unsigned)hp.col_threads), lds, s, dp, A, out,
-                       off0, m);
+    if (lds > (size_t)limit || njobs < 1 || njobs > 65535) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_colinv, dim3((unsigned)hp.ntiles, (unsigned)njobs), dim3((unsigned)hp.col_threads), lds, s,
+                       dp, ja);
     return hipGetLastError();
 }
 

@@ -184,3 +184,45 @@ def test_stream_ordering_on_side_stream():
         out = pa.toeplitz_hash(dk, n, ds, m, stream=s)
     s.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.uint64)[: wl.words(m)], oracle.toeplitz_hash(key, n, seed, m))
+
+
+def test_batched_uneven_blocks_match_single_calls_and_oracle():
+    # log-uniform n in [2^14, 2^19], m/n in [0.05, 0.5]: many length classes
+    g = np.random.default_rng(21)
+    blocks, keys = [], []
+    for i in range(40):
+        n = int(round(2.0 ** g.uniform(14, 19)))
+        m = max(1, int(round(n * g.uniform(0.05, 0.5))))
+        key, seed = wl.key_and_seed(22, n, m, i)
+        keys.append((key, seed, n, m))
+        blocks.append((dev(key), n, dev(seed), m, torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")))
+    assert len({pa.transform_len(n, m) for _, _, n, m in keys}) >= 5
+    outs = pa.toeplitz_hash_batched(blocks)
+    order = list(range(len(blocks)))[::-1]  # permuted submission gives the same per-block results
+    outs2 = pa.toeplitz_hash_batched([(blocks[i][0], blocks[i][1], blocks[i][2], blocks[i][3],
+                                       torch.zeros_like(blocks[i][4])) for i in order])
+    for j, i in enumerate(order):
+        key, seed, n, m = keys[i]
+        want = oracle.toeplitz_hash(key, n, seed, m)
+        assert np.array_equal(host(outs[i])[: want.size], want), (i, n, m)
+        assert np.array_equal(host(outs2[j])[: want.size], want)
+        if i % 8 == 0:
+            assert np.array_equal(gpu_hash(key, n, seed, m), want)
+
+
+def test_profile_records_every_kernel():
+    n, m = 300_000, 60_000
+    key, seed = wl.key_and_seed(23, n, m, 0)
+    dk, ds = dev(key), dev(seed)
+    pa.profile_enable(True)
+    try:
+        for _ in range(3):
+            pa.toeplitz_hash(dk, n, ds, m)
+        torch.cuda.synchronize()
+        prof = pa.profile_collect()
+    finally:
+        pa.profile_enable(False)
+    assert set(prof) >= {"colfwd", "rowconv", "colinv"}
+    for st in prof.values():
+        assert st["launches"] == 3 and st["avg_ms"] > 0 and st["alg_bytes"] > 0 and st["alg_ops"] > 0
+    assert pa.profile_collect() == {}

@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (independent blocks shard by routing whole blocks to "
@@ -114,8 +116,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    pa.lib()  # fails loudly if the HIP library is missing
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        a = torch.ones(2**28, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written": b.numel() * 4}))
+        return
+    pa.lib()  # fails loudly if the HIP library is missing
     n, m = N_BITS, M_BITS
     key, seed = wl.key_and_seed(2, n, m, 0)
     dk = torch.from_numpy(key.view(np.int64)).cuda()

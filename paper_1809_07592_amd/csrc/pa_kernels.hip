@@ -315,6 +315,16 @@ extern __shared__ int pa_lds[];
 // blockIdx.z the job.
 #define PA_INLINE __attribute__((always_inline))
 
+// Column tile of this workgroup.  Workgroups are dispatched round-robin
+// over the 8 XCDs (each with its own L2); consecutive tiles share 128-byte
+// lines of every row, so tile t goes to the XCD of workgroup
+// (t % per) * 8 + t / per, putting runs of neighbouring tiles on one XCD.
+__device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
+    if (ntiles % 8) return bid;
+    const int per = ntiles >> 3;
+    return (bid & 7) * per + (bid >> 3);
+}
+
 // The job's descriptor (every field wave-uniform).
 __device__ __forceinline__ JobDesc job_of(const JobArgs &ja, unsigned idx) {
     JobDesc j = ja.table ? ja.table[idx] : ja.one;
@@ -342,7 +352,7 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
     const rsrc_t bits = make_rsrc(src ? job.seed : job.key, (uint32_t)(((uint32_t)nbits + 31) / 32 * 4));
     const rsrc_t out = make_rsrc(src ? job.S : job.A, (uint32_t)(lp.L * 4));
     const int W = lp.W, wsh = __builtin_ctz((unsigned)W), C = lp.C;
-    const int c0 = blockIdx.x * W;
+    const int c0 = xcd_tile(blockIdx.x, lp.ntiles) * W;
     int *lds = pa_lds;
     auto pre = [&](int, int, int) PA_INLINE { return NoCtx{}; };
     auto mid = [&](NoCtx, auto &, Geo) PA_INLINE {};
@@ -497,7 +507,7 @@ __global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ pla
 // multiple of 64, matching the key shift of P1).  Chunks of W bits are
 // written whole for i < 64*ceil(m/64); bits >= m are zero.  blockIdx.y
 // selects the job.
-__global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan, JobArgs ja) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_colinv(const LenPlan *__restrict__ plan, JobArgs ja) {
     const LenPlan &lp = *plan;
     const XDesc &xd = lp.col;
     const JobDesc job = job_of(ja, blockIdx.y);
@@ -505,7 +515,7 @@ __global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan
     uint64_t *out = job.out;
     const uint32_t off0 = job.off0, m = job.m;
     const int W = lp.W, wsh = __builtin_ctz((unsigned)W), C = lp.C, nr = xd.nrounds;
-    const int c0 = blockIdx.x * W;
+    const int c0 = xcd_tile(blockIdx.x, lp.ntiles) * W;
     int *lds = pa_lds;
     const rsrc_t ain = make_rsrc(A, (uint32_t)(lp.L * 4));
     const rsrc_t obuf = make_rsrc(out, (uint32_t)((m + 63) / 64 * 8));

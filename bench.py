@@ -92,6 +92,64 @@ def cpu_baseline(key, seed, n, m, budget_s=12.0):
             "sample": "%d full blocks of n=%d, m=%d (all %d outputs each), %.1f s" % (reps, n, m, m, el)}
 
 
+def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30):
+    """Open-loop Poisson serving run (see module docstring)."""
+    n_seeds, seed_bits = 16, 1 << 24
+    seeds = [torch.from_numpy(wl.random_bits(seed_bits, wl.rng(5, wl.ROLE_SEED, i)).view(np.int64)).cuda()
+             for i in range(n_seeds)]
+    pool = [torch.from_numpy(wl.random_bits(10_000_000, wl.rng(5, wl.ROLE_KEY, i)).view(np.int64)).cuda()
+            for i in range(64)]
+    reqs = wl.serving_requests(count, rate_per_s=1.0, n_seeds=n_seeds)  # unit rate: rescaled below
+    offs, tot = [], 0
+    for r in reqs:
+        offs.append(tot)
+        tot += wl.words(r.m)
+    outs = torch.zeros(tot, dtype=torch.int64, device="cuda")
+
+    def out_ptr(i):
+        return outs.data_ptr() + 8 * offs[i]
+
+    def run(srv, ids, arrivals):
+        tickets, lag = [], []
+        t0 = time.perf_counter()
+        for i, r in enumerate(reqs):
+            if arrivals is not None:
+                target = t0 + arrivals[i]
+                while time.perf_counter() < target:
+                    pass
+                lag.append(max(0.0, time.perf_counter() - target) * 1e6)
+            tickets.append(srv.submit(ids[r.seed_id], pool[i % len(pool)].data_ptr(), r.n, r.m, out_ptr(i)))
+        srv.drain()
+        el = time.perf_counter() - t0
+        lat = [srv.latency_us(t) + (lag[i] if lag else 0.0) for i, t in enumerate(tickets)]
+        return el, lat
+
+    bits = sum(r.n for r in reqs)
+    with pa.Server(budget_bytes, max_inflight=512, streams=4) as srv:
+        ids = [srv.register_seed(sd, seed_bits) for sd in seeds]
+        run(srv, ids, None)                    # warm-up: builds the resident seed spectra
+        run_sat_el, _ = run(srv, ids, None)    # saturated (all submitted at once): capacity
+        cap_gbs = bits / run_sat_el / 1e9
+        rate = load * cap_gbs * 1e9 / (bits / len(reqs))
+        arrivals = np.array([r.arrival_s for r in reqs]) / rate   # unit-rate Poisson times, rescaled
+        el, lat = run(srv, ids, arrivals)
+        st = srv.stats()
+    torch.cuda.synchronize()
+    served = outs.cpu()
+    mism = 0
+    for i, r in enumerate(reqs):
+        alone = pa.toeplitz_hash(pool[i % len(pool)], r.n, seeds[r.seed_id], r.m)
+        if not torch.equal(alone.cpu()[: wl.words(r.m)], served[offs[i]: offs[i] + wl.words(r.m)]):
+            mism += 1
+    lat = np.array(lat) / 1e3
+    return {"requests": len(reqs), "offered_load": load, "arrival_rate_per_s": rate, "value": bits / el / 1e9,
+            "unit": "Gb/s", "saturated_Gbs": cap_gbs, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()), "makespan_s": el,
+            "budget_GiB": budget_bytes / 2**30, "peak_inflight": st["peak_inflight"], "batches": st["batches"],
+            "peak_bytes_in_flight": st["peak_bytes_in_flight"], "mismatches_vs_alone": mism,
+            "latency": "completion minus scheduled Poisson arrival (open loop)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +157,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serving", type=int, default=10000, help="requests in the serving run (0: skip)")
+    ap.add_argument("--load", type=float, default=0.7, help="offered load as a fraction of saturated capacity")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -198,6 +258,7 @@ def main():
                    "speedup_vs_plain": args.batch * n / (bms * 1e-3) / 1e9 / value}
         del blocks
 
+    serving = serving_run(pa, wl, torch, np, args.serving, args.load) if args.serving > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(key, seed, n, m)
     line = {
         "metric": METRIC, "value": value, "unit": "Gb/s", "n_gpus": 1, "steps": args.steps,
@@ -208,7 +269,7 @@ def main():
                    "transform_len": pa.transform_len(n, m)},
         "wall_s_timed_region": wall,
         "roofline": roofline, "roofline_hbm": roofline_hbm, "kernels": kernels,
-        "batched": batched, "serving": None, "cpu_baseline": cpu,
+        "batched": batched, "serving": serving, "cpu_baseline": cpu,
         "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(line))

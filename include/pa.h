@@ -168,6 +168,68 @@ typedef struct pa_kernel_stat {
 pa_status pa_profile_enable(int on);
 pa_status pa_profile_collect(pa_kernel_stat *stats, uint32_t capacity, uint32_t *count);
 
+/*
+ * Serving loop: continuous batching of privacy-amplification requests.
+ * Requests are admitted in arrival order while the server's device memory
+ * pool (its HBM budget) can hold their workspace (4 bytes per transform
+ * point) and fewer than max_inflight are running; every scheduler
+ * iteration launches all newly admitted requests as one batched pass
+ * sequence on the next of `streams` HIP streams, so requests that arrive
+ * while others run are admitted as memory frees up and their work overlaps
+ * on the device.  Seeds are registered once; the spectrum of each (seed,
+ * transform length) pair is built on first use and stays resident.  Each
+ * result is bit-identical to pa_toeplitz_hash on the same block.
+ *
+ * Pointers passed to submit are device pointers owned by the caller and
+ * must stay valid until the request completes.  executor =
+ * PA_EXEC_SIMULATED runs the scheduler without touching the device
+ * (requests complete after n / sim_bits_per_us microseconds, outputs are
+ * not written): for testing admission and bookkeeping on a host without a
+ * GPU.  Submission returns PA_ERR_BUSY if the request can never fit the
+ * budget or the queue holds max_queue requests.
+ */
+typedef struct pa_server_s *pa_server_t;
+
+enum { PA_EXEC_GPU = 0, PA_EXEC_SIMULATED = 1 };
+
+typedef struct pa_server_config {
+    uint64_t hbm_budget_bytes;  /* device workspace pool */
+    uint32_t max_inflight;      /* requests running at once */
+    uint32_t max_queue;         /* pending requests accepted */
+    uint32_t streams;           /* HIP streams batches rotate over */
+    uint32_t executor;          /* PA_EXEC_GPU or PA_EXEC_SIMULATED */
+    double sim_bits_per_us;     /* simulated executor speed */
+} pa_server_config;
+
+typedef struct pa_server_stats {
+    uint64_t submitted, completed, rejected, batches;
+    uint64_t bytes_in_flight, peak_bytes_in_flight, budget_bytes;
+    uint64_t inflight, peak_inflight, pending;
+    uint64_t input_bits_completed;
+} pa_server_stats;
+
+pa_status pa_server_create(const pa_server_config *cfg, pa_server_t *server);
+/* Registers seed bits (device pointer, kept by the caller until the server
+ * is destroyed); returns its id. */
+pa_status pa_server_register_seed(pa_server_t server, const uint64_t *seed_bits, uint64_t seed_len_bits,
+                                  uint32_t *seed_id);
+/* Queues y = T x mod 2 with the Toeplitz matrix of seed `seed_id` (its
+ * first n+m-1 bits).  *ticket identifies the request. */
+pa_status pa_server_submit(pa_server_t server, uint32_t seed_id, const uint64_t *key_bits, uint64_t n, uint64_t m,
+                           uint64_t *out_bits, uint64_t *ticket);
+/* *done = 1 once the request's output is written (and visible to the
+ * host-side caller's later stream work). */
+pa_status pa_server_poll(pa_server_t server, uint64_t ticket, int *done);
+/* Blocks until the request completes; *latency_us (optional) receives
+ * completion time minus submit time. */
+pa_status pa_server_wait(pa_server_t server, uint64_t ticket, double *latency_us);
+/* Blocks until every submitted request has completed. */
+pa_status pa_server_drain(pa_server_t server);
+pa_status pa_server_stats_get(pa_server_t server, pa_server_stats *stats);
+/* Completion-minus-submit latency of a completed request, microseconds. */
+pa_status pa_server_latency(pa_server_t server, uint64_t ticket, double *latency_us);
+pa_status pa_server_destroy(pa_server_t server);
+
 /* Static text for a status code. */
 const char *pa_status_string(pa_status s);
 

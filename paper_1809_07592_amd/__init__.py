@@ -55,6 +55,18 @@ class KernelStat(ctypes.Structure):
                 ("alg_bytes", ctypes.c_double), ("alg_ops", ctypes.c_double)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
+                ("max_queue", ctypes.c_uint32), ("streams", ctypes.c_uint32), ("executor", ctypes.c_uint32),
+                ("sim_bits_per_us", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in (
+        "submitted", "completed", "rejected", "batches", "bytes_in_flight", "peak_bytes_in_flight",
+        "budget_bytes", "inflight", "peak_inflight", "pending", "input_bits_completed")]
+
+
 class _Block(ctypes.Structure):
     _fields_ = [("key_bits", ctypes.c_void_p), ("n", ctypes.c_uint64), ("seed_bits", ctypes.c_void_p),
                 ("m", ctypes.c_uint64), ("out_bits", ctypes.c_void_p)]
@@ -92,6 +104,25 @@ def lib():
                 L.pa_profile_enable.restype = st
                 L.pa_profile_collect.argtypes = [ctypes.POINTER(KernelStat), u32, ctypes.POINTER(u32)]
                 L.pa_profile_collect.restype = st
+                vpp = ctypes.POINTER(vp)
+                L.pa_server_create.argtypes = [ctypes.POINTER(ServerConfig), vpp]
+                L.pa_server_create.restype = st
+                L.pa_server_register_seed.argtypes = [vp, vp, u64, ctypes.POINTER(u32)]
+                L.pa_server_register_seed.restype = st
+                L.pa_server_submit.argtypes = [vp, u32, vp, u64, u64, vp, ctypes.POINTER(u64)]
+                L.pa_server_submit.restype = st
+                L.pa_server_poll.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_int)]
+                L.pa_server_poll.restype = st
+                L.pa_server_wait.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_double)]
+                L.pa_server_wait.restype = st
+                L.pa_server_drain.argtypes = [vp]
+                L.pa_server_drain.restype = st
+                L.pa_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+                L.pa_server_stats_get.restype = st
+                L.pa_server_latency.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_double)]
+                L.pa_server_latency.restype = st
+                L.pa_server_destroy.argtypes = [vp]
+                L.pa_server_destroy.restype = st
                 L.pa_workspace_bytes.argtypes = [u64, u64]
                 L.pa_workspace_bytes.restype = ctypes.c_size_t
                 L.pa_status_string.argtypes = [st]
@@ -246,4 +277,78 @@ class Plan:
 
     def __exit__(self, *exc):
         self.destroy()
+        return False
+
+
+EXEC_GPU = 0
+EXEC_SIMULATED = 1
+
+
+class Server:
+    """Continuous-batching serving loop (pa_server_*).
+
+    Pointers are device addresses (ints) or torch CUDA tensors; the caller
+    keeps them alive until the request completes.  With
+    executor=EXEC_SIMULATED nothing touches the device.
+    """
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 256, max_queue: int = 1 << 20,
+                 streams: int = 4, executor: int = EXEC_GPU, sim_bits_per_us: float = 1e4):
+        cfg = ServerConfig(int(hbm_budget_bytes), int(max_inflight), int(max_queue), int(streams), int(executor),
+                           float(sim_bits_per_us))
+        h = ctypes.c_void_p()
+        _check(lib().pa_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def _addr(x, nwords, what):
+        if isinstance(x, int):
+            return x
+        return _ptr(x, nwords, what)
+
+    def register_seed(self, seed, seed_len_bits: int) -> int:
+        sid = ctypes.c_uint32()
+        _check(lib().pa_server_register_seed(self._h, self._addr(seed, words(seed_len_bits), "seed"),
+                                             int(seed_len_bits), ctypes.byref(sid)))
+        return sid.value
+
+    def submit(self, seed_id: int, key, n: int, m: int, out) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().pa_server_submit(self._h, int(seed_id), self._addr(key, words(n), "key"), int(n), int(m),
+                                      self._addr(out, words(m), "out"), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int()
+        _check(lib().pa_server_poll(self._h, int(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int) -> float:
+        lat = ctypes.c_double()
+        _check(lib().pa_server_wait(self._h, int(ticket), ctypes.byref(lat)))
+        return lat.value
+
+    def latency_us(self, ticket: int) -> float:
+        lat = ctypes.c_double()
+        _check(lib().pa_server_latency(self._h, int(ticket), ctypes.byref(lat)))
+        return lat.value
+
+    def drain(self):
+        _check(lib().pa_server_drain(self._h))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().pa_server_stats_get(self._h, ctypes.byref(st)))
+        return {f: int(getattr(st, f)) for f, _ in st._fields_}
+
+    def close(self):
+        if self._h:
+            _check(lib().pa_server_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
         return False

@@ -16,8 +16,10 @@
 #include "pa_internal.h"
 #include "pa_kernels.h"
 #include "pa_plan.h"
+#include "pa_runtime.h"
 
-namespace {
+namespace pa {
+namespace rt {
 
 thread_local std::string g_last_error;
 
@@ -296,7 +298,10 @@ pa_status hash_one(const uint64_t *key, uint64_t n, const uint64_t *seed, uint64
     return run_plain(p, ja, 1, words8(n) + words8(n + m - 1), words8(m), s);
 }
 
-}  // namespace
+}  // namespace rt
+}  // namespace pa
+
+using namespace pa::rt;
 
 struct pa_plan_s {
     int device = 0;

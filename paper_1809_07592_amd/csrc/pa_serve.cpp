@@ -1,0 +1,468 @@
+// Serving loop (pa_server_* in include/pa.h): continuous batching of
+// privacy-amplification requests under an HBM budget.
+//
+// One scheduler thread per server.  Each iteration it (1) retires batches
+// whose completion event has fired, returning their workspace to the pool
+// and waking waiters; (2) admits queued requests in arrival order while the
+// pool can hold their workspace and fewer than max_inflight are running;
+// (3) launches all newly admitted requests as one batched plan-path pass
+// sequence (key column pass, row convolution against the resident seed
+// spectrum, extraction; one launch per pass and transform length) on the
+// next stream.  Batches of successive iterations run on different streams,
+// so work admitted while earlier work is on the device overlaps with it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/pa.h"
+#include "pa_internal.h"
+#include "pa_plan.h"
+#include "pa_runtime.h"
+
+using namespace pa::rt;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+
+// First-fit allocator over [0, size): offsets into the device pool.
+class Pool {
+   public:
+    explicit Pool(uint64_t size) : size_(size) { free_[0] = size; }
+    bool alloc(uint64_t bytes, uint64_t *off) {
+        bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const uint64_t rest = it->second - bytes, start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                used_ += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t bytes) {
+        bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint64_t used() const { return used_; }
+    uint64_t size() const { return size_; }
+
+   private:
+    uint64_t size_, used_ = 0;
+    std::map<uint64_t, uint64_t> free_;
+};
+
+struct Req {
+    uint64_t ticket;
+    uint32_t seed;
+    const uint64_t *key;
+    uint64_t n, m, L, need, ws_off = 0;
+    uint64_t *out;
+    Clock::time_point t_submit, t_done;
+    bool done = false;
+};
+
+struct Batch {
+    std::vector<Req *> reqs;
+    hipEvent_t ev = nullptr;
+    Clock::time_point sim_done;
+};
+
+struct StreamCtx {
+    hipStream_t s = nullptr;
+    void *pinned = nullptr;       // host staging of job tables
+    pa::JobDesc *dtable = nullptr; // device job table
+    size_t cap = 0;                // entries of both
+    hipEvent_t staged = nullptr;   // after the last copy out of `pinned`
+};
+
+struct Seed {
+    const uint64_t *bits;
+    uint64_t len;
+    std::map<uint64_t, int32_t *> spectra;  // by transform length
+};
+
+}  // namespace
+
+struct pa_server_s {
+    pa_server_config cfg{};
+    bool sim = false;
+    int device = 0;
+    void *pool_base = nullptr;
+    std::unique_ptr<Pool> pool;
+    std::vector<StreamCtx> streams;
+    hipStream_t plan_stream = nullptr;
+    size_t next_stream = 0;
+    std::vector<Seed> seeds;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Req *> pending;
+    std::vector<Batch> running;
+    std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread th;
+    pa_server_stats st{};
+    std::string error;  // first scheduler failure
+
+    void loop();
+    bool retire_locked();
+    pa_status launch(std::vector<Req *> &batch_reqs, Batch *b);
+    pa_status spectrum_for(uint32_t seed, uint64_t L, int32_t **out);
+};
+
+pa_status pa_server_s::spectrum_for(uint32_t seed, uint64_t L, int32_t **out) {
+    Seed &sd = seeds[seed];
+    auto it = sd.spectra.find(L);
+    if (it != sd.spectra.end()) {
+        *out = it->second;
+        return PA_OK;
+    }
+    pa::PlanRef p{};
+    pa_status stt = plan_for(L, &p);
+    if (stt != PA_OK) return stt;
+    int32_t *S = nullptr;
+    hipError_t e = hipMalloc((void **)&S, (size_t)(4 * L));
+    if (e != hipSuccess) return from_hip(e, "spectrum allocation");
+    stt = run_seed_path(p, sd.bits, std::min(sd.len, L), S, plan_stream);
+    if (stt == PA_OK) stt = from_hip(hipStreamSynchronize(plan_stream), "spectrum build");
+    if (stt != PA_OK) {
+        (void)hipFree(S);
+        return stt;
+    }
+    sd.spectra[L] = S;
+    *out = S;
+    return PA_OK;
+}
+
+// Launches the admitted requests (already holding workspace offsets) as
+// one batch; fills b->ev.
+pa_status pa_server_s::launch(std::vector<Req *> &rs, Batch *b) {
+    StreamCtx &sc = streams[next_stream];
+    next_stream = (next_stream + 1) % streams.size();
+    std::vector<pa::JobDesc> table;
+    std::vector<std::pair<uint64_t, size_t>> groups;  // (L, count) in table order
+    std::sort(rs.begin(), rs.end(), [](const Req *a, const Req *c) { return a->L < c->L; });
+    for (Req *r : rs) {
+        int32_t *S = nullptr;
+        pa_status stt = spectrum_for(r->seed, r->L, &S);
+        if (stt != PA_OK) return stt;
+        int32_t *A = (int32_t *)((char *)pool_base + r->ws_off);
+        pa::JobDesc j = plain_job(r->key, r->n, nullptr, r->m, r->out, A, nullptr);
+        j.Shat = S;
+        table.push_back(j);
+        if (groups.empty() || groups.back().first != r->L)
+            groups.push_back({r->L, 1});
+        else
+            groups.back().second++;
+    }
+    if (table.size() > sc.cap) return fail(PA_ERR_DEVICE, "job table overflow");
+    if (sc.staged) {
+        hipError_t e = hipEventSynchronize(sc.staged);
+        if (e != hipSuccess) return from_hip(e, "staging wait");
+    }
+    memcpy(sc.pinned, table.data(), table.size() * sizeof(pa::JobDesc));
+    hipError_t e = hipMemcpyAsync(sc.dtable, sc.pinned, table.size() * sizeof(pa::JobDesc), hipMemcpyHostToDevice,
+                                  sc.s);
+    if (e == hipSuccess) e = hipEventRecord(sc.staged, sc.s);
+    if (e != hipSuccess) return from_hip(e, "job table upload");
+    size_t first = 0;
+    for (auto &g : groups) {
+        pa::PlanRef p{};
+        pa_status stt = plan_for(g.first, &p);
+        if (stt != PA_OK) return stt;
+        pa::JobArgs ja{};
+        ja.table = sc.dtable + first;
+        const int nj = (int)g.second;
+        double in_b = 0, out_b = 0;
+        for (size_t k = first; k < first + g.second; ++k) {
+            in_b += words8(table[k].n);
+            out_b += words8(table[k].m);
+        }
+        e = p1(p, 1, ja, nj, in_b, sc.s);
+        if (e == hipSuccess) e = p2(p, 0, ja, nj, sc.s);
+        if (e == hipSuccess) e = p3(p, ja, nj, out_b, sc.s);
+        if (e != hipSuccess) return from_hip(e, "batch launch");
+        first += g.second;
+    }
+    e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(b->ev, sc.s);
+    return from_hip(e, "batch event");
+}
+
+// Retires finished batches (lock held).  Returns true if any finished.
+bool pa_server_s::retire_locked() {
+    bool any = false;
+    const auto now = Clock::now();
+    for (size_t i = 0; i < running.size();) {
+        Batch &b = running[i];
+        bool fin;
+        if (sim)
+            fin = now >= b.sim_done;
+        else
+            fin = hipEventQuery(b.ev) == hipSuccess;
+        if (!fin) {
+            ++i;
+            continue;
+        }
+        const auto t = Clock::now();
+        for (Req *r : b.reqs) {
+            r->t_done = t;
+            r->done = true;
+            pool->release(r->ws_off, r->need);
+            st.completed++;
+            st.inflight--;
+            st.input_bits_completed += r->n;
+        }
+        if (b.ev) (void)hipEventDestroy(b.ev);
+        running.erase(running.begin() + (long)i);
+        any = true;
+    }
+    st.bytes_in_flight = pool->used();
+    return any;
+}
+
+void pa_server_s::loop() {
+    if (!sim) (void)hipSetDevice(device);
+    for (;;) {
+        std::vector<Req *> admitted;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            if (retire_locked()) cv_done.notify_all();
+            if (stop && pending.empty() && running.empty()) break;
+            while (!pending.empty() && st.inflight < cfg.max_inflight) {
+                Req *r = pending.front();
+                uint64_t off = 0;
+                if (!pool->alloc(r->need, &off)) break;  // arrival order: wait for memory
+                r->ws_off = off;
+                admitted.push_back(r);
+                pending.pop_front();
+                st.inflight++;
+            }
+            st.pending = pending.size();
+            st.bytes_in_flight = pool->used();
+            st.peak_bytes_in_flight = std::max(st.peak_bytes_in_flight, st.bytes_in_flight);
+            st.peak_inflight = std::max(st.peak_inflight, st.inflight);
+            if (admitted.empty()) {
+                // nothing to launch: wait for a submission, or poll running work
+                cv_work.wait_for(lk, std::chrono::microseconds(running.empty() ? 2000 : 20));
+                continue;
+            }
+        }
+        Batch b;
+        b.reqs = admitted;
+        if (sim) {
+            double us = 0;
+            for (Req *r : admitted) us += (double)r->n / std::max(cfg.sim_bits_per_us, 1e-9);
+            b.sim_done = Clock::now() + std::chrono::microseconds((int64_t)us);
+        } else {
+            pa_status stt = launch(b.reqs, &b);
+            if (stt != PA_OK) {
+                std::lock_guard<std::mutex> lk(mu);
+                if (error.empty()) error = pa_last_error();
+                // fail the batch: complete its requests (outputs unspecified)
+                for (Req *r : admitted) {
+                    r->done = true;
+                    r->t_done = Clock::now();
+                    pool->release(r->ws_off, r->need);
+                    st.inflight--;
+                }
+                cv_done.notify_all();
+                continue;
+            }
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        running.push_back(b);
+        st.batches++;
+    }
+}
+
+extern "C" {
+
+pa_status pa_server_create(const pa_server_config *cfg, pa_server_t *server) {
+    if (!cfg || !server) return fail(PA_ERR_INVALID_ARG, "null argument");
+    *server = nullptr;
+    if (cfg->hbm_budget_bytes < (1u << 20) || cfg->max_inflight == 0 || cfg->max_queue == 0 || cfg->streams == 0 ||
+        cfg->streams > 16)
+        return fail(PA_ERR_INVALID_ARG, "budget >= 1 MiB, max_inflight, max_queue >= 1, 1 <= streams <= 16");
+    if (cfg->executor != PA_EXEC_GPU && cfg->executor != PA_EXEC_SIMULATED)
+        return fail(PA_ERR_INVALID_ARG, "unknown executor");
+    std::unique_ptr<pa_server_s> s(new (std::nothrow) pa_server_s());
+    if (!s) return fail(PA_ERR_OUT_OF_MEMORY, "host allocation");
+    s->cfg = *cfg;
+    s->sim = cfg->executor == PA_EXEC_SIMULATED;
+    s->pool.reset(new Pool(cfg->hbm_budget_bytes / kAlign * kAlign));
+    s->st.budget_bytes = s->pool->size();
+    if (!s->sim) {
+        hipError_t e = hipGetDevice(&s->device);
+        if (e == hipSuccess) e = hipMalloc(&s->pool_base, (size_t)s->pool->size());
+        if (e != hipSuccess) return from_hip(e, "server pool");
+        e = hipStreamCreateWithFlags(&s->plan_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return from_hip(e, "server stream");
+        s->streams.resize(cfg->streams);
+        for (auto &sc : s->streams) {
+            sc.cap = cfg->max_inflight;
+            e = hipStreamCreateWithFlags(&sc.s, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipHostMalloc(&sc.pinned, sc.cap * sizeof(pa::JobDesc), hipHostMallocDefault);
+            if (e == hipSuccess) e = hipMalloc((void **)&sc.dtable, sc.cap * sizeof(pa::JobDesc));
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&sc.staged, hipEventDisableTiming);
+            if (e != hipSuccess) return from_hip(e, "server stream setup");
+        }
+    }
+    pa_server_s *raw = s.release();
+    raw->th = std::thread([raw] { raw->loop(); });
+    *server = raw;
+    return PA_OK;
+}
+
+pa_status pa_server_register_seed(pa_server_t s, const uint64_t *seed_bits, uint64_t seed_len_bits,
+                                  uint32_t *seed_id) {
+    if (!s || !seed_bits || !seed_id || seed_len_bits == 0) return fail(PA_ERR_INVALID_ARG, "bad seed arguments");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->seeds.push_back(Seed{seed_bits, seed_len_bits, {}});
+    *seed_id = (uint32_t)(s->seeds.size() - 1);
+    return PA_OK;
+}
+
+pa_status pa_server_submit(pa_server_t s, uint32_t seed_id, const uint64_t *key_bits, uint64_t n, uint64_t m,
+                           uint64_t *out_bits, uint64_t *ticket) {
+    if (!s || !ticket) return fail(PA_ERR_INVALID_ARG, "null argument");
+    uint64_t L = 0;
+    pa_status stt = check_block(key_bits, n, key_bits, m, out_bits, &L);
+    if (stt != PA_OK) return stt;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (seed_id >= s->seeds.size()) return fail(PA_ERR_INVALID_ARG, "unknown seed id");
+    if (n + m - 1 > s->seeds[seed_id].len) return fail(PA_ERR_INVALID_ARG, "seed shorter than n + m - 1");
+    const uint64_t need = 4 * L;
+    if ((need + kAlign - 1) / kAlign * kAlign > s->pool->size()) {
+        s->st.rejected++;
+        return fail(PA_ERR_BUSY, "request workspace exceeds the whole budget");
+    }
+    if (s->pending.size() >= s->cfg.max_queue) {
+        s->st.rejected++;
+        return fail(PA_ERR_BUSY, "queue full");
+    }
+    auto r = std::make_unique<Req>();
+    r->ticket = s->next_ticket++;
+    r->seed = seed_id;
+    r->key = key_bits;
+    r->n = n;
+    r->m = m;
+    r->out = out_bits;
+    r->L = L;
+    r->need = need;
+    r->t_submit = Clock::now();
+    *ticket = r->ticket;
+    s->pending.push_back(r.get());
+    s->reqs[r->ticket] = std::move(r);
+    s->st.submitted++;
+    s->st.pending = s->pending.size();
+    s->cv_work.notify_one();
+    return PA_OK;
+}
+
+static Req *find_req(pa_server_t s, uint64_t ticket) {
+    auto it = s->reqs.find(ticket);
+    return it == s->reqs.end() ? nullptr : it->second.get();
+}
+
+pa_status pa_server_poll(pa_server_t s, uint64_t ticket, int *done) {
+    if (!s || !done) return fail(PA_ERR_INVALID_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    Req *r = find_req(s, ticket);
+    if (!r) return fail(PA_ERR_INVALID_ARG, "unknown ticket");
+    *done = r->done ? 1 : 0;
+    return PA_OK;
+}
+
+pa_status pa_server_latency(pa_server_t s, uint64_t ticket, double *latency_us) {
+    if (!s || !latency_us) return fail(PA_ERR_INVALID_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    Req *r = find_req(s, ticket);
+    if (!r) return fail(PA_ERR_INVALID_ARG, "unknown ticket");
+    if (!r->done) return fail(PA_ERR_BUSY, "request not complete");
+    *latency_us = std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count();
+    return PA_OK;
+}
+
+pa_status pa_server_wait(pa_server_t s, uint64_t ticket, double *latency_us) {
+    if (!s) return fail(PA_ERR_INVALID_ARG, "null server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    Req *r = find_req(s, ticket);
+    if (!r) return fail(PA_ERR_INVALID_ARG, "unknown ticket");
+    s->cv_done.wait(lk, [&] { return r->done; });
+    if (latency_us) *latency_us = std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count();
+    if (!s->error.empty()) return fail(PA_ERR_DEVICE, s->error);
+    return PA_OK;
+}
+
+pa_status pa_server_drain(pa_server_t s) {
+    if (!s) return fail(PA_ERR_INVALID_ARG, "null server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return s->pending.empty() && s->running.empty() && s->st.inflight == 0; });
+    if (!s->error.empty()) return fail(PA_ERR_DEVICE, s->error);
+    return PA_OK;
+}
+
+pa_status pa_server_stats_get(pa_server_t s, pa_server_stats *out) {
+    if (!s || !out) return fail(PA_ERR_INVALID_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->st;
+    return PA_OK;
+}
+
+pa_status pa_server_destroy(pa_server_t s) {
+    if (!s) return PA_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->th.joinable()) s->th.join();
+    hipError_t err = hipSuccess;
+    if (!s->sim) {
+        for (auto &sc : s->streams) {
+            if (sc.s) (void)hipStreamSynchronize(sc.s);
+            if (sc.staged) (void)hipEventDestroy(sc.staged);
+            if (sc.dtable) (void)hipFree(sc.dtable);
+            if (sc.pinned) (void)hipHostFree(sc.pinned);
+            if (sc.s) (void)hipStreamDestroy(sc.s);
+        }
+        for (auto &sd : s->seeds)
+            for (auto &kv : sd.spectra) (void)hipFree(kv.second);
+        if (s->plan_stream) (void)hipStreamDestroy(s->plan_stream);
+        if (s->pool_base) err = hipFree(s->pool_base);
+    }
+    delete s;
+    return from_hip(err, "server teardown");
+}
+
+}  // extern "C"

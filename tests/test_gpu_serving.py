@@ -1,0 +1,57 @@
+"""Serving loop on the GPU: every served result equals the same request run
+alone (pa_toeplitz_hash), a sample matches the CPU oracle, the budget holds,
+and requests overlap on the device."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1809_07592_amd as pa
+from paper_1809_07592_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def test_served_results_equal_alone_and_oracle():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    g = np.random.default_rng(31)
+    seeds = [wl.random_bits(L, wl.rng(30, wl.ROLE_SEED, i)) for i, L in enumerate([3_000_000, 1_200_000])]
+    dseeds = [dev(s) for s in seeds]
+    reqs = []
+    for i in range(60):
+        sid = int(g.integers(0, 2))
+        n = int(round(10 ** g.uniform(4.5, 6.2)))
+        n = min(n, 700_000 if sid == 1 else 2_000_000)
+        m = max(1, min(n, int(round(n * g.uniform(0.1, 0.5)))))
+        key = wl.random_bits(n, wl.rng(30, wl.ROLE_KEY, i))
+        reqs.append((sid, key, n, m))
+    budget = 64 << 20  # a handful of requests at a time
+    with pa.Server(budget, max_inflight=16, streams=3) as srv:
+        ids = [srv.register_seed(dseeds[k], seeds[k].size * 64) for k in range(2)]
+        outs, tickets, keep = [], [], []
+        for sid, key, n, m in reqs:
+            dk = dev(key)
+            out = torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")
+            keep.append(dk)
+            outs.append(out)
+            tickets.append(srv.submit(ids[sid], dk, n, m, out))
+        srv.drain()
+        st = srv.stats()
+        assert st["completed"] == len(reqs)
+        assert st["peak_bytes_in_flight"] <= budget
+        assert st["peak_inflight"] >= 2 and st["batches"] >= 3
+        lat = [srv.latency_us(t) for t in tickets]
+        assert min(lat) > 0
+    torch.cuda.synchronize()
+    for i, ((sid, key, n, m), out) in enumerate(zip(reqs, outs)):
+        served = out.cpu().numpy().view(np.uint64)[: wl.words(m)]
+        alone = pa.toeplitz_hash(keep[i], n, dseeds[sid], m)
+        torch.cuda.synchronize()
+        assert np.array_equal(served, alone.cpu().numpy().view(np.uint64)[: wl.words(m)]), i
+        if i % 10 == 0:
+            assert np.array_equal(served, oracle.toeplitz_hash(key, n, seeds[sid], m)), i

@@ -62,6 +62,11 @@ constexpr int kNumPow2Kinds = 4;
 
 constexpr int kMaxRounds = 6;
 constexpr int kMaxStages = 24;
+// Most radix-2 stages in one register round: column transforms hold up to
+// 16 values per thread, row transforms (which also carry the twist and the
+// spectrum) up to 8.
+constexpr int kColMaxLg = 4;
+constexpr int kRowMaxLg = 3;
 
 struct RoundDesc {
     int kind;        // index into kKind*

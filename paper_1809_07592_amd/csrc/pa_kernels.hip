@@ -129,14 +129,14 @@ using RegArr = double[(N3 == 0 ? 1 : N3 == 1 ? 3 : N3 == 2 ? 9 : 27) << N2];
 // Forward Cooley-Tukey stage K of a round: block index b_full = b*before+sb,
 // input u multiplied by gamma^u (table entry), then r-point DFT.
 template <int N3, int N2, int K>
-__device__ __forceinline__ void fwd_stage(RegArr<N3, N2> &v, int b, rsrc_t tw, int off) {
+__device__ __forceinline__ void fwd_stage(RegArr<N3, N2> &v, int b, const double2 *__restrict__ tw, int off) {
     using S = Shape<N3, N2>;
     constexpr int r = S::radix(K), rb = S::before(K), ra = S::after(K);
 #pragma unroll
     for (int sb = 0; sb < rb; ++sb) {
         const int t = off + (b * rb + sb) * (r - 1);
         if constexpr (r == 2) {
-            const double2 w = ld_tw(tw, t);
+            const double2 w = tw[t];
 #pragma unroll
             for (int x = 0; x < ra; ++x) {
                 const int i0 = sb * 2 * ra + x, i1 = i0 + ra;
@@ -146,7 +146,7 @@ __device__ __forceinline__ void fwd_stage(RegArr<N3, N2> &v, int b, rsrc_t tw, i
                 v[i1] = a - mm;
             }
         } else {
-            const double2 w1 = ld_tw(tw, t), w2 = ld_tw(tw, t + 1);
+            const double2 w1 = tw[t], w2 = tw[t + 1];
 #pragma unroll
             for (int x = 0; x < ra; ++x) {
                 const int i0 = sb * 3 * ra + x, i1 = i0 + ra, i2 = i1 + ra;
@@ -165,14 +165,15 @@ __device__ __forceinline__ void fwd_stage(RegArr<N3, N2> &v, int b, rsrc_t tw, i
 // Inverse (decimation in time) stage K of a round: input i of the r-point
 // inverse DFT multiplied by omega_M^(-j' i), j' = x*J_last + jj.
 template <int N3, int N2, int K>
-__device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, rsrc_t tw, int off) {
+__device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, const double2 *__restrict__ tw,
+                                          int off) {
     using S = Shape<N3, N2>;
     constexpr int r = S::radix(K), rb = S::before(K), ra = S::after(K);
 #pragma unroll
     for (int x = 0; x < ra; ++x) {
         const int t = off + (x * jlast + jj) * (r - 1);
         if constexpr (r == 2) {
-            const double2 w = ld_tw(tw, t);
+            const double2 w = tw[t];
 #pragma unroll
             for (int sb = 0; sb < rb; ++sb) {
                 const int i0 = sb * 2 * ra + x, i1 = i0 + ra;
@@ -182,7 +183,7 @@ __device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, 
                 v[i1] = a - mm;
             }
         } else {
-            const double2 w1 = ld_tw(tw, t), w2 = ld_tw(tw, t + 1);
+            const double2 w1 = tw[t], w2 = tw[t + 1];
 #pragma unroll
             for (int sb = 0; sb < rb; ++sb) {
                 const int i0 = sb * 3 * ra + x, i1 = i0 + ra, i2 = i1 + ra;
@@ -199,23 +200,24 @@ __device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, 
 }
 
 template <int N3, int N2, int K>
-__device__ __forceinline__ void fwd_stages(RegArr<N3, N2> &v, int b, const XDesc &xd, int s0) {
+__device__ __forceinline__ void fwd_stages(RegArr<N3, N2> &v, int b, const XDesc &xd, const double2 *__restrict__ tw,
+                                           int s0) {
     if constexpr (K < Shape<N3, N2>::Q) {
-        fwd_stage<N3, N2, K>(v, b, make_rsrc(uni(xd.fwd_tw), 0x7fffffff), xd.fwd_off[s0 + K]);
+        fwd_stage<N3, N2, K>(v, b, tw, xd.fwd_off[s0 + K]);
         // keep the next stage's twiddle loads from being hoisted above this
         // stage (otherwise all of a round's twiddles are live at once)
         __builtin_amdgcn_sched_barrier(0);
-        fwd_stages<N3, N2, K + 1>(v, b, xd, s0);
+        fwd_stages<N3, N2, K + 1>(v, b, xd, tw, s0);
     }
 }
 
 template <int N3, int N2, int K>
 __device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast, const XDesc &xd,
-                                           int s0) {
+                                           const double2 *__restrict__ tw, int s0) {
     if constexpr (K >= 0) {
-        inv_stage<N3, N2, K>(v, jj, jlast, make_rsrc(uni(xd.inv_tw), 0x7fffffff), xd.inv_off[s0 + K]);
+        inv_stage<N3, N2, K>(v, jj, jlast, tw, xd.inv_off[s0 + K]);
         __builtin_amdgcn_sched_barrier(0);
-        inv_stages<N3, N2, K - 1>(v, jj, jlast, xd, s0);
+        inv_stages<N3, N2, K - 1>(v, jj, jlast, xd, tw, s0);
     }
 }
 
@@ -248,8 +250,9 @@ __device__ __forceinline__ Geo launder(Geo g) {
 }
 
 template <int MODE, int N3, int N2, bool FIRST, bool LAST, class Pre, class Load, class Mid, class Store>
-__device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, int wsh, Pre &pre, Load &load,
-                                         Mid &mid, Store &store) {
+__device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, const double2 *__restrict__ ftw,
+                                         const double2 *__restrict__ itw, int wsh, Pre &pre, Load &load, Mid &mid,
+                                         Store &store) {
     constexpr int RHO = Shape<N3, N2>::RHO;
     const int W = 1 << wsh;
     const int items = rd.ngroups << wsh;
@@ -257,6 +260,9 @@ __device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, i
     const int lgp = xd.lgpad;
     const int J = 1 << jl;
     const int lstep = LAST ? W : ((J + (J >> lgp)) << wsh);
+    // the block index b = item >> (wsh + jl) is the same on all 64 lanes of
+    // a wave when wsh + jl >= 6: its twiddles then come from scalar loads
+    const bool b_uniform = FIRST || (wsh + jl >= 6);
     for (int item = threadIdx.x; item < items; item += blockDim.x) {
         const int c = item & (W - 1);
         const int g = item >> wsh;
@@ -268,32 +274,45 @@ __device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, i
         RegArr<N3, N2> v;
 #pragma unroll
         for (int l = 0; l < RHO; ++l) v[l] = load(ctx, G, l);
-        if constexpr (MODE == MODE_FWD || MODE == MODE_CONV) fwd_stages<N3, N2, 0>(v, b, xd, rd.s0);
+        if constexpr (MODE == MODE_FWD || MODE == MODE_CONV) {
+            if (FIRST)
+                fwd_stages<N3, N2, 0>(v, 0, xd, ftw, rd.s0);
+            else if (b_uniform)
+                fwd_stages<N3, N2, 0>(v, __builtin_amdgcn_readfirstlane(b), xd, ftw, rd.s0);
+            else
+                fwd_stages<N3, N2, 0>(v, b, xd, ftw, rd.s0);
+        }
         if constexpr (MODE == MODE_CONV) mid(ctx, v, launder(G));
         if constexpr (MODE == MODE_INV || MODE == MODE_CONV)
-            inv_stages<N3, N2, Shape<N3, N2>::Q - 1>(v, jj, J, xd, rd.s0);
+            inv_stages<N3, N2, Shape<N3, N2>::Q - 1>(v, jj, J, xd, itw, rd.s0);
         store(ctx, v, launder(G));
     }
 }
 
-// Round r of a transform whose rounds are pure radix-2 (kinds 0..3).
-template <int MODE, bool FIRST, bool LAST, class Pre, class Load, class Mid, class Store>
-__device__ __forceinline__ void round_p2(const XDesc &xd, int r, int wsh, Pre &pre, Load &load, Mid &mid,
-                                         Store &store) {
+// Round r of a transform whose rounds are pure radix-2 (kinds 0..3); MAXLG
+// bounds the kinds the plan can give this pass (kColMaxLg / kRowMaxLg).
+template <int MODE, bool FIRST, bool LAST, int MAXLG, class Pre, class Load, class Mid, class Store>
+__device__ __forceinline__ void round_p2(const XDesc &xd, const double2 *__restrict__ ftw,
+                                         const double2 *__restrict__ itw, int r, int wsh, Pre &pre, Load &load,
+                                         Mid &mid, Store &store) {
     const RoundDesc &rd = xd.round[r];
     switch (rd.kind) {
-        case 0: round_io<MODE, 0, 1, FIRST, LAST>(rd, xd, wsh, pre, load, mid, store); break;
-        case 1: round_io<MODE, 0, 2, FIRST, LAST>(rd, xd, wsh, pre, load, mid, store); break;
-        case 2: round_io<MODE, 0, 3, FIRST, LAST>(rd, xd, wsh, pre, load, mid, store); break;
-        case 3: round_io<MODE, 0, 4, FIRST, LAST>(rd, xd, wsh, pre, load, mid, store); break;
+        case 0: round_io<MODE, 0, 1, FIRST, LAST>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
+        case 1: round_io<MODE, 0, 2, FIRST, LAST>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
+        case 2: round_io<MODE, 0, 3, FIRST, LAST>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
+        case 3:
+            if constexpr (MAXLG >= 4) round_io<MODE, 0, 4, FIRST, LAST>(rd, xd, ftw, itw, wsh, pre, load, mid, store);
+            break;
         default: break;
     }
 }
 
 // Round 0 of a transform whose first round has the compile-time kind FK.
 template <int MODE, int FK, bool LAST, class Pre, class Load, class Mid, class Store>
-__device__ __forceinline__ void round_fk(const XDesc &xd, int wsh, Pre &pre, Load &load, Mid &mid, Store &store) {
-    round_io<MODE, kKindN3[FK], kKindN2[FK], true, LAST>(xd.round[0], xd, wsh, pre, load, mid, store);
+__device__ __forceinline__ void round_fk(const XDesc &xd, const double2 *__restrict__ ftw,
+                                         const double2 *__restrict__ itw, int wsh, Pre &pre, Load &load, Mid &mid,
+                                         Store &store) {
+    round_io<MODE, kKindN3[FK], kKindN2[FK], true, LAST>(xd.round[0], xd, ftw, itw, wsh, pre, load, mid, store);
 }
 
 template <class V>
@@ -342,7 +361,9 @@ __device__ __forceinline__ JobDesc job_of(const JobArgs &ja, unsigned idx) {
     return j;
 }
 
-__global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan, JobArgs ja) {
+__global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan, JobArgs ja,
+                                                const double2 *__restrict__ ftw) {
+    const double2 *itw = nullptr;
     const LenPlan &lp = *plan;
     const XDesc &xd = lp.col;
     const JobDesc job = job_of(ja, blockIdx.z);
@@ -376,16 +397,16 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
     };
     const int nr = xd.nrounds;
     if (nr == 1) {
-        round_p2<MODE_FWD, true, true>(xd, 0, wsh, pre, load_bits, mid, store_glb);
+        round_p2<MODE_FWD, true, true, kColMaxLg>(xd, ftw, itw, 0, wsh, pre, load_bits, mid, store_glb);
         return;
     }
-    round_p2<MODE_FWD, true, false>(xd, 0, wsh, pre, load_bits, mid, store_lds);
+    round_p2<MODE_FWD, true, false, kColMaxLg>(xd, ftw, itw, 0, wsh, pre, load_bits, mid, store_lds);
     __syncthreads();
     for (int r = 1; r < nr - 1; ++r) {
-        round_p2<MODE_FWD, false, false>(xd, r, wsh, pre, load_lds, mid, store_lds);
+        round_p2<MODE_FWD, false, false, kColMaxLg>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
         __syncthreads();
     }
-    round_p2<MODE_FWD, false, true>(xd, nr - 1, wsh, pre, load_lds, mid, store_glb);
+    round_p2<MODE_FWD, false, true, kColMaxLg>(xd, ftw, itw, nr - 1, wsh, pre, load_lds, mid, store_glb);
 }
 
 // P2: one row (index blockIdx.x, column-spectrum index k1 = bitrev(row)).
@@ -402,7 +423,8 @@ struct TwCtx {
 };
 
 template <int FK>
-__global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ plan, JobArgs ja, int mode) {
+__global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ plan, JobArgs ja, int mode,
+                                                 const double2 *__restrict__ ftw, const double2 *__restrict__ itw) {
     const LenPlan &lp = *plan;
     const XDesc &xd = lp.row;
     const JobDesc job = job_of(ja, blockIdx.y);
@@ -443,10 +465,10 @@ __global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ pla
             for (int l = 0; l < group_size(v); ++l) lds[g.lbase + l * g.lstep] = (int)v[l];
         };
         auto load_l = [&](auto, const Geo &g, int l) PA_INLINE -> double { return (double)lds[g.lbase + l * g.lstep]; };
-        round_fk<MODE_FWD, FK, false>(xd, 0, pre_fwd, load_tw, mid_none, store_l);
+        round_fk<MODE_FWD, FK, false>(xd, ftw, itw, 0, pre_fwd, load_tw, mid_none, store_l);
         __syncthreads();
         for (int r = 1; r < nr - 1; ++r) {
-            round_p2<MODE_FWD, false, false>(xd, r, 0, pre_none, load_l, mid_none, store_l);
+            round_p2<MODE_FWD, false, false, kRowMaxLg>(xd, ftw, itw, r, 0, pre_none, load_l, mid_none, store_l);
             __syncthreads();
         }
     };
@@ -462,7 +484,7 @@ __global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ pla
 #pragma unroll
             for (int l = 0; l < group_size(v); ++l) st32(rowS, (g.q0 + (l << g.jl)) * 4, (int)reduce_sym(v[l]));
         };
-        round_p2<MODE_FWD, false, true>(xd, nr - 1, 0, pre_none, load_la, mid_none, store_g);
+        round_p2<MODE_FWD, false, true, kRowMaxLg>(xd, ftw, itw, nr - 1, 0, pre_none, load_la, mid_none, store_g);
         return;
     }
     if (mode == 2) {
@@ -472,7 +494,7 @@ __global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ pla
 #pragma unroll
             for (int l = 0; l < group_size(v); ++l) lds_s[g.lbase + l * g.lstep] = (int)reduce_sym(v[l]);
         };
-        round_p2<MODE_FWD, false, true>(xd, nr - 1, 0, pre_none, load_ls, mid_none, store_ls);
+        round_p2<MODE_FWD, false, true, kRowMaxLg>(xd, ftw, itw, nr - 1, 0, pre_none, load_ls, mid_none, store_ls);
         // the key's last forward round reads the seed spectrum from LDS; the
         // barrier at the end of the key's round 0 orders the two.
     }
@@ -485,10 +507,10 @@ __global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ pla
             v[l] = mulmod(v[l], s, s * kPinv);
         }
     };
-    round_p2<MODE_CONV, false, true>(xd, nr - 1, 0, pre_none, load_la, mid_mul, store_la);
+    round_p2<MODE_CONV, false, true, kRowMaxLg>(xd, ftw, itw, nr - 1, 0, pre_none, load_la, mid_mul, store_la);
     __syncthreads();
     for (int r = nr - 2; r >= 1; --r) {
-        round_p2<MODE_INV, false, false>(xd, r, 0, pre_none, load_la, mid_none, store_la);
+        round_p2<MODE_INV, false, false, kRowMaxLg>(xd, ftw, itw, r, 0, pre_none, load_la, mid_none, store_la);
         __syncthreads();
     }
     auto store_tw = [&](TwCtx t, auto &v, Geo g) PA_INLINE {
@@ -499,7 +521,7 @@ __global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ pla
             st32(rowA, (g.q0 + (l << g.jl)) * 4, (int)mulmod(y, t.beta.x, t.beta.y));
         }
     };
-    round_fk<MODE_INV, FK, false>(xd, 0, pre_inv, load_la, mid_none, store_tw);
+    round_fk<MODE_INV, FK, false>(xd, ftw, itw, 0, pre_inv, load_la, mid_none, store_tw);
 }
 
 // P3: inverse column NTT of one tile of job.A, then the output window.
@@ -507,7 +529,10 @@ __global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ pla
 // multiple of 64, matching the key shift of P1).  Chunks of W bits are
 // written whole for i < 64*ceil(m/64); bits >= m are zero.  blockIdx.y
 // selects the job.
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_colinv(const LenPlan *__restrict__ plan, JobArgs ja) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_colinv(const LenPlan *__restrict__ plan,
+                                                                                       JobArgs ja,
+                                                                                       const double2 *__restrict__ itw) {
+    const double2 *ftw = nullptr;
     const LenPlan &lp = *plan;
     const XDesc &xd = lp.col;
     const JobDesc job = job_of(ja, blockIdx.y);
@@ -553,16 +578,16 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
         }
     };
     if (nr == 1) {
-        round_p2<MODE_INV, true, true>(xd, 0, wsh, pre, load_glb, mid, store_bits);
+        round_p2<MODE_INV, true, true, kColMaxLg>(xd, ftw, itw, 0, wsh, pre, load_glb, mid, store_bits);
         return;
     }
-    round_p2<MODE_INV, false, true>(xd, nr - 1, wsh, pre, load_glb, mid, store_lds);
+    round_p2<MODE_INV, false, true, kColMaxLg>(xd, ftw, itw, nr - 1, wsh, pre, load_glb, mid, store_lds);
     __syncthreads();
     for (int r = nr - 2; r >= 1; --r) {
-        round_p2<MODE_INV, false, false>(xd, r, wsh, pre, load_lds, mid, store_lds);
+        round_p2<MODE_INV, false, false, kColMaxLg>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
         __syncthreads();
     }
-    round_p2<MODE_INV, true, false>(xd, 0, wsh, pre, load_lds, mid, store_bits);
+    round_p2<MODE_INV, true, false, kColMaxLg>(xd, ftw, itw, 0, wsh, pre, load_lds, mid, store_bits);
 }
 
 // ----------------------------------------------------------------- launchers
@@ -607,7 +632,7 @@ hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const J
     const size_t lds = (size_t)hp.col_lds * sizeof(int);
     if (lds > (size_t)limit || nsrc < 1 || nsrc > 2 || njobs < 1 || njobs > 65535) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_colfwd, dim3((unsigned)hp.ntiles, (unsigned)nsrc, (unsigned)njobs),
-                       dim3((unsigned)hp.col_threads), lds, s, dp, ja);
+                       dim3((unsigned)hp.col_threads), lds, s, dp, ja, hp.col.fwd_tw);
     return hipGetLastError();
 }
 
@@ -622,7 +647,7 @@ hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int mode, const 
     const dim3 grid((unsigned)hp.R, (unsigned)njobs), block((unsigned)hp.row_threads);
     switch (hp.row.round[0].kind) {
 #define PA_FK(K) \
-    case K: hipLaunchKernelGGL(k_rowconv<K>, grid, block, lds, s, dp, ja, mode); break;
+    case K: hipLaunchKernelGGL(k_rowconv<K>, grid, block, lds, s, dp, ja, mode, hp.row.fwd_tw, hp.row.inv_tw); break;
         PA_FK(0) PA_FK(1) PA_FK(2) PA_FK(3) PA_FK(4) PA_FK(5) PA_FK(6) PA_FK(7) PA_FK(8) PA_FK(9) PA_FK(10)
 #undef PA_FK
         default: return hipErrorInvalidConfiguration;
@@ -637,7 +662,7 @@ hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const JobArgs &ja
     const size_t lds = (size_t)hp.col_lds * sizeof(int);
     if (lds > (size_t)limit || njobs < 1 || njobs > 65535) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_colinv, dim3((unsigned)hp.ntiles, (unsigned)njobs), dim3((unsigned)hp.col_threads), lds, s,
-                       dp, ja);
+                       dp, ja, hp.col.inv_tw);
     return hipGetLastError();
 }
 

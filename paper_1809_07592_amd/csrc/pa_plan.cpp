@@ -97,19 +97,21 @@ static int kind_of(int n3, int n2) {
 
 // Split n3 radix-3 and n2 radix-2 stages into register rounds: all radix-3
 // stages in the first round (with at most 2, 1, 0 radix-2 stages for n3 =
-// 1, 2, 3), later rounds pure radix-2 with at most 4 stages; the fewest
-// rounds, and among those the split whose smallest round is largest (fewest
-// idle threads when a work item is one group).
-static std::vector<std::pair<int, int>> split_rounds(int n3, int n2) {
-    static const int cap1[4] = {4, 3, 1, 0};
+// 1, 2, 3 -- maxlg - 1, 1, 0 -- and at most maxlg for n3 = 0), later rounds pure radix-2 with at
+// most maxlg stages; the fewest rounds, and among those the split whose
+// smallest round is largest (fewest idle threads when a work item is one
+// group).  maxlg is 4 (16 values per thread) for the column transforms and 3
+// for the row transforms, whose kernel holds more state per thread.
+static std::vector<std::pair<int, int>> split_rounds(int n3, int n2, int maxlg) {
+    const int cap1[4] = {maxlg, maxlg - 1, 1, 0};
     const int c1 = cap1[n3];
     if (n2 <= c1 && (n3 > 0 || n2 > 0)) return {{n3, n2}};
-    const int nr = 1 + (n2 - c1 + 3) / 4;
+    const int nr = 1 + (n2 - c1 + maxlg - 1) / maxlg;
     std::vector<std::pair<int, int>> best;
     double best_min = -1;
     for (int first = (n3 == 0 ? 1 : 0); first <= c1; ++first) {
         const int rem = n2 - first, rest = nr - 1;
-        if (rem < rest || rem > 4 * rest) continue;
+        if (rem < rest || rem > maxlg * rest) continue;
         std::vector<std::pair<int, int>> cand{{n3, first}};
         for (int r = 0; r < rest; ++r) cand.push_back({0, rem / rest + (r < rem % rest ? 1 : 0)});
         double mn = 1e30;
@@ -146,7 +148,7 @@ struct XTables {
 
 // Descriptor and (optionally) twiddle tables of a length-N transform; pure
 // host code.
-static XDesc describe_xdesc(int N, XTables *tabs) {
+static XDesc describe_xdesc(int N, int maxlg, XTables *tabs) {
     XDesc x{};
     x.N = N;
     uint64_t tmp = (uint64_t)N;
@@ -158,7 +160,7 @@ static XDesc describe_xdesc(int N, XTables *tabs) {
     x.nstages = (int)radix.size();
     if (x.nstages > kMaxStages) throw std::runtime_error("too many stages");
 
-    auto rounds = split_rounds(k3, k2);
+    auto rounds = split_rounds(k3, k2, maxlg);
     if ((int)rounds.size() > kMaxRounds) throw std::runtime_error("too many rounds");
     x.nrounds = (int)rounds.size();
     int s = 0;
@@ -283,8 +285,8 @@ void plan_geometry(uint64_t L, int log2R, int Wreq, LenPlan &lp, XTables *ct, XT
     lp.R = 1 << a;
     lp.C = (int)(L >> a);
     if ((uint64_t)lp.R * (uint64_t)lp.C != L || lp.C % 64) throw std::runtime_error("bad four-step split");
-    lp.col = describe_xdesc(lp.R, ct);
-    lp.row = describe_xdesc(lp.C, rt);
+    lp.col = describe_xdesc(lp.R, kColMaxLg, ct);
+    lp.row = describe_xdesc(lp.C, kRowMaxLg, rt);
     if (lp.row.nrounds < 2) throw std::runtime_error("row transform needs at least two rounds");
     const int rho_c0 = lp.col.round[0].M >> lp.col.round[0].jl_log2;
     // Column tile width: the extraction ballots need whole waves per item

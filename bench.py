@@ -35,6 +35,10 @@ FP64_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # CUs x SIMDs x lanes x clock
 N_BITS, M_BITS = 1_000_000, 250_000
 
 
+def progress(msg: str) -> None:
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("pa_kernels.hip", "pa_internal.h"):
@@ -198,6 +202,7 @@ def main():
 
     ms, wall = time_steps(step, args.steps, args.warmup, torch)
     value = n / (ms * 1e-3) / 1e9
+    progress("plain path: %.3f ms/step, %.2f Gb/s" % (ms, value))
 
     # per-kernel timing of the same steps (separate, profiled pass)
     pa.profile_enable(True)
@@ -257,9 +262,14 @@ def main():
                    "ms_per_batch": bms, "kernels": bk,
                    "speedup_vs_plain": args.batch * n / (bms * 1e-3) / 1e9 / value}
         del blocks
+        progress("batched: %.3f ms per %d blocks, %.2f Gb/s" % (bms, args.batch, batched["value"]))
 
     serving = serving_run(pa, wl, torch, np, args.serving, args.load) if args.serving > 0 else None
+    if serving is not None:
+        progress("serving: done")
     cpu = None if args.no_cpu else cpu_baseline(key, seed, n, m)
+    if cpu is not None:
+        progress("cpu baseline: %.4g %s" % (cpu["value"], cpu["unit"]))
     line = {
         "metric": METRIC, "value": value, "unit": "Gb/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",

@@ -146,16 +146,55 @@ pa_status pa_plan_describe(uint64_t transform_len, uint32_t log2_rows, uint32_t 
 size_t pa_workspace_bytes(uint64_t n, uint64_t m);
 
 /*
- * Kernel timing (tracing).  While enabled, the library brackets every
- * kernel it launches with a pair of HIP events recorded on the launch's
- * own stream, and notes the launch's algorithmic HBM bytes (what the
+ * Geometry tuning.  The library keeps a per-process table of the (R, W)
+ * split used for each transform length L in two batch classes: class 0 is
+ * one block per launch (pa_toeplitz_hash, plans), class 1 is several blocks
+ * of one length per launch (pa_toeplitz_hash_batched groups of >= 2 blocks,
+ * the serving loop).  Any valid split gives the same bits; the choice only
+ * changes speed.  Plans and the server's resident seed spectra keep the
+ * geometry they were built with.
+ *
+ * pa_tune_set: use log2_rows / tile_width for (transform_len, batch_class)
+ *   from now on; (0, 0) restores the built-in default.  PA_ERR_INVALID_ARG
+ *   for an impossible split or class, PA_ERR_UNSUPPORTED_SIZE for a length
+ *   that is not supported.  Host only.
+ * pa_tune_get: the geometry now in effect (the default if none is set).
+ * pa_autotune: times every valid split of transform_len on `count`
+ *   synthetic blocks (n = 4m, the largest that fit L) submitted as one
+ *   launch sequence on `stream`, `reps` timed repetitions each after one
+ *   warm-up (median of HIP-event time), installs the fastest for the class
+ *   of `count` (1: class 0, else class 1) and fills *result.  Allocates and
+ *   frees its own device buffers (count * (8 L + bits) bytes; at most
+ *   16 GiB, else PA_ERR_INVALID_ARG) and synchronizes `stream`.
+ * pa_tune_save / pa_tune_load: the table as text, one "L class log2_rows
+ *   tile_width" line per entry; load validates every line before
+ *   installing any (PA_ERR_INVALID_ARG with the line number otherwise).
+ */
+typedef struct pa_tune_result {
+    uint32_t log2_rows;     /* chosen split (installed) */
+    uint32_t tile_width;
+    uint32_t candidates;    /* splits timed */
+    uint32_t count;         /* blocks per timed launch sequence */
+    double best_us;         /* median time of one launch sequence, chosen split */
+    double default_us;      /* the same for the built-in default split */
+} pa_tune_result;
+
+pa_status pa_tune_set(uint64_t transform_len, uint32_t batch_class, uint32_t log2_rows, uint32_t tile_width);
+pa_status pa_tune_get(uint64_t transform_len, uint32_t batch_class, uint32_t *log2_rows, uint32_t *tile_width);
+pa_status pa_autotune(uint64_t transform_len, uint32_t count, uint32_t reps, void *stream, pa_tune_result *result);
+pa_status pa_tune_save(const char *path);
+pa_status pa_tune_load(const char *path);
+
+/*
+ * Kernel timing (tracing).  While enabled, the library records a pair of
+ * HIP events with every kernel it launches, carrying that kernel's own
+ * start and end timestamps on the launch's stream, and notes the launch's algorithmic HBM bytes (what the
  * method must read and write: packed bits, residue arrays, spectra) and
  * algorithmic fp64 operations (butterflies, twists, products, reductions;
  * an FMA or an add counts as one operation).  pa_profile_collect waits for
  * the recorded events, aggregates them per kernel name into `stats`
  * (capacity entries; *count receives the number of kernel names) and
- * clears the record.  Timing adds one event pair per launch; leave it off
- * for throughput runs.
+ * clears the record.  Leave it off for throughput runs.
  */
 typedef struct pa_kernel_stat {
     char name[32];

@@ -67,6 +67,11 @@ class ServerStats(ctypes.Structure):
         "budget_bytes", "inflight", "peak_inflight", "pending", "input_bits_completed")]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("log2_rows", ctypes.c_uint32), ("tile_width", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
+                ("count", ctypes.c_uint32), ("best_us", ctypes.c_double), ("default_us", ctypes.c_double)]
+
+
 class _Block(ctypes.Structure):
     _fields_ = [("key_bits", ctypes.c_void_p), ("n", ctypes.c_uint64), ("seed_bits", ctypes.c_void_p),
                 ("m", ctypes.c_uint64), ("out_bits", ctypes.c_void_p)]
@@ -100,6 +105,16 @@ def lib():
                 L.pa_transform_len.restype = u64
                 L.pa_plan_describe.argtypes = [u64, u32, u32, ctypes.POINTER(PlanInfo)]
                 L.pa_plan_describe.restype = st
+                L.pa_tune_set.argtypes = [u64, u32, u32, u32]
+                L.pa_tune_set.restype = st
+                L.pa_tune_get.argtypes = [u64, u32, ctypes.POINTER(u32), ctypes.POINTER(u32)]
+                L.pa_tune_get.restype = st
+                L.pa_autotune.argtypes = [u64, u32, u32, vp, ctypes.POINTER(TuneResult)]
+                L.pa_autotune.restype = st
+                L.pa_tune_save.argtypes = [ctypes.c_char_p]
+                L.pa_tune_save.restype = st
+                L.pa_tune_load.argtypes = [ctypes.c_char_p]
+                L.pa_tune_load.restype = st
                 L.pa_profile_enable.argtypes = [ctypes.c_int]
                 L.pa_profile_enable.restype = st
                 L.pa_profile_collect.argtypes = [ctypes.POINTER(KernelStat), u32, ctypes.POINTER(u32)]
@@ -165,6 +180,36 @@ def plan_info(transform_len: int, log2_rows: int = 0, tile_width: int = 0) -> di
     info = PlanInfo()
     _check(lib().pa_plan_describe(int(transform_len), int(log2_rows), int(tile_width), ctypes.byref(info)))
     return info.as_dict()
+
+
+def tune_set(transform_len: int, batch_class: int, log2_rows: int, tile_width: int):
+    """Use this (R, W) split for the length in batch class 0 (one block per
+    launch) or 1 (several); (0, 0) restores the default."""
+    _check(lib().pa_tune_set(int(transform_len), int(batch_class), int(log2_rows), int(tile_width)))
+
+
+def tune_get(transform_len: int, batch_class: int) -> tuple:
+    """(log2_rows, tile_width) in effect for the length and class."""
+    a, w = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().pa_tune_get(int(transform_len), int(batch_class), ctypes.byref(a), ctypes.byref(w)))
+    return int(a.value), int(w.value)
+
+
+def autotune(transform_len: int, count: int = 1, reps: int = 5, stream=None) -> dict:
+    """Time every valid split of the length on `count` synthetic blocks and
+    install the fastest for that batch class."""
+    r = TuneResult()
+    _check(lib().pa_autotune(int(transform_len), int(count), int(reps), _stream_handle(stream), ctypes.byref(r)))
+    return {"log2_rows": int(r.log2_rows), "tile_width": int(r.tile_width), "candidates": int(r.candidates),
+            "count": int(r.count), "best_us": r.best_us, "default_us": r.default_us}
+
+
+def tune_save(path: str):
+    _check(lib().pa_tune_save(os.fsencode(path)))
+
+
+def tune_load(path: str):
+    _check(lib().pa_tune_load(os.fsencode(path)))
 
 
 def profile_enable(on: bool = True):

@@ -34,18 +34,6 @@ pa_status from_hip(hipError_t e, const char *what) {
     return fail(PA_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define PA_TRY(expr)                            \
-    do {                                        \
-        pa_status st_ = (expr);                 \
-        if (st_ != PA_OK) return st_;           \
-    } while (0)
-
-#define PA_HIP(expr, what)                      \
-    do {                                        \
-        hipError_t he_ = (expr);                \
-        if (he_ != hipSuccess) return from_hip(he_, what); \
-    } while (0)
-
 
 // Host-only validation of one block; returns the transform length in *L.
 pa_status check_block(const uint64_t *key, uint64_t n, const uint64_t *seed, uint64_t m, const uint64_t *out,
@@ -155,26 +143,23 @@ double xform_ops(const pa::XDesc &x) {
     return ops;
 }
 
-// Launch `fn` (returning hipError_t), timed when profiling is on.
+// Launch `fn(start, stop)` (returning hipError_t); when profiling is on,
+// start / stop are pool events that the launch records with the kernel's
+// own timestamps, else null.
 template <class F>
-hipError_t timed(const char *name, hipStream_t s, double bytes, double ops, F &&fn) {
+hipError_t timed(const char *name, double bytes, double ops, F &&fn) {
     hipEvent_t a = nullptr, b = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         if (g_prof_on) {
             a = pool_event();
             b = pool_event();
+            if (!a || !b) a = b = nullptr;
         }
     }
-    if (a && b) {
-        hipError_t e = hipEventRecord(a, s);
-        if (e != hipSuccess) return e;
-    }
-    hipError_t e = fn();
+    hipError_t e = fn(a, b);
     if (e != hipSuccess) return e;
     if (a && b) {
-        e = hipEventRecord(b, s);
-        if (e != hipSuccess) return e;
         std::lock_guard<std::mutex> lk(g_prof_mu);
         g_prof.push_back({name, a, b, bytes, ops});
     }
@@ -188,7 +173,8 @@ hipError_t p1(const pa::PlanRef &p, int nsrc, const pa::JobArgs &ja, int njobs, 
     const double L = (double)p.host->L;
     const double bytes = in_bytes + 4.0 * L * nsrc * njobs;
     const double ops = (double)nsrc * njobs * xform_ops(p.host->col) * p.host->C;
-    return timed("colfwd", s, bytes, ops, [&] { return pa::launch_colfwd(*p.host, p.dev, nsrc, ja, njobs, s); });
+    return timed("colfwd", bytes, ops,
+                 [&](hipEvent_t a, hipEvent_t b) { return pa::launch_colfwd(*p.host, p.dev, nsrc, ja, njobs, s, a, b); });
 }
 
 // P2 in the given mode (0 plan, 1 seed spectrum, 2 fused plain path).
@@ -204,8 +190,8 @@ hipError_t p2(const pa::PlanRef &p, int mode, const pa::JobArgs &ja, int njobs, 
         ops = 2.0 * xf + 12.0 * L + 4.0 * L;  // forward + inverse, two twists, product
         if (mode == 2) ops += xf + 6.0 * L + 3.0 * L;
     }
-    return timed(mode == 1 ? "rowspec" : "rowconv", s, bytes * njobs, ops * njobs,
-                 [&] { return pa::launch_rowconv(*p.host, p.dev, mode, ja, njobs, s); });
+    return timed(mode == 1 ? "rowspec" : "rowconv", bytes * njobs, ops * njobs,
+                 [&](hipEvent_t a, hipEvent_t b) { return pa::launch_rowconv(*p.host, p.dev, mode, ja, njobs, s, a, b); });
 }
 
 // P3 of njobs jobs (out_bytes: the packed outputs).
@@ -213,7 +199,8 @@ hipError_t p3(const pa::PlanRef &p, const pa::JobArgs &ja, int njobs, double out
     const double L = (double)p.host->L;
     const double bytes = 4.0 * L * njobs + out_bytes;
     const double ops = njobs * (xform_ops(p.host->col) * p.host->C + 4.0 * L);
-    return timed("colinv", s, bytes, ops, [&] { return pa::launch_colinv(*p.host, p.dev, ja, njobs, s); });
+    return timed("colinv", bytes, ops,
+                 [&](hipEvent_t a, hipEvent_t b) { return pa::launch_colinv(*p.host, p.dev, ja, njobs, s, a, b); });
 }
 
 inline uint64_t out_offset(uint64_t n) { return 64 * ((n - 1 + 63) / 64); }
@@ -251,9 +238,11 @@ pa_status run_plain(const pa::PlanRef &p, const pa::JobArgs &ja, int njobs, doub
     return PA_OK;
 }
 
-pa_status plan_for(uint64_t L, pa::PlanRef *lp) {
+pa_status plan_for(uint64_t L, int cls, pa::PlanRef *lp) {
     try {
-        *lp = pa::get_len_plan(L);
+        int a = 0, w = 0;
+        pa::tuned_geometry(L, cls, &a, &w);
+        *lp = pa::get_len_plan(L, a, w);
     } catch (const std::bad_alloc &) {
         return fail(PA_ERR_OUT_OF_MEMORY, "allocating transform tables");
     } catch (const std::exception &e) {
@@ -290,7 +279,7 @@ pa_status run_seed_path(const pa::PlanRef &p, const uint64_t *seed, uint64_t nbi
 pa_status hash_one(const uint64_t *key, uint64_t n, const uint64_t *seed, uint64_t m, uint64_t *out, uint64_t L,
                    hipStream_t s) {
     pa::PlanRef p{};
-    PA_TRY(plan_for(L, &p));
+    PA_TRY(plan_for(L, 0, &p));
     void *ws = nullptr;
     PA_TRY(get_workspace(s, (size_t)(8 * L), &ws));
     pa::JobArgs ja{};
@@ -438,7 +427,7 @@ pa_status pa_toeplitz_hash_batched(const pa_block *blocks, uint32_t count, void 
     std::vector<std::pair<uint64_t, pa::PlanRef>> plans;
     for (auto &g : groups) {
         pa::PlanRef p{};
-        PA_TRY(plan_for(g.first, &p));
+        PA_TRY(plan_for(g.first, g.second.size() > 1 ? 1 : 0, &p));
         plans.push_back({g.first, p});
     }
     // Workspace: the job table, then 8L bytes (A and S) per block.
@@ -499,7 +488,7 @@ pa_status pa_plan_create(const uint64_t *seed_bits, uint64_t seed_len_bits, uint
             return fail(PA_ERR_INVALID_ARG, "transform_len " + std::to_string(L) + " is not a supported length");
     }
     pa::PlanRef lp{};
-    PA_TRY(plan_for(L, &lp));
+    PA_TRY(plan_for(L, 0, &lp));
     pa_plan_s *p = new (std::nothrow) pa_plan_s();
     if (!p) return fail(PA_ERR_OUT_OF_MEMORY, "host allocation");
     hipError_t e = hipGetDevice(&p->device);

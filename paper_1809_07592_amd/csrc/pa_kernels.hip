@@ -20,6 +20,7 @@
 // stays in the transform's own (digit-reversed) order, so no transpose pass
 // exists; the column passes stream W-column tiles through LDS, the GPU
 // counterpart of the 32-row partitioned transpose of Sec. 3.4.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -625,19 +626,19 @@ static hipError_t set_lds_limits(int *limit) {
 }
 
 hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const JobArgs &ja, int njobs,
-                         hipStream_t s) {
+                         hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     int limit = 0;
     hipError_t e = set_lds_limits(&limit);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)hp.col_lds * sizeof(int);
     if (lds > (size_t)limit || nsrc < 1 || nsrc > 2 || njobs < 1 || njobs > 65535) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_colfwd, dim3((unsigned)hp.ntiles, (unsigned)nsrc, (unsigned)njobs),
-                       dim3((unsigned)hp.col_threads), lds, s, dp, ja, hp.col.fwd_tw);
+    hipExtLaunchKernelGGL(k_colfwd, dim3((unsigned)hp.ntiles, (unsigned)nsrc, (unsigned)njobs),
+                          dim3((unsigned)hp.col_threads), (uint32_t)lds, s, e0, e1, 0, dp, ja, hp.col.fwd_tw);
     return hipGetLastError();
 }
 
 hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int mode, const JobArgs &ja, int njobs,
-                          hipStream_t s) {
+                          hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     int limit = 0;
     hipError_t e = set_lds_limits(&limit);
     if (e != hipSuccess) return e;
@@ -647,7 +648,10 @@ hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int mode, const 
     const dim3 grid((unsigned)hp.R, (unsigned)njobs), block((unsigned)hp.row_threads);
     switch (hp.row.round[0].kind) {
 #define PA_FK(K) \
-    case K: hipLaunchKernelGGL(k_rowconv<K>, grid, block, lds, s, dp, ja, mode, hp.row.fwd_tw, hp.row.inv_tw); break;
+    case K:                                                                                              \
+        hipExtLaunchKernelGGL(k_rowconv<K>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, mode, hp.row.fwd_tw, \
+                              hp.row.inv_tw);                                                            \
+        break;
         PA_FK(0) PA_FK(1) PA_FK(2) PA_FK(3) PA_FK(4) PA_FK(5) PA_FK(6) PA_FK(7) PA_FK(8) PA_FK(9) PA_FK(10)
 #undef PA_FK
         default: return hipErrorInvalidConfiguration;
@@ -655,14 +659,15 @@ hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int mode, const 
     return hipGetLastError();
 }
 
-hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const JobArgs &ja, int njobs, hipStream_t s) {
+hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const JobArgs &ja, int njobs, hipStream_t s,
+                         hipEvent_t e0, hipEvent_t e1) {
     int limit = 0;
     hipError_t e = set_lds_limits(&limit);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)hp.col_lds * sizeof(int);
     if (lds > (size_t)limit || njobs < 1 || njobs > 65535) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_colinv, dim3((unsigned)hp.ntiles, (unsigned)njobs), dim3((unsigned)hp.col_threads), lds, s,
-                       dp, ja, hp.col.inv_tw);
+    hipExtLaunchKernelGGL(k_colinv, dim3((unsigned)hp.ntiles, (unsigned)njobs), dim3((unsigned)hp.col_threads),
+                          (uint32_t)lds, s, e0, e1, 0, dp, ja, hp.col.inv_tw);
     return hipGetLastError();
 }
 

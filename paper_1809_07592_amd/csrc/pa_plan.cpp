@@ -317,9 +317,47 @@ void plan_geometry(uint64_t L, int log2R, int Wreq, LenPlan &lp, XTables *ct, XT
     lp.rho0 = lp.row.round[0].M >> lp.row.round[0].jl_log2;
 }
 
+// ---------------------------------------------------------------- tuning
+
+static std::mutex g_tune_mu;
+static std::map<std::pair<uint64_t, int>, std::pair<int, int>> g_tuned;  // (L, class) -> (log2R, W)
+
+void tuned_geometry(uint64_t L, int cls, int *log2R, int *W) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find({L, cls});
+    *log2R = it == g_tuned.end() ? 0 : it->second.first;
+    *W = it == g_tuned.end() ? 0 : it->second.second;
+}
+
+void set_tuned_geometry(uint64_t L, int cls, int log2R, int W) {
+    if (cls != 0 && cls != 1) throw std::runtime_error("batch class must be 0 or 1");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (log2R == 0 && W == 0) {
+        g_tuned.erase({L, cls});
+        return;
+    }
+    LenPlan lp;
+    plan_geometry(L, log2R, W, lp);  // throws for an invalid geometry
+    g_tuned[{L, cls}] = {lp.log2R, lp.W};
+}
+
+std::vector<TunedEntry> tuned_entries() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::vector<TunedEntry> v;
+    for (auto &e : g_tuned) v.push_back({e.first.first, e.first.second, e.second.first, e.second.second});
+    return v;
+}
+
 PlanRef get_len_plan(uint64_t L, int log2R_override, int W_override) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) throw std::runtime_error("hipGetDevice failed");
+    {
+        // cache on the effective geometry, so an explicit default shares the entry
+        LenPlan g;
+        plan_geometry(L, log2R_override, W_override, g);
+        log2R_override = g.log2R;
+        W_override = g.W;
+    }
     const uint64_t key_len = L | ((uint64_t)log2R_override << 40) | ((uint64_t)W_override << 48);
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_plans.find({dev, key_len});

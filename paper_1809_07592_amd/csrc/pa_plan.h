@@ -39,4 +39,16 @@ struct PlanRef {
 // std::runtime_error on failure.
 PlanRef get_len_plan(uint64_t L, int log2R_override = 0, int W_override = 0);
 
+// Tuning table: the geometry used for length L in batch class cls (0: one
+// block per launch, 1: several).  (0, 0) means the built-in default.
+void tuned_geometry(uint64_t L, int cls, int *log2R, int *W);
+// Validates with plan_geometry (throws std::runtime_error if invalid);
+// (0, 0) removes the entry.
+void set_tuned_geometry(uint64_t L, int cls, int log2R, int W);
+struct TunedEntry {
+    uint64_t L;
+    int cls, log2R, W;
+};
+std::vector<TunedEntry> tuned_entries();
+
 }  // namespace pa

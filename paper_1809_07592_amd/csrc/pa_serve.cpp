@@ -103,10 +103,17 @@ struct StreamCtx {
     hipEvent_t staged = nullptr;   // after the last copy out of `pinned`
 };
 
+// A resident seed spectrum and the plan (geometry) it was built with; the
+// key passes of a request must use the same geometry.
+struct Spectrum {
+    int32_t *S = nullptr;
+    pa::PlanRef plan{};
+};
+
 struct Seed {
     const uint64_t *bits;
     uint64_t len;
-    std::map<uint64_t, int32_t *> spectra;  // by transform length
+    std::map<uint64_t, Spectrum> spectra;  // by transform length
 };
 
 }  // namespace
@@ -136,18 +143,18 @@ struct pa_server_s {
     void loop();
     bool retire_locked();
     pa_status launch(std::vector<Req *> &batch_reqs, Batch *b);
-    pa_status spectrum_for(uint32_t seed, uint64_t L, int32_t **out);
+    pa_status spectrum_for(uint32_t seed, uint64_t L, const Spectrum **out);
 };
 
-pa_status pa_server_s::spectrum_for(uint32_t seed, uint64_t L, int32_t **out) {
+pa_status pa_server_s::spectrum_for(uint32_t seed, uint64_t L, const Spectrum **out) {
     Seed &sd = seeds[seed];
     auto it = sd.spectra.find(L);
     if (it != sd.spectra.end()) {
-        *out = it->second;
+        *out = &it->second;
         return PA_OK;
     }
     pa::PlanRef p{};
-    pa_status stt = plan_for(L, &p);
+    pa_status stt = plan_for(L, 1, &p);
     if (stt != PA_OK) return stt;
     int32_t *S = nullptr;
     hipError_t e = hipMalloc((void **)&S, (size_t)(4 * L));
@@ -158,8 +165,10 @@ pa_status pa_server_s::spectrum_for(uint32_t seed, uint64_t L, int32_t **out) {
         (void)hipFree(S);
         return stt;
     }
-    sd.spectra[L] = S;
-    *out = S;
+    Spectrum &sp = sd.spectra[L];
+    sp.S = S;
+    sp.plan = p;
+    *out = &sp;
     return PA_OK;
 }
 
@@ -169,20 +178,33 @@ pa_status pa_server_s::launch(std::vector<Req *> &rs, Batch *b) {
     StreamCtx &sc = streams[next_stream];
     next_stream = (next_stream + 1) % streams.size();
     std::vector<pa::JobDesc> table;
-    std::vector<std::pair<uint64_t, size_t>> groups;  // (L, count) in table order
-    std::sort(rs.begin(), rs.end(), [](const Req *a, const Req *c) { return a->L < c->L; });
+    // one pass sequence per (length, geometry) group, in table order
+    struct Group {
+        pa::PlanRef plan;
+        size_t count;
+    };
+    std::vector<Group> groups;
+    std::vector<std::pair<Req *, const Spectrum *>> order;
     for (Req *r : rs) {
-        int32_t *S = nullptr;
-        pa_status stt = spectrum_for(r->seed, r->L, &S);
+        const Spectrum *sp = nullptr;
+        pa_status stt = spectrum_for(r->seed, r->L, &sp);
         if (stt != PA_OK) return stt;
+        order.push_back({r, sp});
+    }
+    std::sort(order.begin(), order.end(), [](const auto &a, const auto &c) {
+        if (a.first->L != c.first->L) return a.first->L < c.first->L;
+        return a.second->plan.host < c.second->plan.host;
+    });
+    for (auto &o : order) {
+        Req *r = o.first;
         int32_t *A = (int32_t *)((char *)pool_base + r->ws_off);
         pa::JobDesc j = plain_job(r->key, r->n, nullptr, r->m, r->out, A, nullptr);
-        j.Shat = S;
+        j.Shat = o.second->S;
         table.push_back(j);
-        if (groups.empty() || groups.back().first != r->L)
-            groups.push_back({r->L, 1});
+        if (groups.empty() || groups.back().plan.host != o.second->plan.host)
+            groups.push_back({o.second->plan, 1});
         else
-            groups.back().second++;
+            groups.back().count++;
     }
     if (table.size() > sc.cap) return fail(PA_ERR_DEVICE, "job table overflow");
     if (sc.staged) {
@@ -196,14 +218,12 @@ pa_status pa_server_s::launch(std::vector<Req *> &rs, Batch *b) {
     if (e != hipSuccess) return from_hip(e, "job table upload");
     size_t first = 0;
     for (auto &g : groups) {
-        pa::PlanRef p{};
-        pa_status stt = plan_for(g.first, &p);
-        if (stt != PA_OK) return stt;
+        const pa::PlanRef &p = g.plan;
         pa::JobArgs ja{};
         ja.table = sc.dtable + first;
-        const int nj = (int)g.second;
+        const int nj = (int)g.count;
         double in_b = 0, out_b = 0;
-        for (size_t k = first; k < first + g.second; ++k) {
+        for (size_t k = first; k < first + g.count; ++k) {
             in_b += words8(table[k].n);
             out_b += words8(table[k].m);
         }
@@ -211,7 +231,7 @@ pa_status pa_server_s::launch(std::vector<Req *> &rs, Batch *b) {
         if (e == hipSuccess) e = p2(p, 0, ja, nj, sc.s);
         if (e == hipSuccess) e = p3(p, ja, nj, out_b, sc.s);
         if (e != hipSuccess) return from_hip(e, "batch launch");
-        first += g.second;
+        first += g.count;
     }
     e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(b->ev, sc.s);
@@ -457,7 +477,7 @@ pa_status pa_server_destroy(pa_server_t s) {
             if (sc.s) (void)hipStreamDestroy(sc.s);
         }
         for (auto &sd : s->seeds)
-            for (auto &kv : sd.spectra) (void)hipFree(kv.second);
+            for (auto &kv : sd.spectra) (void)hipFree(kv.second.S);
         if (s->plan_stream) (void)hipStreamDestroy(s->plan_stream);
         if (s->pool_base) err = hipFree(s->pool_base);
     }

@@ -133,27 +133,49 @@ def test_product_never_touches_oracle():
                 assert "toeplitz_oracle" not in text and "liboracle" not in text, f
 
 
+def _check_geometry(d, L):
+    R, C, W = d["rows"], d["cols"], d["tile_width"]
+    assert R * C == L and C % 64 == 0 and W in (16, 32, 64) and C % W == 0
+    assert 1 <= d["col_threads"] <= 512 and d["col_threads"] % 64 == 0
+    assert 1 <= d["row_threads"] <= 512 and d["row_threads"] % 64 == 0
+    assert d["col_lds_bytes"] <= 160 * 1024 and d["row_lds_bytes"] <= 160 * 1024
+    prod = 1
+    for r in d["col_round_size"]:
+        assert r in (2, 4, 8, 16)
+        prod *= r
+    assert prod == R
+    prod = 1
+    for i, r in enumerate(d["row_round_size"]):
+        # rows: radix-2 rounds of at most 8 after a first round that takes
+        # all radix-3 stages (at most 27)
+        assert r <= 27 and (i == 0 or r in (2, 4, 8))
+        prod *= r
+    assert prod == C and d["row_rounds"] >= 2
+    # the output-packing ballots need the first column round to cover
+    # whole 64-lane waves
+    assert (R // d["col_round_size"][0]) * W % 64 == 0
+
+
 def test_every_supported_length_has_a_valid_launch_geometry(lib):
     for L in pa.supported_lengths():
-        d = pa.plan_info(L)
-        R, C, W = d["rows"], d["cols"], d["tile_width"]
-        assert R * C == L and C % 64 == 0 and W in (16, 32, 64) and C % W == 0
-        assert 1 <= d["col_threads"] <= 512 and d["col_threads"] % 64 == 0
-        assert 1 <= d["row_threads"] <= 512 and d["row_threads"] % 64 == 0
-        assert d["col_lds_bytes"] <= 160 * 1024 and d["row_lds_bytes"] <= 160 * 1024
-        prod = 1
-        for r in d["col_round_size"]:
-            assert r in (2, 4, 8, 16)
-            prod *= r
-        assert prod == R
-        prod = 1
-        for i, r in enumerate(d["row_round_size"]):
-            assert r <= 27 and (i == 0 or r in (2, 4, 8, 16))
-            prod *= r
-        assert prod == C and d["row_rounds"] >= 2
-        # the output-packing ballots need the first column round to cover
-        # whole 64-lane waves
-        assert (R // d["col_round_size"][0]) * W % 64 == 0
+        _check_geometry(pa.plan_info(L), L)
+
+
+def test_every_accepted_split_is_a_valid_launch_geometry(lib):
+    """Every (R, W) the planner accepts (what tuning may select) satisfies
+    the kernels' launch assumptions, and each length has several."""
+    for L in pa.supported_lengths():
+        accepted = 0
+        for a in range(1, 11):
+            for w in (16, 32, 64):
+                try:
+                    d = pa.plan_info(L, a, w)
+                except pa.PAError:
+                    continue
+                assert d["rows"] == 2**a and d["tile_width"] == w
+                _check_geometry(d, L)
+                accepted += 1
+        assert accepted >= 1, L
 
 
 def test_geometry_overrides(lib):

@@ -1,0 +1,121 @@
+"""Geometry tuning on the GPU: every valid R x C split of a length gives the
+same bits (the four-step split of Sec. 3.1 is a free choice), the autotuner
+installs a valid split, and plans and server spectra built before a change
+of the table keep working."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1809_07592_amd as pa
+from paper_1809_07592_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+N, M = 100_003, 25_001
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def host(t, m):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)[: wl.words(m)]
+
+
+def valid_splits(L):
+    out = []
+    for a in range(1, 11):
+        for w in (16, 32, 64):
+            try:
+                pa.plan_info(L, a, w)
+            except pa.PAError:
+                continue
+            out.append((a, w))
+    return out
+
+
+@pytest.fixture(autouse=True)
+def _gpu_and_restore():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build()
+    yield
+    L = pa.transform_len(N, M)
+    for cls in (0, 1):
+        pa.tune_set(L, cls, 0, 0)
+
+
+def test_every_split_gives_the_same_bits():
+    key, seed = wl.key_and_seed(40, N, M, 0)
+    want = oracle.toeplitz_hash(key, N, seed, M)
+    L = pa.transform_len(N, M)
+    splits = valid_splits(L)
+    assert len(splits) >= 6
+    dk, ds = dev(key), dev(seed)
+    blocks_np = [wl.key_and_seed(41, N, M, i) for i in range(3)]
+    blocks_want = [oracle.toeplitz_hash(k, N, s, M) for k, s in blocks_np]
+    bdev = [(dev(k), dev(s)) for k, s in blocks_np]
+    for a, w in splits:
+        print("split log2_rows=%d tile_width=%d" % (a, w), flush=True)
+        pa.tune_set(L, 0, a, w)
+        assert pa.tune_get(L, 0) == (a, w)
+        got = host(pa.toeplitz_hash(dk, N, ds, M), M)
+        assert np.array_equal(got, want), (a, w)
+        pa.tune_set(L, 1, a, w)
+        outs = [torch.zeros(wl.words(M), dtype=torch.int64, device="cuda") for _ in bdev]
+        pa.toeplitz_hash_batched([(k, N, s, M, o) for (k, s), o in zip(bdev, outs)])
+        for i, o in enumerate(outs):
+            assert np.array_equal(host(o, M), blocks_want[i]), (a, w, i)
+
+
+@pytest.mark.parametrize("count", [1, 4])
+def test_autotune_installs_a_valid_split(count):
+    L = pa.transform_len(N, M)
+    r = pa.autotune(L, count=count, reps=2)
+    cls = 0 if count == 1 else 1
+    assert r["candidates"] == len(valid_splits(L))
+    assert pa.tune_get(L, cls) == (r["log2_rows"], r["tile_width"])
+    assert 0 < r["best_us"] <= r["default_us"]
+    key, seed = wl.key_and_seed(42, N, M, count)
+    got = host(pa.toeplitz_hash(dev(key), N, dev(seed), M), M)
+    assert np.array_equal(got, oracle.toeplitz_hash(key, N, seed, M))
+
+
+def test_autotune_rejects_bad_arguments():
+    L = pa.transform_len(N, M)
+    for args in [(L, 0, 2), (L, 1, 0), (L + 1, 1, 2), (2**24 * 3, 4096, 1)]:
+        with pytest.raises(pa.PAError):
+            pa.autotune(*args)
+
+
+def test_plan_and_server_keep_their_geometry_across_a_table_change():
+    L = pa.transform_len(N, M)
+    splits = valid_splits(L)
+    first, second = splits[0], splits[-1]
+    seed_bits = 400_000
+    seed = wl.random_bits(seed_bits, wl.rng(43, wl.ROLE_SEED, 0))
+    ds = dev(seed)
+    keys = [wl.random_bits(N, wl.rng(43, wl.ROLE_KEY, i)) for i in range(6)]
+    dkeys = [dev(k) for k in keys]
+    want = [oracle.toeplitz_hash(k, N, seed, M) for k in keys]
+
+    pa.tune_set(L, 0, *first)
+    with pa.Plan(ds, seed_bits, transform_len=L) as plan:
+        pa.tune_set(L, 0, *second)
+        assert np.array_equal(host(plan.hash(dkeys[0], N, M), M), want[0])
+
+    pa.tune_set(L, 1, *first)
+    with pa.Server(256 << 20, max_inflight=8, streams=2) as srv:
+        sid = srv.register_seed(ds, seed_bits)
+        outs = [torch.zeros(wl.words(M), dtype=torch.int64, device="cuda") for _ in keys]
+        for i in range(3):
+            srv.submit(sid, dkeys[i], N, M, outs[i])
+        srv.drain()
+        pa.tune_set(L, 1, *second)        # the resident spectrum keeps the first split
+        for i in range(3, 6):
+            srv.submit(sid, dkeys[i], N, M, outs[i])
+        srv.drain()
+    for i in range(6):
+        assert np.array_equal(host(outs[i], M), want[i]), i

@@ -6,17 +6,27 @@ Bernoulli(0.5) key and seed bits (seeded, synthetic), plain path: each step
 is one pa_toeplitz_hash call = seed and key column transforms, the fused
 row pass (both row transforms, product, inverse), and the inverse column
 pass with parity extraction.  Inputs are resident in HBM before timing.
+The library's autotuner picks the four-step split per batch class before
+the timed regions (--no-tune keeps the defaults).
 
 Also reported on the same JSON line:
   * batched: 256 blocks of the same shape in one pa_toeplitz_hash_batched
     call (aggregate input Gb/s);
+  * batched_uneven: 256 blocks with n log-uniform in [2^18, 2^22] and
+    m/n uniform in [0.05, 0.5], own seed each, one batched call;
+  * serving: 10,000 requests (n log-uniform in [1e5, 1e7]) against 16
+    resident seeds under an open-loop Poisson arrival process, p50/p99/max
+    latency at offered loads 0.3/0.5/0.9 and the headline 0.7 of the
+    measured saturated capacity; every served result compared with the
+    same request run alone;
   * roofline of the dominant kernel, from HIP events the library records
-    around each launch on its own stream (algorithmic bytes and fp64
+    with each launch on its own stream (algorithmic bytes and fp64
     operations per launch / average duration);
   * cpu_baseline: the CPU oracle (packed AND + popcount parity) timed on
     this host's cores on full blocks of the same workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-tune]
+       [--batch B] [--serving COUNT] [--load RHO]
 """
 import argparse
 import hashlib
@@ -92,8 +102,45 @@ def cpu_baseline(key, seed, n, m, budget_s=12.0):
         el = time.perf_counter() - t0
         if el >= budget_s or reps >= 200:
             break
+    t1 = time.perf_counter()
+    oracle.toeplitz_hash(key, n, seed, m, threads=1)
+    one = time.perf_counter() - t1
     return {"value": n * reps / el / 1e9, "unit": "Gb/s", "cores": threads, "kind": "oracle",
-            "sample": "%d full blocks of n=%d, m=%d (all %d outputs each), %.1f s" % (reps, n, m, m, el)}
+            "sample": "%d full blocks of n=%d, m=%d (all %d outputs each), %.1f s" % (reps, n, m, m, el),
+            "one_thread_Gbs": n / one / 1e9, "cpu_model": cpu_model()}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def batched_uneven_run(pa, wl, torch, np, count, stream):
+    """Uneven batch: `count` blocks with n log-uniform in [2^18, 2^22] and
+    m/n uniform in [0.05, 0.5], each with its own key and seed, in one
+    pa_toeplitz_hash_batched call (the library groups them by length)."""
+    shapes = wl.batched_shapes(count, 4)
+    blocks = []
+    for i, sh in enumerate(shapes):
+        k_i, s_i = wl.key_and_seed(8, sh.n, sh.m, i)
+        blocks.append((torch.from_numpy(k_i.view(np.int64)).cuda(), sh.n, torch.from_numpy(s_i.view(np.int64)).cuda(),
+                       sh.m, torch.zeros(wl.words(sh.m), dtype=torch.int64, device="cuda")))
+
+    def step():
+        pa.toeplitz_hash_batched(blocks, stream=stream)
+
+    bms, _ = time_steps(step, 5, 2, torch)
+    bits = sum(sh.n for sh in shapes)
+    lens = sorted({pa.transform_len(sh.n, sh.m) for sh in shapes})
+    return {"value": bits / (bms * 1e-3) / 1e9, "unit": "Gb/s", "blocks": count, "ms_per_batch": bms,
+            "sum_n": bits, "distinct_lengths": len(lens), "min_len": lens[0], "max_len": lens[-1],
+            "shapes": "n = round(2^U(18,22)), m = max(1, round(n U(0.05, 0.5))), own seed per block"}
 
 
 def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30):
@@ -134,9 +181,15 @@ def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30):
         run(srv, ids, None)                    # warm-up: builds the resident seed spectra
         run_sat_el, _ = run(srv, ids, None)    # saturated (all submitted at once): capacity
         cap_gbs = bits / run_sat_el / 1e9
-        rate = load * cap_gbs * 1e9 / (bits / len(reqs))
-        arrivals = np.array([r.arrival_s for r in reqs]) / rate   # unit-rate Poisson times, rescaled
-        el, lat = run(srv, ids, arrivals)
+        unit_arrivals = np.array([r.arrival_s for r in reqs])   # unit-rate Poisson times, rescaled per load
+        sweep = []
+        for rho in [x for x in (0.3, 0.5, 0.9) if x != load] + [load]:   # headline load last
+            rate = rho * cap_gbs * 1e9 / (bits / len(reqs))
+            el, lat = run(srv, ids, unit_arrivals / rate)
+            la = np.array(lat) / 1e3
+            sweep.append({"offered_load": rho, "Gbs": bits / el / 1e9, "p50_ms": float(np.percentile(la, 50)),
+                          "p99_ms": float(np.percentile(la, 99)), "max_ms": float(la.max())})
+            progress("serving load %.1f: p50 %.3f ms p99 %.3f ms" % (rho, sweep[-1]["p50_ms"], sweep[-1]["p99_ms"]))
         st = srv.stats()
     torch.cuda.synchronize()
     served = outs.cpu()
@@ -151,7 +204,7 @@ def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30):
             "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()), "makespan_s": el,
             "budget_GiB": budget_bytes / 2**30, "peak_inflight": st["peak_inflight"], "batches": st["batches"],
             "peak_bytes_in_flight": st["peak_bytes_in_flight"], "mismatches_vs_alone": mism,
-            "latency": "completion minus scheduled Poisson arrival (open loop)"}
+            "load_sweep": sweep, "latency": "completion minus scheduled Poisson arrival (open loop)"}
 
 
 def main():
@@ -161,6 +214,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in default splits")
     ap.add_argument("--serving", type=int, default=10000, help="requests in the serving run (0: skip)")
     ap.add_argument("--load", type=float, default=0.7, help="offered load as a fraction of saturated capacity")
     ap.add_argument("--copy-probe", action="store_true",
@@ -200,6 +254,14 @@ def main():
     def step():
         pa.toeplitz_hash(dk, n, ds, m, out, stream=stream)
 
+    L = pa.transform_len(n, m)
+    tuning = {"transform_len": L}
+    if not args.no_tune:
+        # the library's autotuner picks the (R, W) split per batch class; untimed
+        tuning["plain"] = pa.autotune(L, count=1, reps=20, stream=stream)
+        progress("autotune plain: log2_rows=%d tile_width=%d" % (tuning["plain"]["log2_rows"],
+                                                                  tuning["plain"]["tile_width"]))
+    tuning["plain_geometry"] = pa.plan_info(L, *pa.tune_get(L, 0))
     ms, wall = time_steps(step, args.steps, args.warmup, torch)
     value = n / (ms * 1e-3) / 1e9
     progress("plain path: %.3f ms/step, %.2f Gb/s" % (ms, value))
@@ -245,6 +307,12 @@ def main():
         def bstep():
             pa.toeplitz_hash_batched(blocks, stream=stream)
 
+        if not args.no_tune:
+            tuning["batched"] = pa.autotune(L, count=args.batch, reps=3, stream=stream)
+            progress("autotune batched: log2_rows=%d tile_width=%d" % (tuning["batched"]["log2_rows"],
+                                                                        tuning["batched"]["tile_width"]))
+
+        tuning["batched_geometry"] = pa.plan_info(L, *pa.tune_get(L, 1))
         bsteps = max(3, args.steps // 40)
         bms, _ = time_steps(bstep, bsteps, 2, torch)
         pa.profile_enable(True)
@@ -264,6 +332,10 @@ def main():
         del blocks
         progress("batched: %.3f ms per %d blocks, %.2f Gb/s" % (bms, args.batch, batched["value"]))
 
+    uneven = batched_uneven_run(pa, wl, torch, np, args.batch, stream) if args.batch > 0 else None
+    if uneven is not None:
+        progress("batched uneven: %.3f ms per %d blocks, %.2f Gb/s" % (uneven["ms_per_batch"], args.batch,
+                                                                       uneven["value"]))
     serving = serving_run(pa, wl, torch, np, args.serving, args.load) if args.serving > 0 else None
     if serving is not None:
         progress("serving: done")
@@ -279,7 +351,7 @@ def main():
                    "transform_len": pa.transform_len(n, m)},
         "wall_s_timed_region": wall,
         "roofline": roofline, "roofline_hbm": roofline_hbm, "kernels": kernels,
-        "batched": batched, "serving": serving, "cpu_baseline": cpu,
+        "batched": batched, "batched_uneven": uneven, "serving": serving, "tuning": tuning, "cpu_baseline": cpu,
         "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(line))

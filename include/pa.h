@@ -163,7 +163,8 @@ size_t pa_workspace_bytes(uint64_t n, uint64_t m);
  *   synthetic blocks (n = 4m, the largest that fit L) submitted as one
  *   launch sequence on `stream`, `reps` timed repetitions each after one
  *   warm-up (median of HIP-event time), installs the fastest for the class
- *   of `count` (1: class 0, else class 1) and fills *result.  Allocates and
+ *   of `count` (1: class 0, else class 1) -- the default unless another
+ *   split is at least 2% faster -- and fills *result.  Allocates and
  *   frees its own device buffers (count * (8 L + bits) bytes; at most
  *   16 GiB, else PA_ERR_INVALID_ARG) and synchronizes `stream`.
  * pa_tune_save / pa_tune_load: the table as text, one "L class log2_rows

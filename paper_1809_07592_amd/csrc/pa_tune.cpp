@@ -20,6 +20,9 @@ using namespace pa::rt;
 
 namespace {
 
+// A split replaces the default only if it is at least 2% faster.
+constexpr double kKeepDefault = 0.98;
+
 // Maps host-side geometry errors to statuses.
 pa_status check_geometry(uint64_t L, uint32_t cls, uint32_t a, uint32_t w) {
     if (cls > 1) return fail(PA_ERR_INVALID_ARG, "batch_class must be 0 or 1");
@@ -209,6 +212,13 @@ pa_status pa_autotune(uint64_t transform_len, uint32_t count, uint32_t reps, voi
             }
         }
     if (r.candidates == 0) return fail(PA_ERR_UNSUPPORTED_SIZE, "no valid split");
+    // keep the default unless a split beats it clearly (timing noise would
+    // otherwise flip between near-equal splits from run to run)
+    if (r.default_us > 0 && r.best_us > kKeepDefault * r.default_us) {
+        r.best_us = r.default_us;
+        r.log2_rows = (uint32_t)def.log2R;
+        r.tile_width = (uint32_t)def.W;
+    }
     pa::set_tuned_geometry(L, count > 1 ? 1 : 0, (int)r.log2_rows, (int)r.tile_width);
     *result = r;
     return PA_OK;

@@ -86,6 +86,32 @@ pa_status pa_toeplitz_hash_batched(const pa_block *blocks, uint32_t count,
                                    void *stream);
 
 /*
+ * Modified Toeplitz hash (Sec. 2.2, Eq. 2-3): S = (I, V) with V the
+ * m x (n-m) Toeplitz matrix of the n-1 bits v, V[i][j] = v[i - j + (n-m) - 1],
+ * so y = x[0:m] XOR V x[m:n].  The Toeplitz part is the plain hash of the key
+ * suffix x[m:n] (n-m bits) with the n-1 seed bits v, computed by the same
+ * passes (transform length of an (n-m)-bit key with m outputs, about n
+ * instead of n+m), with the XOR applied where P3 packs the output.
+ * key_bits: n bits; v_bits: n-1 bits (device, ceil((n-1)/64) words);
+ * out_bits: m bits, tail zero.  Requires 1 <= m < n (V needs a column);
+ * otherwise PA_ERR_INVALID_ARG.  Conventions as for pa_toeplitz_hash.
+ * The batched form takes pa_block descriptors whose seed_bits field holds v.
+ */
+pa_status pa_modified_toeplitz_hash(const uint64_t *key_bits, uint64_t n,
+                                    const uint64_t *v_bits, uint64_t m,
+                                    uint64_t *out_bits, void *stream);
+pa_status pa_modified_toeplitz_hash_batched(const pa_block *blocks, uint32_t count,
+                                            void *stream);
+
+/*
+ * Final key length for privacy amplification (Sec. 2.1, Eq. 1): with n
+ * sifted bits of which Eve may know t, and a security parameter s (her
+ * information about the output is at most 2^-s / ln 2), the output length
+ * is r = n - t - s; 0 when t + s >= n.  Pure host function.
+ */
+uint64_t pa_final_key_length(uint64_t n, uint64_t t, uint64_t s);
+
+/*
  * Seed plans: the transformed seed (spectrum of the seed prefix, scaled by
  * the inverse length) kept resident in HBM so repeated hashes with one
  * seed skip the seed transform.  A plan built from seed_len_bits bits with

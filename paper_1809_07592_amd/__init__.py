@@ -105,6 +105,12 @@ def lib():
                 L.pa_transform_len.restype = u64
                 L.pa_plan_describe.argtypes = [u64, u32, u32, ctypes.POINTER(PlanInfo)]
                 L.pa_plan_describe.restype = st
+                L.pa_modified_toeplitz_hash.argtypes = [vp, u64, vp, u64, vp, vp]
+                L.pa_modified_toeplitz_hash.restype = st
+                L.pa_modified_toeplitz_hash_batched.argtypes = [ctypes.POINTER(_Block), u32, vp]
+                L.pa_modified_toeplitz_hash_batched.restype = st
+                L.pa_final_key_length.argtypes = [u64, u64, u64]
+                L.pa_final_key_length.restype = u64
                 L.pa_tune_set.argtypes = [u64, u32, u32, u32]
                 L.pa_tune_set.restype = st
                 L.pa_tune_get.argtypes = [u64, u32, ctypes.POINTER(u32), ctypes.POINTER(u32)]
@@ -288,6 +294,31 @@ def toeplitz_hash_batched(blocks, stream=None):
                         _ptr(out, words(m), "out"))
     _check(lib().pa_toeplitz_hash_batched(arr, len(blocks), _stream_handle(stream)))
     return [b[4] for b in blocks]
+
+
+def modified_toeplitz_hash(key, n: int, v, m: int, out=None, stream=None):
+    """y = x[0:m] ^ V x[m:n] (V: m x (n-m) Toeplitz of the n-1 bits v); returns out."""
+    import torch
+    if out is None:
+        out = torch.empty(max(words(m), 1), dtype=torch.int64, device=key.device)
+    _check(lib().pa_modified_toeplitz_hash(_ptr(key, words(n), "key"), int(n), _ptr(v, words(n - 1), "v"),
+                                           int(m), _ptr(out, words(m), "out"), _stream_handle(stream)))
+    return out
+
+
+def modified_toeplitz_hash_batched(blocks, stream=None):
+    """blocks: sequence of (key, n, v, m, out) tuples (v: n-1 bits); returns the outs."""
+    arr = (_Block * max(len(blocks), 1))()
+    for i, (key, n, v, m, out) in enumerate(blocks):
+        arr[i] = _Block(_ptr(key, words(n), "key"), int(n), _ptr(v, words(n - 1), "v"), int(m),
+                        _ptr(out, words(m), "out"))
+    _check(lib().pa_modified_toeplitz_hash_batched(arr, len(blocks), _stream_handle(stream)))
+    return [b[4] for b in blocks]
+
+
+def final_key_length(n: int, t: int, s: int) -> int:
+    """Output length r = n - t - s of the hash (0 if t + s >= n)."""
+    return int(lib().pa_final_key_length(int(n), int(t), int(s)))
 
 
 class Plan:

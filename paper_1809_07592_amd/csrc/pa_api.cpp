@@ -51,12 +51,39 @@ pa_status check_block(const uint64_t *key, uint64_t n, const uint64_t *seed, uin
     return PA_OK;
 }
 
+// Host-only validation of one modified-Toeplitz block (Sec. 2.2, Eq. 3):
+// y = x[0:m] ^ V x[m:n] with V the m x (n-m) Toeplitz matrix of the n-1
+// bits v.  The Toeplitz part is the plain hash of the key suffix, so *L is
+// the transform length of an (n-m)-bit key with m outputs.
+pa_status check_modified(const uint64_t *key, uint64_t n, const uint64_t *v, uint64_t m, const uint64_t *out,
+                         uint64_t *L) {
+    if (!key || !v || !out) return fail(PA_ERR_INVALID_ARG, "null bit pointer");
+    if (m == 0 || m >= n) return fail(PA_ERR_INVALID_ARG, "modified Toeplitz needs 1 <= m < n");
+    if (n > pa::kMaxLen) return fail(PA_ERR_UNSUPPORTED_SIZE, "n exceeds the largest transform length");
+    const uint64_t need = pa::required_len(n - m, m);
+    const uint64_t len = pa::choose_len(need);
+    if (len == 0)
+        return fail(PA_ERR_UNSUPPORTED_SIZE, "block needs a transform of length " + std::to_string(need) +
+                                                 " > " + std::to_string(pa::kMaxLen));
+    *L = len;
+    return PA_OK;
+}
+
+// Side streams per caller stream for concurrent length groups (with the
+// caller's own stream, four lanes: as many as the default hardware queues).
+constexpr int kSideStreams = 3;
+
 struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
     void *pinned = nullptr;       // host staging for job tables
     size_t pinned_bytes = 0;
     hipEvent_t staged = nullptr;  // recorded after the last copy out of `pinned`
+    // side streams that run length groups of a batched call concurrently
+    // with the caller's stream (forked from and joined back into it)
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kSideStreams] = {};
 };
 std::mutex g_ws_mu;
 std::map<std::pair<int, void *>, Workspace> g_ws;
@@ -80,6 +107,42 @@ pa_status get_workspace(hipStream_t s, size_t bytes, void **out) {
         w.bytes = alloc;
     }
     *out = w.ptr;
+    return PA_OK;
+}
+
+// Streams for k concurrent lanes of work ordered after everything already
+// on s: out[0] = s, out[1..k-1] = side streams that wait for s.  Every
+// lane must be joined back with join_lanes before s is used again.
+pa_status fork_lanes(hipStream_t s, int k, hipStream_t *out) {
+    int dev = 0;
+    PA_HIP(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[{dev, (void *)s}];
+    out[0] = s;
+    if (k <= 1) return PA_OK;
+    if (!w.fork_ev) PA_HIP(hipEventCreateWithFlags(&w.fork_ev, hipEventDisableTiming), "hipEventCreate");
+    PA_HIP(hipEventRecord(w.fork_ev, s), "hipEventRecord");
+    for (int i = 1; i < k; ++i) {
+        if (!w.side[i - 1]) {
+            PA_HIP(hipStreamCreateWithFlags(&w.side[i - 1], hipStreamNonBlocking), "hipStreamCreate");
+            PA_HIP(hipEventCreateWithFlags(&w.join_ev[i - 1], hipEventDisableTiming), "hipEventCreate");
+        }
+        PA_HIP(hipStreamWaitEvent(w.side[i - 1], w.fork_ev, 0), "hipStreamWaitEvent");
+        out[i] = w.side[i - 1];
+    }
+    return PA_OK;
+}
+
+// Makes s wait for lanes 1..k-1 of the last fork_lanes(s, k).
+pa_status join_lanes(hipStream_t s, int k) {
+    int dev = 0;
+    PA_HIP(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[{dev, (void *)s}];
+    for (int i = 1; i < k; ++i) {
+        PA_HIP(hipEventRecord(w.join_ev[i - 1], w.side[i - 1]), "hipEventRecord");
+        PA_HIP(hipStreamWaitEvent(s, w.join_ev[i - 1], 0), "hipStreamWaitEvent");
+    }
     return PA_OK;
 }
 
@@ -220,6 +283,17 @@ pa::JobDesc plain_job(const uint64_t *key, uint64_t n, const uint64_t *seed, uin
     j.m = (uint32_t)m;
     j.off0 = (uint32_t)out_offset(n);
     j.shift = (uint32_t)(out_offset(n) - (n - 1));
+    return j;
+}
+
+// Descriptor of a modified-Toeplitz block: the plain job of the key
+// suffix x[m:n] (read from bit m of key) against v, with x[0:m] XORed into
+// the output by P3.
+pa::JobDesc modified_job(const uint64_t *key, uint64_t n, const uint64_t *v, uint64_t m, uint64_t *out, int32_t *A,
+                         int32_t *S) {
+    pa::JobDesc j = plain_job(key, n - m, v, m, out, A, S);
+    j.key_off = (uint32_t)m;
+    j.xor_src = key;
     return j;
 }
 
@@ -412,13 +486,45 @@ pa_status pa_toeplitz_hash(const uint64_t *key_bits, uint64_t n, const uint64_t 
 }
 
 pa_status pa_toeplitz_hash_batched(const pa_block *blocks, uint32_t count, void *stream) {
+    return hash_batched(blocks, count, (hipStream_t)stream, false);
+}
+
+pa_status pa_modified_toeplitz_hash_batched(const pa_block *blocks, uint32_t count, void *stream) {
+    return hash_batched(blocks, count, (hipStream_t)stream, true);
+}
+
+pa_status pa_modified_toeplitz_hash(const uint64_t *key_bits, uint64_t n, const uint64_t *v_bits, uint64_t m,
+                                    uint64_t *out_bits, void *stream) {
+    uint64_t L = 0;
+    PA_TRY(check_modified(key_bits, n, v_bits, m, out_bits, &L));
+    hipStream_t s = (hipStream_t)stream;
+    pa::PlanRef p{};
+    PA_TRY(plan_for(L, 0, &p));
+    void *ws = nullptr;
+    PA_TRY(get_workspace(s, (size_t)(8 * L), &ws));
+    pa::JobArgs ja{};
+    ja.one = modified_job(key_bits, n, v_bits, m, out_bits, (int32_t *)ws, (int32_t *)ws + L);
+    return run_plain(p, ja, 1, words8(n) + words8(n - 1) + words8(m), words8(m), s);
+}
+
+uint64_t pa_final_key_length(uint64_t n, uint64_t t, uint64_t s) {
+    return (t >= n || s >= n - t) ? 0 : n - t - s;
+}
+
+}  // extern "C"
+
+namespace pa {
+namespace rt {
+
+// Plain or modified Toeplitz over a block array (see pa_toeplitz_hash_batched).
+pa_status hash_batched(const pa_block *blocks, uint32_t count, hipStream_t s, bool modified) {
     if (count == 0) return PA_OK;
     if (!blocks) return fail(PA_ERR_INVALID_ARG, "null block array");
-    hipStream_t s = (hipStream_t)stream;
     std::vector<uint64_t> lens(count);
     for (uint32_t i = 0; i < count; ++i) {
         const pa_block &b = blocks[i];
-        pa_status st = check_block(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, &lens[i]);
+        pa_status st = modified ? check_modified(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, &lens[i])
+                                : check_block(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, &lens[i]);
         if (st != PA_OK) return fail(st, "block " + std::to_string(i) + ": " + g_last_error);
     }
     // Group blocks by transform length: one pass sequence per length class.
@@ -446,31 +552,57 @@ pa_status pa_toeplitz_hash_batched(const pa_block *blocks, uint32_t count, void 
         for (uint32_t i : g.second) {
             const pa_block &b = blocks[i];
             const uint64_t L = g.first;
-            table.push_back(plain_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, next, next + L));
+            table.push_back(modified ? modified_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, next, next + L)
+                                     : plain_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, next, next + L));
             next += 2 * L;
         }
     }
     PA_TRY(stage_upload(s, dtable, table.data(), table.size() * sizeof(pa::JobDesc)));
-    size_t gi = 0;
-    for (auto &g : groups) {
+    // Length groups are independent: spread them over up to 1 + kSideStreams
+    // lanes (largest work first, each to the least-loaded lane) so one
+    // group's tail overlaps the next group's passes.
+    const int ng = (int)groups.size();
+    const int lanes = std::min(ng, 1 + kSideStreams);
+    std::vector<int> order(ng), lane_of(ng, 0);
+    std::vector<double> work(ng), load(lanes, 0.0);
+    for (int i = 0; i < ng; ++i) {
+        order[i] = i;
+        work[i] = (double)plans[i].first * (double)spans[i].second;
+    }
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    for (int i : order) {
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        lane_of[i] = l;
+        load[l] += work[i];
+    }
+    hipStream_t lane_s[1 + kSideStreams];
+    PA_TRY(fork_lanes(s, lanes, lane_s));
+    pa_status st = PA_OK;
+    for (int gi : order) {
         const pa::PlanRef &p = plans[gi].second;
         const size_t first = spans[gi].first, n = spans[gi].second;
-        for (size_t off = 0; off < n; off += 65535) {
+        for (size_t off = 0; off < n && st == PA_OK; off += 65535) {
             const int nj = (int)std::min<size_t>(65535, n - off);
             pa::JobArgs ja{};
             ja.table = dtable + first + off;
             double in_b = 0, out_b = 0;
             for (size_t k = first + off; k < first + off + (size_t)nj; ++k) {
-                in_b += words8(table[k].n) + words8(table[k].seed_bits);
+                in_b += words8(table[k].n) + words8(table[k].seed_bits) + (modified ? words8(table[k].m) : 0.0);
                 out_b += words8(table[k].m);
             }
-            PA_TRY(run_plain(p, ja, nj, in_b, out_b, s));
+            st = run_plain(p, ja, nj, in_b, out_b, lane_s[lane_of[gi]]);
         }
-        (void)g;
-        ++gi;
+        if (st != PA_OK) break;
     }
-    return PA_OK;
+    // join even after a failed launch so the caller's stream stays ordered
+    pa_status js = join_lanes(s, lanes);
+    return st != PA_OK ? st : js;
 }
+
+}  // namespace rt
+}  // namespace pa
+
+extern "C" {
 
 pa_status pa_plan_create(const uint64_t *seed_bits, uint64_t seed_len_bits, uint64_t transform_len, void *stream,
                          pa_plan_t *plan) {

@@ -126,7 +126,8 @@ struct JobDesc {
     uint32_t m;            // output bits
     uint32_t off0;         // first convolution position of the output window
     uint32_t shift;        // shift of source 0 (off0 - (n - 1)); source 1 is unshifted
-    uint32_t pad_;
+    uint32_t key_off;      // source 0 starts at this bit of `key` (modified Toeplitz: m)
+    const uint64_t *xor_src;  // non-null: P3 XORs output bit i with bit i of this array
 };
 
 // Jobs of a launch: either one descriptor passed inline in the kernel

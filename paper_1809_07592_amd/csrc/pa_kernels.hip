@@ -205,9 +205,10 @@ __device__ __forceinline__ void fwd_stages(RegArr<N3, N2> &v, int b, const XDesc
                                            int s0) {
     if constexpr (K < Shape<N3, N2>::Q) {
         fwd_stage<N3, N2, K>(v, b, tw, xd.fwd_off[s0 + K]);
-        // keep the next stage's twiddle loads from being hoisted above this
-        // stage (otherwise all of a round's twiddles are live at once)
-        __builtin_amdgcn_sched_barrier(0);
+        // in groups of more than 8 values, keep the next stage's twiddle
+        // loads from being hoisted above this stage (otherwise all of the
+        // round's twiddles are live at once and occupancy drops)
+        if constexpr (Shape<N3, N2>::RHO > 8) __builtin_amdgcn_sched_barrier(0);
         fwd_stages<N3, N2, K + 1>(v, b, xd, tw, s0);
     }
 }
@@ -217,7 +218,7 @@ __device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast,
                                            const double2 *__restrict__ tw, int s0) {
     if constexpr (K >= 0) {
         inv_stage<N3, N2, K>(v, jj, jlast, tw, xd.inv_off[s0 + K]);
-        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (Shape<N3, N2>::RHO > 8) __builtin_amdgcn_sched_barrier(0);
         inv_stages<N3, N2, K - 1>(v, jj, jlast, xd, tw, s0);
     }
 }
@@ -359,6 +360,8 @@ __device__ __forceinline__ JobDesc job_of(const JobArgs &ja, unsigned idx) {
     j.m = uni(j.m);
     j.off0 = uni(j.off0);
     j.shift = uni(j.shift);
+    j.key_off = uni(j.key_off);
+    j.xor_src = uni(j.xor_src);
     return j;
 }
 
@@ -371,7 +374,12 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
     const bool src = blockIdx.y != 0;
     const int nbits = (int)(src ? job.seed_bits : job.n);
     const int shift = src ? 0 : (int)job.shift;
-    const rsrc_t bits = make_rsrc(src ? job.seed : job.key, (uint32_t)(((uint32_t)nbits + 31) / 32 * 4));
+    // source 0 may start at bit key_off: address its 32-bit word, keep the
+    // remainder ro as a bit offset inside the buffer
+    const uint32_t koff = src ? 0u : job.key_off;
+    const int ro = (int)(koff & 31u);
+    const uint32_t *base = (const uint32_t *)(src ? job.seed : job.key) + (koff >> 5);
+    const rsrc_t bits = make_rsrc(base, (uint32_t)(((uint32_t)nbits + (uint32_t)ro + 31) / 32 * 4));
     const rsrc_t out = make_rsrc(src ? job.S : job.A, (uint32_t)(lp.L * 4));
     const int W = lp.W, wsh = __builtin_ctz((unsigned)W), C = lp.C;
     const int c0 = xcd_tile(blockIdx.x, lp.ntiles) * W;
@@ -381,8 +389,9 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
     auto load_bits = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double {
         // branch-free: a negative p reads out of range (0); bits >= nbits are masked
         const int p = (g.q0 + (l << g.jl)) * C + c0 + g.c - shift;
-        const unsigned w = (unsigned)ld32(bits, (p >> 5) * 4);
-        const unsigned bit = (w >> (p & 31)) & ((unsigned)p < (unsigned)nbits ? 1u : 0u);
+        const int pr = p + ro;
+        const unsigned w = (unsigned)ld32(bits, (pr >> 5) * 4);
+        const unsigned bit = (w >> (pr & 31)) & ((unsigned)p < (unsigned)nbits ? 1u : 0u);
         return (double)bit;
     };
     auto load_lds = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double {
@@ -424,7 +433,7 @@ struct TwCtx {
 };
 
 template <int FK>
-__global__ void __launch_bounds__(512) k_rowconv(const LenPlan *__restrict__ plan, JobArgs ja, int mode,
+__global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ plan, JobArgs ja, int mode,
                                                  const double2 *__restrict__ ftw, const double2 *__restrict__ itw) {
     const LenPlan &lp = *plan;
     const XDesc &xd = lp.row;
@@ -558,6 +567,21 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     const int olim = (int)(64 * ((m + 63) / 64));
     const int mm = (int)m, off = (int)off0;
     const int lane = threadIdx.x & 63;
+    // modified Toeplitz: output bit i ^= bit i of xor_src (i < m)
+    const bool do_xor = job.xor_src != nullptr;
+    // (a zero-size resource when absent: any access is out of range)
+    const rsrc_t xbuf = make_rsrc(job.xor_src, do_xor ? (uint32_t)((m + 63) / 64 * 8) : 0u);
+    // bits [pos, pos + W) of xor_src that lie below m, as the low W bits
+    auto xor_chunk = [&](int pos) PA_INLINE -> uint64_t {
+        uint64_t x;
+        if (W == 64)
+            x = (uint64_t)(uint32_t)ld32(xbuf, (pos >> 6) * 8) | ((uint64_t)(uint32_t)ld32(xbuf, (pos >> 6) * 8 + 4) << 32);
+        else
+            x = (uint64_t)((uint32_t)ld32(xbuf, (pos >> 5) * 4) >> (pos & 31 & (W == 16 ? 16 : 0)));
+        const int keep = mm - pos;  // >= 1 for a stored chunk
+        if (keep < 64) x &= (1ull << keep) - 1ull;
+        return W == 64 ? x : (x & ((1ull << W) - 1ull));
+    };
     // Every wave runs whole iterations of the item loop (items and blockDim
     // are multiples of 64), so each ballot sees all 64 lanes.
     auto store_bits = [&](NoCtx, auto &v, Geo g) PA_INLINE {
@@ -569,12 +593,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
             const int pos = (g.q0 + (l << g.jl)) * C + c0 + g.c - off;
             const uint64_t mask = __ballot(((par >> l) & 1u) && pos >= 0 && pos < mm);
             if (g.c == 0 && pos >= 0 && pos < olim) {
+                const uint64_t x = (do_xor && pos < mm) ? xor_chunk(pos) : 0ull;
                 if (W == 64)
-                    st64(obuf, (pos >> 6) * 8, mask);
+                    st64(obuf, (pos >> 6) * 8, mask ^ x);
                 else if (W == 32)
-                    st32(obuf, (pos >> 5) * 4, (int)(uint32_t)(mask >> (lane & 32)));
+                    st32(obuf, (pos >> 5) * 4, (int)((uint32_t)(mask >> (lane & 32)) ^ (uint32_t)x));
                 else
-                    st16(obuf, (pos >> 4) * 2, (unsigned)(mask >> (lane & 48)) & 0xFFFFu);
+                    st16(obuf, (pos >> 4) * 2, ((unsigned)(mask >> (lane & 48)) ^ (unsigned)x) & 0xFFFFu);
             }
         }
     };

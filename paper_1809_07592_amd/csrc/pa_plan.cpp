@@ -259,10 +259,12 @@ static int choose_log2R(uint64_t L) {
 
 static int round_items(const RoundDesc &rd, int W) { return rd.ngroups * W; }
 
-static int threads_for(const XDesc &x, int W) {
+// Workgroup size: enough threads for the largest round's work items (one
+// item each), at most `cap`.
+static int threads_for(const XDesc &x, int W, int cap) {
     int mx = 0;
     for (int r = 0; r < x.nrounds; ++r) mx = std::max(mx, round_items(x.round[r], W));
-    int t = std::min(512, mx);
+    int t = std::min(cap, mx);
     t = (t + 63) / 64 * 64;
     return std::max(t, 64);
 }
@@ -307,8 +309,10 @@ void plan_geometry(uint64_t L, int log2R, int Wreq, LenPlan &lp, XTables *ct, XT
     if (W != 16 && W != 32 && W != 64) throw std::runtime_error("tile width must be 16, 32 or 64");
     lp.W = W;
     lp.ntiles = lp.C / W;
-    lp.col_threads = threads_for(lp.col, W);
-    lp.row_threads = threads_for(lp.row, 1);
+    lp.col_threads = threads_for(lp.col, W, 512);
+    // rows: one item per thread in every round keeps more waves in flight
+    // to hide the LDS and twiddle latency of a single row
+    lp.row_threads = threads_for(lp.row, 1, 1024);
     if (round_items(lp.col.round[0], W) % 64) throw std::runtime_error("column round not a multiple of 64 items");
     lp.col_lds = (lp.R + (lp.R >> lp.col.lgpad)) * W;
     lp.row_lds = lp.C + (lp.C >> lp.row.lgpad);

@@ -52,6 +52,9 @@ hipError_t p3(const PlanRef &p, const JobArgs &ja, int njobs, double out_bytes, 
 // one length.
 pa_status run_plain(const PlanRef &p, const JobArgs &ja, int njobs, double in_bytes, double out_bytes,
                     hipStream_t s);
+// Plain (modified = false) or modified Toeplitz over a host array of
+// blocks: validation, grouping by transform length, concurrent lanes.
+pa_status hash_batched(const pa_block *blocks, uint32_t count, hipStream_t s, bool modified);
 // Spectrum of the first nbits seed bits into S (L residues), on stream s.
 pa_status run_seed_path(const PlanRef &p, const uint64_t *seed, uint64_t nbits, int32_t *S, hipStream_t s);
 

@@ -70,6 +70,32 @@ def test_batched_validation(lib):
     assert lib.pa_toeplitz_hash_batched(None, 3, None) == pa.PA_ERR_INVALID_ARG
 
 
+@pytest.mark.parametrize("key,n,v,m,out,status", [
+    (FAKE, 100, FAKE, 100, FAKE, pa.PA_ERR_INVALID_ARG),   # m = n: V would have no column
+    (FAKE, 100, FAKE, 0, FAKE, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 1, FAKE, 1, FAKE, pa.PA_ERR_INVALID_ARG),
+    (None, 100, FAKE, 10, FAKE, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 100, None, 10, FAKE, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 100, FAKE, 10, None, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 40_000_000, FAKE, 10, FAKE, pa.PA_ERR_UNSUPPORTED_SIZE),
+])
+def test_modified_rejects_before_device_work(lib, key, n, v, m, out, status):
+    assert lib.pa_modified_toeplitz_hash(key, n, v, m, out, None) == status
+    blocks = (pa._Block * 1)()
+    blocks[0] = pa._Block(key, n, v, m, out)
+    assert lib.pa_modified_toeplitz_hash_batched(blocks, 1, None) == status
+    assert "block 0" in pa.last_error()
+
+
+def test_final_key_length_follows_eq1():
+    # r = n - t - s (Eq. 1: s = n - t - r), clamped at 0
+    assert pa.final_key_length(1_000_000, 200_000, 100) == 799_900
+    assert pa.final_key_length(100, 40, 60) == 0
+    assert pa.final_key_length(100, 101, 0) == 0
+    assert pa.final_key_length(100, 0, 2**63) == 0
+    assert pa.final_key_length(2**62, 1, 1) == 2**62 - 2
+
+
 def test_plan_validation(lib):
     h = ctypes.c_void_p()
     assert lib.pa_plan_create(None, 100, 0, None, ctypes.byref(h)) == pa.PA_ERR_INVALID_ARG
@@ -137,7 +163,7 @@ def _check_geometry(d, L):
     R, C, W = d["rows"], d["cols"], d["tile_width"]
     assert R * C == L and C % 64 == 0 and W in (16, 32, 64) and C % W == 0
     assert 1 <= d["col_threads"] <= 512 and d["col_threads"] % 64 == 0
-    assert 1 <= d["row_threads"] <= 512 and d["row_threads"] % 64 == 0
+    assert 1 <= d["row_threads"] <= 1024 and d["row_threads"] % 64 == 0
     assert d["col_lds_bytes"] <= 160 * 1024 and d["row_lds_bytes"] <= 160 * 1024
     prod = 1
     for r in d["col_round_size"]:

@@ -1,0 +1,109 @@
+"""Modified Toeplitz hash on the GPU (Sec. 2.2, Eq. 2-3): y = x[0:m] XOR
+V x[m:n], V the m x (n-m) Toeplitz matrix of n-1 bits v.  Compared word for
+word with the CPU oracle's modified hash (itself pinned by brute force and
+by its reduction to identity plus plain Toeplitz), and cross-checked
+against the plain GPU path run on the key suffix."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1809_07592_amd as pa
+from paper_1809_07592_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def host(t, m):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)[: wl.words(m)]
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build()
+    yield
+
+
+def inputs(cfg, n, m, idx, garbage=False):
+    key = wl.random_bits(n, wl.rng(cfg, wl.ROLE_KEY, idx), garbage_tail=garbage)
+    v = wl.random_bits(n - 1, wl.rng(cfg, wl.ROLE_SEED, idx), garbage_tail=garbage)
+    return key, v
+
+
+SHAPES = [(2, 1), (3, 2), (64, 63), (65, 1), (65, 64), (128, 64), (129, 65), (130, 70), (1000, 1), (1000, 999),
+          (1000, 500), (4097, 2048), (5000, 4000), (4096, 32), (100_003, 31_337), (262_144, 65_536),
+          (300_000, 27_001)]
+
+
+@pytest.mark.parametrize("n,m", SHAPES)
+def test_matches_oracle(n, m):
+    key, v = inputs(50, n, m, n * 3 + m)
+    got = host(pa.modified_toeplitz_hash(dev(key), n, dev(v), m), m)
+    want = oracle.modified_toeplitz_hash(key, n, v, m)
+    assert np.array_equal(got, want), "n=%d m=%d: %d words differ" % (n, m, int(np.sum(got != want)))
+
+
+def test_garbage_padding_is_ignored():
+    n, m = 100_001, 20_003
+    k1, v1 = inputs(51, n, m, 0, garbage=False)
+    k2, v2 = inputs(51, n, m, 0, garbage=True)
+    y1 = host(pa.modified_toeplitz_hash(dev(k1), n, dev(v1), m), m)
+    y2 = host(pa.modified_toeplitz_hash(dev(k2), n, dev(v2), m), m)
+    assert np.array_equal(y1, y2)
+    assert np.array_equal(y1, oracle.modified_toeplitz_hash(k1, n, v1, m))
+
+
+def test_finite_size_block_full():
+    n, m = 1_000_000, 250_000
+    key, v = inputs(52, n, m, 0)
+    got = host(pa.modified_toeplitz_hash(dev(key), n, dev(v), m), m)
+    assert np.array_equal(got, oracle.modified_toeplitz_hash(key, n, v, m))
+
+
+def _suffix(key, n, m):
+    bits = np.unpackbits(key.view(np.uint8), bitorder="little")[:n]
+    tail = bits[m:]
+    return np.packbits(np.concatenate([tail, np.zeros((-tail.size) % 64, np.uint8)]), bitorder="little").view(np.uint64)
+
+
+@pytest.mark.parametrize("n,m", [(1000, 333), (70_000, 9_001), (200_000, 150_000)])
+def test_equals_xor_plus_plain_hash_of_the_suffix(n, m):
+    # the offset read of the key suffix against an explicit host-side shift
+    key, v = inputs(53, n, m, n)
+    suf = _suffix(key, n, m)
+    plain = host(pa.toeplitz_hash(dev(suf), n - m, dev(v), m), m) if m <= n - m else None
+    got = host(pa.modified_toeplitz_hash(dev(key), n, dev(v), m), m)
+    head = np.packbits(np.concatenate([np.unpackbits(key.view(np.uint8), bitorder="little")[:m],
+                                       np.zeros((-m) % 64, np.uint8)]), bitorder="little").view(np.uint64)
+    if plain is not None:
+        assert np.array_equal(got, head ^ plain)
+    assert np.array_equal(got, oracle.modified_toeplitz_hash(key, n, v, m))
+
+
+def test_batched_matches_single_and_oracle():
+    g = np.random.default_rng(54)
+    blocks, ins = [], []
+    for i in range(24):
+        n = int(round(2.0 ** g.uniform(12, 18)))
+        m = max(1, min(n - 1, int(round(n * g.uniform(0.05, 0.7)))))
+        key, v = inputs(55, n, m, i)
+        ins.append((key, v, n, m))
+        blocks.append((dev(key), n, dev(v), m, torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")))
+    outs = pa.modified_toeplitz_hash_batched(blocks)
+    for i, (key, v, n, m) in enumerate(ins):
+        want = oracle.modified_toeplitz_hash(key, n, v, m)
+        assert np.array_equal(host(outs[i], m), want), (i, n, m)
+        if i % 6 == 0:
+            assert np.array_equal(host(pa.modified_toeplitz_hash(blocks[i][0], n, blocks[i][2], m), m), want)
+
+
+def test_transform_is_shorter_than_plain():
+    # the Toeplitz part spans (n - m) + m = n instead of n + m
+    assert pa.transform_len(1_000_000 - 250_000, 250_000) == 2**20 < pa.transform_len(1_000_000, 250_000)

@@ -210,6 +210,40 @@ def test_batched_uneven_blocks_match_single_calls_and_oracle():
             assert np.array_equal(gpu_hash(key, n, seed, m), want)
 
 
+def test_batched_groups_join_back_into_the_callers_stream():
+    # length groups run on side lanes; the outputs must be complete for work
+    # queued afterwards on the caller's stream (only that stream is synced)
+    g = np.random.default_rng(24)
+    shapes = [(2_000_000, 500_000)] + [(int(round(2.0 ** g.uniform(13, 17))), 0) for _ in range(11)]
+    blocks, keys = [], []
+    for i, (n, m) in enumerate(shapes):
+        m = m or max(1, n // 5)
+        key, seed = wl.key_and_seed(25, n, m, i)
+        keys.append((key, seed, n, m))
+        blocks.append((dev(key), n, dev(seed), m, torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")))
+    assert len({pa.transform_len(n, m) for _, _, n, m in keys}) >= 4
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for b in blocks:
+            b[4].record_stream(s)
+        for rep in range(2):
+            pa.toeplitz_hash_batched(blocks, stream=s)
+            copies = [b[4].clone() for b in blocks]   # queued on s after the call
+            s.synchronize()
+            for i, (key, seed, n, m) in enumerate(keys):
+                if n > 1_000_000:
+                    idx = np.arange(0, m, 997)
+                    words_ = copies[i].cpu().numpy().view(np.uint64)
+                    got = ((words_[idx >> 6] >> (idx & 63).astype(np.uint64)) & np.uint64(1)).astype(np.uint8)
+                    assert np.array_equal(got, oracle.toeplitz_bits(key, n, seed, m, idx)), (rep, i)
+                else:
+                    want = oracle.toeplitz_hash(key, n, seed, m)
+                    assert np.array_equal(copies[i].cpu().numpy().view(np.uint64)[: want.size], want), (rep, i)
+            for b in blocks:
+                b[4].zero_()
+
+
 def test_profile_records_every_kernel():
     n, m = 300_000, 60_000
     key, seed = wl.key_and_seed(23, n, m, 0)

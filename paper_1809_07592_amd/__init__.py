@@ -261,19 +261,43 @@ def _stream_handle(stream):
     return stream.cuda_stream
 
 
+_BIT_DTYPES = None
+
+
+def _bit_dtypes():
+    global _BIT_DTYPES
+    if _BIT_DTYPES is None:
+        import torch
+        _BIT_DTYPES = frozenset({torch.int64, getattr(torch, "uint64", torch.int64)})
+    return _BIT_DTYPES
+
+
 def _ptr(t, nwords: int, what: str):
-    import torch
     if t is None:
         return None
     if not t.is_cuda:
         raise ValueError("%s must be a device (CUDA/HIP) tensor" % what)
-    if t.dtype not in (torch.int64, getattr(torch, "uint64", torch.int64)):
+    if t.dtype not in _bit_dtypes():
         raise ValueError("%s must be int64/uint64 packed bits" % what)
     if not t.is_contiguous():
         raise ValueError("%s must be contiguous" % what)
     if t.numel() < nwords:
         raise ValueError("%s has %d words, needs %d" % (what, t.numel(), nwords))
     return t.data_ptr()
+
+
+def _blocks(blocks, seed_words):
+    """ctypes array of pa_block from (key, n, seed, m, out) tuples."""
+    arr = (_Block * max(len(blocks), 1))()
+    for i, (key, n, seed, m, out) in enumerate(blocks):
+        n, m = int(n), int(m)
+        b = arr[i]
+        b.key_bits = _ptr(key, (n + 63) >> 6, "key")
+        b.n = n
+        b.seed_bits = _ptr(seed, seed_words(n, m), "seed")
+        b.m = m
+        b.out_bits = _ptr(out, (m + 63) >> 6, "out")
+    return arr
 
 
 def toeplitz_hash(key, n: int, seed, m: int, out=None, stream=None):
@@ -288,10 +312,7 @@ def toeplitz_hash(key, n: int, seed, m: int, out=None, stream=None):
 
 def toeplitz_hash_batched(blocks, stream=None):
     """blocks: sequence of (key, n, seed, m, out) tuples; returns the outs."""
-    arr = (_Block * max(len(blocks), 1))()
-    for i, (key, n, seed, m, out) in enumerate(blocks):
-        arr[i] = _Block(_ptr(key, words(n), "key"), int(n), _ptr(seed, words(n + m - 1), "seed"), int(m),
-                        _ptr(out, words(m), "out"))
+    arr = _blocks(blocks, lambda n, m: (n + m + 62) >> 6)
     _check(lib().pa_toeplitz_hash_batched(arr, len(blocks), _stream_handle(stream)))
     return [b[4] for b in blocks]
 
@@ -308,10 +329,7 @@ def modified_toeplitz_hash(key, n: int, v, m: int, out=None, stream=None):
 
 def modified_toeplitz_hash_batched(blocks, stream=None):
     """blocks: sequence of (key, n, v, m, out) tuples (v: n-1 bits); returns the outs."""
-    arr = (_Block * max(len(blocks), 1))()
-    for i, (key, n, v, m, out) in enumerate(blocks):
-        arr[i] = _Block(_ptr(key, words(n), "key"), int(n), _ptr(v, words(n - 1), "v"), int(m),
-                        _ptr(out, words(m), "out"))
+    arr = _blocks(blocks, lambda n, m: (n + 62) >> 6)
     _check(lib().pa_modified_toeplitz_hash_batched(arr, len(blocks), _stream_handle(stream)))
     return [b[4] for b in blocks]
 

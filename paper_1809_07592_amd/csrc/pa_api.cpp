@@ -73,12 +73,21 @@ pa_status check_modified(const uint64_t *key, uint64_t n, const uint64_t *v, uin
 // caller's own stream, four lanes: as many as the default hardware queues).
 constexpr int kSideStreams = 3;
 
+// Pinned staging slots per caller stream: a call waits only for the copy
+// out of the slot it reuses, so the host can run this many calls ahead.
+constexpr int kStageSlots = 4;
+
+struct StageSlot {
+    void *pinned = nullptr;       // host staging for a job table
+    size_t bytes = 0;
+    hipEvent_t staged = nullptr;  // recorded after the copy out of `pinned`
+};
+
 struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
-    void *pinned = nullptr;       // host staging for job tables
-    size_t pinned_bytes = 0;
-    hipEvent_t staged = nullptr;  // recorded after the last copy out of `pinned`
+    StageSlot slot[kStageSlots];
+    int next_slot = 0;
     // side streams that run length groups of a batched call concurrently
     // with the caller's stream (forked from and joined back into it)
     hipStream_t side[kSideStreams] = {};
@@ -147,26 +156,28 @@ pa_status join_lanes(hipStream_t s, int k) {
 }
 
 // Copy `bytes` of host data to device address `dst` on stream s through
-// the stream's pinned staging buffer (waits until the previous copy out of
-// the staging buffer has completed before overwriting it).
+// the next of the stream's pinned staging slots (waits only until the
+// previous copy out of that slot has completed before overwriting it).
 pa_status stage_upload(hipStream_t s, void *dst, const void *src, size_t bytes) {
     int dev = 0;
     PA_HIP(hipGetDevice(&dev), "hipGetDevice");
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace &w = g_ws[{dev, (void *)s}];
-    if (w.staged) PA_HIP(hipEventSynchronize(w.staged), "hipEventSynchronize");
-    if (w.pinned_bytes < bytes) {
-        if (w.pinned) PA_HIP(hipHostFree(w.pinned), "hipHostFree");
-        w.pinned = nullptr;
-        w.pinned_bytes = 0;
+    StageSlot &sl = w.slot[w.next_slot];
+    w.next_slot = (w.next_slot + 1) % kStageSlots;
+    if (sl.staged) PA_HIP(hipEventSynchronize(sl.staged), "hipEventSynchronize");
+    if (sl.bytes < bytes) {
+        if (sl.pinned) PA_HIP(hipHostFree(sl.pinned), "hipHostFree");
+        sl.pinned = nullptr;
+        sl.bytes = 0;
         const size_t alloc = std::max(bytes, (size_t)64 << 10);
-        PA_HIP(hipHostMalloc(&w.pinned, alloc, hipHostMallocDefault), "hipHostMalloc");
-        w.pinned_bytes = alloc;
+        PA_HIP(hipHostMalloc(&sl.pinned, alloc, hipHostMallocDefault), "hipHostMalloc");
+        sl.bytes = alloc;
     }
-    if (!w.staged) PA_HIP(hipEventCreateWithFlags(&w.staged, hipEventDisableTiming), "hipEventCreate");
-    memcpy(w.pinned, src, bytes);
-    PA_HIP(hipMemcpyAsync(dst, w.pinned, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
-    PA_HIP(hipEventRecord(w.staged, s), "hipEventRecord");
+    if (!sl.staged) PA_HIP(hipEventCreateWithFlags(&sl.staged, hipEventDisableTiming), "hipEventCreate");
+    memcpy(sl.pinned, src, bytes);
+    PA_HIP(hipMemcpyAsync(dst, sl.pinned, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    PA_HIP(hipEventRecord(sl.staged, s), "hipEventRecord");
     return PA_OK;
 }
 

@@ -99,7 +99,7 @@ struct LenPlan {
     int W;                   // column-tile width of the column passes (power of two, 16..64)
     int ntiles;              // C / W
     int col_threads;         // workgroup size of the column passes
-    int row_threads;         // workgroup size of the row pass
+    int row_threads;         // largest row-pass workgroup (launches over many rows may use fewer)
     int col_lds;             // LDS ints of one column tile (padded)
     int row_lds;             // LDS ints of one row (padded)
     int fused_ok;            // two rows fit in LDS: the plain path runs seed and key in one row pass

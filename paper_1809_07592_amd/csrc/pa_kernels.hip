@@ -662,6 +662,38 @@ hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const J
     return hipGetLastError();
 }
 
+// VGPRs per thread of k_rowconv<fk> (cached; from the code object).
+static hipError_t rowconv_regs(int fk, int *regs) {
+    static int cache[kNumKinds];
+    if (cache[fk] == 0) {
+        static const void *fns[kNumKinds] = {
+            (const void *)k_rowconv<0>, (const void *)k_rowconv<1>, (const void *)k_rowconv<2>,
+            (const void *)k_rowconv<3>, (const void *)k_rowconv<4>, (const void *)k_rowconv<5>,
+            (const void *)k_rowconv<6>, (const void *)k_rowconv<7>, (const void *)k_rowconv<8>,
+            (const void *)k_rowconv<9>, (const void *)k_rowconv<10>};
+        hipFuncAttributes a{};
+        hipError_t e = hipFuncGetAttributes(&a, fns[fk]);
+        if (e != hipSuccess) return e;
+        cache[fk] = a.numRegs > 0 ? a.numRegs : 128;
+    }
+    *regs = cache[fk];
+    return hipSuccess;
+}
+
+// Waves resident per CU for workgroups of t threads, `regs` VGPRs per
+// thread and `lds` bytes each: 4 SIMDs of 512 VGPRs (granule 8) and at most
+// 8 waves each; a workgroup's waves are spread evenly over the SIMDs.
+static int resident_waves(int t, int regs, size_t lds, int lds_limit) {
+    const int per_simd = t / 256;  // t is a multiple of 256
+    const int vg = (regs + 7) / 8 * 8;
+    int simd_waves = 512 / vg;
+    if (simd_waves > 8) simd_waves = 8;
+    int wgs = simd_waves / per_simd;
+    const int by_lds = lds ? (int)((size_t)lds_limit / lds) : wgs;
+    if (by_lds < wgs) wgs = by_lds;
+    return wgs * t / 64;
+}
+
 hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int mode, const JobArgs &ja, int njobs,
                           hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     int limit = 0;
@@ -670,7 +702,28 @@ hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int mode, const 
     const size_t lds = (size_t)hp.row_lds * sizeof(int) * (mode == 2 ? 2 : 1);
     if (lds > (size_t)limit || njobs < 1 || njobs > 65535 || (mode == 2 && !hp.fused_ok))
         return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)hp.R, (unsigned)njobs), block((unsigned)hp.row_threads);
+    const int fk = hp.row.round[0].kind;
+    if (fk < 0 || fk >= kNumKinds) return hipErrorInvalidConfiguration;
+    int threads = hp.row_threads;
+    // With rows for two or more workgroups per CU, take the size that keeps
+    // the most waves resident per CU (ties: the smaller, whose workgroups
+    // do not wait on each other's barriers).  A single block's few rows
+    // leave one workgroup per CU: the plan's full size.
+    if ((size_t)hp.R * (size_t)njobs >= 512) {
+        int regs = 0;
+        e = rowconv_regs(fk, &regs);
+        if (e != hipSuccess) return e;
+        int best = 0;
+        for (int t : {512, 768, 1024}) {
+            if (t > hp.row_threads) continue;
+            const int w = resident_waves(t, regs, lds, limit);
+            if (w > best) {
+                best = w;
+                threads = t;
+            }
+        }
+    }
+    const dim3 grid((unsigned)hp.R, (unsigned)njobs), block((unsigned)threads);
     switch (hp.row.round[0].kind) {
 #define PA_FK(K) \
     case K:                                                                                              \

@@ -310,9 +310,9 @@ void plan_geometry(uint64_t L, int log2R, int Wreq, LenPlan &lp, XTables *ct, XT
     lp.W = W;
     lp.ntiles = lp.C / W;
     lp.col_threads = threads_for(lp.col, W, 512);
-    // rows: one item per thread in every round keeps more waves in flight
-    // to hide the LDS and twiddle latency of a single row
-    lp.row_threads = threads_for(lp.row, 1, 1024);
+    // rows: up to one item per thread in every round, in whole groups of 4
+    // waves (one per SIMD: a barrier waits for the SIMD with the most waves)
+    lp.row_threads = std::min(1024, (threads_for(lp.row, 1, 1024) + 255) / 256 * 256);
     if (round_items(lp.col.round[0], W) % 64) throw std::runtime_error("column round not a multiple of 64 items");
     lp.col_lds = (lp.R + (lp.R >> lp.col.lgpad)) * W;
     lp.row_lds = lp.C + (lp.C >> lp.row.lgpad);

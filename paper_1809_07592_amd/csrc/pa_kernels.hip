@@ -122,6 +122,8 @@ struct Shape {
 
 template <int N3, int N2>
 using RegArr = double[(N3 == 0 ? 1 : N3 == 1 ? 3 : N3 == 2 ? 9 : 27) << N2];
+template <int N3, int N2, int NA>
+using RegArrN = double[NA][(N3 == 0 ? 1 : N3 == 1 ? 3 : N3 == 2 ? 9 : 27) << N2];
 
 // Register index of a group element: lin = sum_k u_k * after(k), digit of
 // the round's first stage most significant.  Memory position:
@@ -129,8 +131,10 @@ using RegArr = double[(N3 == 0 ? 1 : N3 == 1 ? 3 : N3 == 2 ? 9 : 27) << N2];
 
 // Forward Cooley-Tukey stage K of a round: block index b_full = b*before+sb,
 // input u multiplied by gamma^u (table entry), then r-point DFT.
-template <int N3, int N2, int K>
-__device__ __forceinline__ void fwd_stage(RegArr<N3, N2> &v, int b, const double2 *__restrict__ tw, int off) {
+// NA arrays (NA = 2: the seed and key rows of the fused row pass) share
+// each stage's twiddles.
+template <int N3, int N2, int K, int NA>
+__device__ __forceinline__ void fwd_stage(RegArrN<N3, N2, NA> &v, int b, const double2 *__restrict__ tw, int off) {
     using S = Shape<N3, N2>;
     constexpr int r = S::radix(K), rb = S::before(K), ra = S::after(K);
 #pragma unroll
@@ -139,26 +143,30 @@ __device__ __forceinline__ void fwd_stage(RegArr<N3, N2> &v, int b, const double
         if constexpr (r == 2) {
             const double2 w = tw[t];
 #pragma unroll
-            for (int x = 0; x < ra; ++x) {
-                const int i0 = sb * 2 * ra + x, i1 = i0 + ra;
-                const double mm = mulmod(v[i1], w.x, w.y);
-                const double a = v[i0];
-                v[i0] = a + mm;
-                v[i1] = a - mm;
-            }
+            for (int a = 0; a < NA; ++a)
+#pragma unroll
+                for (int x = 0; x < ra; ++x) {
+                    const int i0 = sb * 2 * ra + x, i1 = i0 + ra;
+                    const double mm = mulmod(v[a][i1], w.x, w.y);
+                    const double y = v[a][i0];
+                    v[a][i0] = y + mm;
+                    v[a][i1] = y - mm;
+                }
         } else {
             const double2 w1 = tw[t], w2 = tw[t + 1];
 #pragma unroll
-            for (int x = 0; x < ra; ++x) {
-                const int i0 = sb * 3 * ra + x, i1 = i0 + ra, i2 = i1 + ra;
-                const double b1 = mulmod(v[i1], w1.x, w1.y);
-                const double c1 = mulmod(v[i2], w2.x, w2.y);
-                const double tt = mulmod(b1 - c1, kW3, kW3p);
-                const double a = v[i0];
-                v[i0] = a + b1 + c1;
-                v[i1] = (a - c1) + tt;
-                v[i2] = (a - b1) - tt;
-            }
+            for (int a = 0; a < NA; ++a)
+#pragma unroll
+                for (int x = 0; x < ra; ++x) {
+                    const int i0 = sb * 3 * ra + x, i1 = i0 + ra, i2 = i1 + ra;
+                    const double b1 = mulmod(v[a][i1], w1.x, w1.y);
+                    const double c1 = mulmod(v[a][i2], w2.x, w2.y);
+                    const double tt = mulmod(b1 - c1, kW3, kW3p);
+                    const double y = v[a][i0];
+                    v[a][i0] = y + b1 + c1;
+                    v[a][i1] = (y - c1) + tt;
+                    v[a][i2] = (y - b1) - tt;
+                }
         }
     }
 }
@@ -200,16 +208,16 @@ __device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, 
     }
 }
 
-template <int N3, int N2, int K>
-__device__ __forceinline__ void fwd_stages(RegArr<N3, N2> &v, int b, const XDesc &xd, const double2 *__restrict__ tw,
-                                           int s0) {
+template <int N3, int N2, int K, int NA>
+__device__ __forceinline__ void fwd_stages(RegArrN<N3, N2, NA> &v, int b, const XDesc &xd,
+                                           const double2 *__restrict__ tw, int s0) {
     if constexpr (K < Shape<N3, N2>::Q) {
-        fwd_stage<N3, N2, K>(v, b, tw, xd.fwd_off[s0 + K]);
+        fwd_stage<N3, N2, K, NA>(v, b, tw, xd.fwd_off[s0 + K]);
         // in groups of more than 8 values, keep the next stage's twiddle
         // loads from being hoisted above this stage (otherwise all of the
         // round's twiddles are live at once and occupancy drops)
         if constexpr (Shape<N3, N2>::RHO > 8) __builtin_amdgcn_sched_barrier(0);
-        fwd_stages<N3, N2, K + 1>(v, b, xd, tw, s0);
+        fwd_stages<N3, N2, K + 1, NA>(v, b, xd, tw, s0);
     }
 }
 
@@ -251,7 +259,13 @@ __device__ __forceinline__ Geo launder(Geo g) {
     return g;
 }
 
-template <int MODE, int N3, int N2, bool FIRST, bool LAST, class Pre, class Load, class Mid, class Store>
+// One register round over all work items.  NA = 1: load(ctx, G, l)
+// returns element l, mid/store receive the group's array.  NA = 2 (forward
+// and CONV modes): load returns the (seed, key) pair of element l, both
+// are transformed, mid/store receive both arrays, and in CONV mode only the
+// key array (index 1) is inverse-transformed.
+template <int MODE, int N3, int N2, bool FIRST, bool LAST, int NA = 1, class Pre, class Load, class Mid,
+          class Store>
 __device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, const double2 *__restrict__ ftw,
                                          const double2 *__restrict__ itw, int wsh, Pre &pre, Load &load, Mid &mid,
                                          Store &store) {
@@ -273,48 +287,67 @@ __device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, c
         const int q0 = FIRST ? jj : (b * rd.M + jj);
         Geo G{q0, jl, c, ((q0 + (q0 >> lgp)) << wsh) + c, lstep};
         auto ctx = pre(c, b, jj);
-        RegArr<N3, N2> v;
+        RegArrN<N3, N2, NA> v;
 #pragma unroll
-        for (int l = 0; l < RHO; ++l) v[l] = load(ctx, G, l);
+        for (int l = 0; l < RHO; ++l) {
+            if constexpr (NA == 1) {
+                v[0][l] = load(ctx, G, l);
+            } else {
+                const double2 p = load(ctx, G, l);
+                v[0][l] = p.x;
+                v[1][l] = p.y;
+            }
+        }
         if constexpr (MODE == MODE_FWD || MODE == MODE_CONV) {
             if (FIRST)
-                fwd_stages<N3, N2, 0>(v, 0, xd, ftw, rd.s0);
+                fwd_stages<N3, N2, 0, NA>(v, 0, xd, ftw, rd.s0);
             else if (b_uniform)
-                fwd_stages<N3, N2, 0>(v, __builtin_amdgcn_readfirstlane(b), xd, ftw, rd.s0);
+                fwd_stages<N3, N2, 0, NA>(v, __builtin_amdgcn_readfirstlane(b), xd, ftw, rd.s0);
             else
-                fwd_stages<N3, N2, 0>(v, b, xd, ftw, rd.s0);
+                fwd_stages<N3, N2, 0, NA>(v, b, xd, ftw, rd.s0);
         }
-        if constexpr (MODE == MODE_CONV) mid(ctx, v, launder(G));
-        if constexpr (MODE == MODE_INV || MODE == MODE_CONV)
-            inv_stages<N3, N2, Shape<N3, N2>::Q - 1>(v, jj, J, xd, itw, rd.s0);
-        store(ctx, v, launder(G));
+        if constexpr (NA == 1) {
+            if constexpr (MODE == MODE_CONV) mid(ctx, v[0], launder(G));
+            if constexpr (MODE == MODE_INV || MODE == MODE_CONV)
+                inv_stages<N3, N2, Shape<N3, N2>::Q - 1>(v[0], jj, J, xd, itw, rd.s0);
+            store(ctx, v[0], launder(G));
+        } else {
+            if constexpr (MODE == MODE_CONV) {
+                mid(ctx, v, launder(G));
+                inv_stages<N3, N2, Shape<N3, N2>::Q - 1>(v[1], jj, J, xd, itw, rd.s0);
+                store(ctx, v[1], launder(G));
+            } else {
+                store(ctx, v, launder(G));
+            }
+        }
     }
 }
 
 // Round r of a transform whose rounds are pure radix-2 (kinds 0..3); MAXLG
 // bounds the kinds the plan can give this pass (kColMaxLg / kRowMaxLg).
-template <int MODE, bool FIRST, bool LAST, int MAXLG, class Pre, class Load, class Mid, class Store>
+template <int MODE, bool FIRST, bool LAST, int MAXLG, int NA = 1, class Pre, class Load, class Mid, class Store>
 __device__ __forceinline__ void round_p2(const XDesc &xd, const double2 *__restrict__ ftw,
                                          const double2 *__restrict__ itw, int r, int wsh, Pre &pre, Load &load,
                                          Mid &mid, Store &store) {
     const RoundDesc &rd = xd.round[r];
     switch (rd.kind) {
-        case 0: round_io<MODE, 0, 1, FIRST, LAST>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
-        case 1: round_io<MODE, 0, 2, FIRST, LAST>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
-        case 2: round_io<MODE, 0, 3, FIRST, LAST>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
+        case 0: round_io<MODE, 0, 1, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
+        case 1: round_io<MODE, 0, 2, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
+        case 2: round_io<MODE, 0, 3, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
         case 3:
-            if constexpr (MAXLG >= 4) round_io<MODE, 0, 4, FIRST, LAST>(rd, xd, ftw, itw, wsh, pre, load, mid, store);
+            if constexpr (MAXLG >= 4)
+                round_io<MODE, 0, 4, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store);
             break;
         default: break;
     }
 }
 
 // Round 0 of a transform whose first round has the compile-time kind FK.
-template <int MODE, int FK, bool LAST, class Pre, class Load, class Mid, class Store>
+template <int MODE, int FK, bool LAST, int NA = 1, class Pre, class Load, class Mid, class Store>
 __device__ __forceinline__ void round_fk(const XDesc &xd, const double2 *__restrict__ ftw,
                                          const double2 *__restrict__ itw, int wsh, Pre &pre, Load &load, Mid &mid,
                                          Store &store) {
-    round_io<MODE, kKindN3[FK], kKindN2[FK], true, LAST>(xd.round[0], xd, ftw, itw, wsh, pre, load, mid, store);
+    round_io<MODE, kKindN3[FK], kKindN2[FK], true, LAST, NA>(xd.round[0], xd, ftw, itw, wsh, pre, load, mid, store);
 }
 
 template <class V>
@@ -497,27 +530,70 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
         round_p2<MODE_FWD, false, true, kRowMaxLg>(xd, ftw, itw, nr - 1, 0, pre_none, load_la, mid_none, store_g);
         return;
     }
-    if (mode == 2) {
-        forward_head(rowS, lds_s);
-        auto load_ls = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double { return (double)lds_s[g.lbase + l * g.lstep]; };
-        auto store_ls = [&](NoCtx, auto &v, Geo g) PA_INLINE {
-#pragma unroll
-            for (int l = 0; l < group_size(v); ++l) lds_s[g.lbase + l * g.lstep] = (int)reduce_sym(v[l]);
+    // Plain path with a first round of at most 12 values: each work item
+    // carries the seed and key groups of one position through the forward
+    // rounds together (shared twiddles, two independent chains), and the
+    // last round multiplies the key by the reduced seed spectrum in
+    // registers before its inverse.
+    constexpr bool kDual = Shape<kKindN3[FK], kKindN2[FK]>::RHO <= 12;
+    if (kDual && mode == 2) {
+        auto load_tw2 = [&](TwCtx t, const Geo &g, int l) PA_INLINE -> double2 {
+            const int off = (g.q0 + (l << g.jl)) * 4;
+            const double xs = (double)ld32(rowS, off), xa = (double)ld32(rowA, off);
+            const double2 al = ld_tw(rs_af, l);
+            const double ys = mulmod(xs, t.beta.x, t.beta.y), ya = mulmod(xa, t.beta.x, t.beta.y);
+            return make_double2(mulmod(ys, al.x, al.y), mulmod(ya, al.x, al.y));
         };
-        round_p2<MODE_FWD, false, true, kRowMaxLg>(xd, ftw, itw, nr - 1, 0, pre_none, load_ls, mid_none, store_ls);
-        // the key's last forward round reads the seed spectrum from LDS; the
-        // barrier at the end of the key's round 0 orders the two.
-    }
-    forward_head(rowA, lds_a);
-    const bool from_lds = mode == 2;
-    auto mid_mul = [&](NoCtx, auto &v, Geo g) PA_INLINE {
+        auto load_l2 = [&](auto, const Geo &g, int l) PA_INLINE -> double2 {
+            const int i = g.lbase + l * g.lstep;
+            return make_double2((double)lds_s[i], (double)lds_a[i]);
+        };
+        auto store_l2 = [&](auto, auto &v, Geo g) PA_INLINE {
 #pragma unroll
-        for (int l = 0; l < group_size(v); ++l) {
-            const double s = (double)(from_lds ? lds_s[g.lbase + l * g.lstep] : ld32(rowH, (g.q0 + (l << g.jl)) * 4));
-            v[l] = mulmod(v[l], s, s * kPinv);
+            for (int l = 0; l < group_size(v[0]); ++l) {
+                const int i = g.lbase + l * g.lstep;
+                lds_s[i] = (int)v[0][l];
+                lds_a[i] = (int)v[1][l];
+            }
+        };
+        auto mid_mul2 = [&](NoCtx, auto &v, Geo) PA_INLINE {
+#pragma unroll
+            for (int l = 0; l < group_size(v[0]); ++l) {
+                const double sp = reduce_sym(v[0][l]);
+                v[1][l] = mulmod(v[1][l], sp, sp * kPinv);
+            }
+        };
+        round_fk<MODE_FWD, FK, false, 2>(xd, ftw, itw, 0, pre_fwd, load_tw2, mid_none, store_l2);
+        __syncthreads();
+        for (int r = 1; r < nr - 1; ++r) {
+            round_p2<MODE_FWD, false, false, kRowMaxLg, 2>(xd, ftw, itw, r, 0, pre_none, load_l2, mid_none, store_l2);
+            __syncthreads();
         }
-    };
-    round_p2<MODE_CONV, false, true, kRowMaxLg>(xd, ftw, itw, nr - 1, 0, pre_none, load_la, mid_mul, store_la);
+        round_p2<MODE_CONV, false, true, kRowMaxLg, 2>(xd, ftw, itw, nr - 1, 0, pre_none, load_l2, mid_mul2,
+                                                        store_la);
+    } else {
+        if (mode == 2) {
+            forward_head(rowS, lds_s);
+            auto load_ls = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double { return (double)lds_s[g.lbase + l * g.lstep]; };
+            auto store_ls = [&](NoCtx, auto &v, Geo g) PA_INLINE {
+#pragma unroll
+                for (int l = 0; l < group_size(v); ++l) lds_s[g.lbase + l * g.lstep] = (int)reduce_sym(v[l]);
+            };
+            round_p2<MODE_FWD, false, true, kRowMaxLg>(xd, ftw, itw, nr - 1, 0, pre_none, load_ls, mid_none, store_ls);
+            // the key's last forward round reads the seed spectrum from LDS; the
+            // barrier at the end of the key's round 0 orders the two.
+        }
+        forward_head(rowA, lds_a);
+        const bool from_lds = mode == 2;
+        auto mid_mul = [&](NoCtx, auto &v, Geo g) PA_INLINE {
+#pragma unroll
+            for (int l = 0; l < group_size(v); ++l) {
+                const double s = (double)(from_lds ? lds_s[g.lbase + l * g.lstep] : ld32(rowH, (g.q0 + (l << g.jl)) * 4));
+                v[l] = mulmod(v[l], s, s * kPinv);
+            }
+        };
+        round_p2<MODE_CONV, false, true, kRowMaxLg>(xd, ftw, itw, nr - 1, 0, pre_none, load_la, mid_mul, store_la);
+    }
     __syncthreads();
     for (int r = nr - 2; r >= 1; --r) {
         round_p2<MODE_INV, false, false, kRowMaxLg>(xd, ftw, itw, r, 0, pre_none, load_la, mid_none, store_la);

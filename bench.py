@@ -14,6 +14,8 @@ Also reported on the same JSON line:
     call (aggregate input Gb/s);
   * batched_uneven: 256 blocks with n log-uniform in [2^18, 2^22] and
     m/n uniform in [0.05, 0.5], own seed each, one batched call;
+  * modified_toeplitz: the S = (I, V) variant at the same shape, one block
+    per call and 256 per batched call;
   * serving: 10,000 requests (n log-uniform in [1e5, 1e7]) against 16
     resident seeds under an open-loop Poisson arrival process, p50/p99/max
     latency at offered loads 0.3/0.5/0.9 and the headline 0.7 of the
@@ -141,6 +143,25 @@ def batched_uneven_run(pa, wl, torch, np, count, stream):
     return {"value": bits / (bms * 1e-3) / 1e9, "unit": "Gb/s", "blocks": count, "ms_per_batch": bms,
             "sum_n": bits, "distinct_lengths": len(lens), "min_len": lens[0], "max_len": lens[-1],
             "shapes": "n = round(2^U(18,22)), m = max(1, round(n U(0.05, 0.5))), own seed per block"}
+
+
+def modified_run(pa, wl, torch, np, n, m, count, stream, steps):
+    """Modified Toeplitz S = (I, V) at the headline shape: one block per call
+    and `count` blocks per batched call (own key and n-1 description bits each)."""
+    key = torch.from_numpy(wl.random_bits(n, wl.rng(6, wl.ROLE_KEY, 0)).view(np.int64)).cuda()
+    v = torch.from_numpy(wl.random_bits(n - 1, wl.rng(6, wl.ROLE_SEED, 0)).view(np.int64)).cuda()
+    out = torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")
+    ms, _ = time_steps(lambda: pa.modified_toeplitz_hash(key, n, v, m, out, stream=stream), steps, 10, torch)
+    blocks = []
+    for i in range(count):
+        k_i = torch.from_numpy(wl.random_bits(n, wl.rng(7, wl.ROLE_KEY, i)).view(np.int64)).cuda()
+        v_i = torch.from_numpy(wl.random_bits(n - 1, wl.rng(7, wl.ROLE_SEED, i)).view(np.int64)).cuda()
+        blocks.append((k_i, n, v_i, m, torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")))
+    bms, _ = time_steps(lambda: pa.modified_toeplitz_hash_batched(blocks, stream=stream), 5, 2, torch)
+    return {"plain_Gbs": n / (ms * 1e-3) / 1e9, "plain_ms_per_block": ms,
+            "batched_Gbs": count * n / (bms * 1e-3) / 1e9, "batched_blocks": count, "batched_ms": bms,
+            "transform_len": pa.transform_len(n - m, m),
+            "definition": "y = x[0:m] ^ V x[m:n], V m x (n-m) Toeplitz of n-1 bits (Eq. 2-3)"}
 
 
 def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30):
@@ -336,6 +357,10 @@ def main():
     if uneven is not None:
         progress("batched uneven: %.3f ms per %d blocks, %.2f Gb/s" % (uneven["ms_per_batch"], args.batch,
                                                                        uneven["value"]))
+    modified = modified_run(pa, wl, torch, np, n, m, args.batch, stream, args.steps) if args.batch > 0 else None
+    if modified is not None:
+        progress("modified Toeplitz: plain %.2f Gb/s, batched %.2f Gb/s" % (modified["plain_Gbs"],
+                                                                          modified["batched_Gbs"]))
     serving = serving_run(pa, wl, torch, np, args.serving, args.load) if args.serving > 0 else None
     if serving is not None:
         progress("serving: done")
@@ -351,7 +376,8 @@ def main():
                    "transform_len": pa.transform_len(n, m)},
         "wall_s_timed_region": wall,
         "roofline": roofline, "roofline_hbm": roofline_hbm, "kernels": kernels,
-        "batched": batched, "batched_uneven": uneven, "serving": serving, "tuning": tuning, "cpu_baseline": cpu,
+        "batched": batched, "batched_uneven": uneven, "modified_toeplitz": modified, "serving": serving,
+        "tuning": tuning, "cpu_baseline": cpu,
         "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(line))

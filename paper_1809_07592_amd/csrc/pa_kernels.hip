@@ -398,6 +398,9 @@ __device__ __forceinline__ JobDesc job_of(const JobArgs &ja, unsigned idx) {
     return j;
 }
 
+// MAXLG: largest radix-2 round of the plan's column transform (3: rounds of
+// at most 8 values, compiled without the 16-value case and its registers).
+template <int MAXLG>
 __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan, JobArgs ja,
                                                 const double2 *__restrict__ ftw) {
     const double2 *itw = nullptr;
@@ -440,16 +443,16 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
     };
     const int nr = xd.nrounds;
     if (nr == 1) {
-        round_p2<MODE_FWD, true, true, kColMaxLg>(xd, ftw, itw, 0, wsh, pre, load_bits, mid, store_glb);
+        round_p2<MODE_FWD, true, true, MAXLG>(xd, ftw, itw, 0, wsh, pre, load_bits, mid, store_glb);
         return;
     }
-    round_p2<MODE_FWD, true, false, kColMaxLg>(xd, ftw, itw, 0, wsh, pre, load_bits, mid, store_lds);
+    round_p2<MODE_FWD, true, false, MAXLG>(xd, ftw, itw, 0, wsh, pre, load_bits, mid, store_lds);
     __syncthreads();
     for (int r = 1; r < nr - 1; ++r) {
-        round_p2<MODE_FWD, false, false, kColMaxLg>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
+        round_p2<MODE_FWD, false, false, MAXLG>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
         __syncthreads();
     }
-    round_p2<MODE_FWD, false, true, kColMaxLg>(xd, ftw, itw, nr - 1, wsh, pre, load_lds, mid, store_glb);
+    round_p2<MODE_FWD, false, true, MAXLG>(xd, ftw, itw, nr - 1, wsh, pre, load_lds, mid, store_glb);
 }
 
 // P2: one row (index blockIdx.x, column-spectrum index k1 = bitrev(row)).
@@ -615,6 +618,7 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
 // multiple of 64, matching the key shift of P1).  Chunks of W bits are
 // written whole for i < 64*ceil(m/64); bits >= m are zero.  blockIdx.y
 // selects the job.
+template <int MAXLG>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_colinv(const LenPlan *__restrict__ plan,
                                                                                        JobArgs ja,
                                                                                        const double2 *__restrict__ itw) {
@@ -680,16 +684,16 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
         }
     };
     if (nr == 1) {
-        round_p2<MODE_INV, true, true, kColMaxLg>(xd, ftw, itw, 0, wsh, pre, load_glb, mid, store_bits);
+        round_p2<MODE_INV, true, true, MAXLG>(xd, ftw, itw, 0, wsh, pre, load_glb, mid, store_bits);
         return;
     }
-    round_p2<MODE_INV, false, true, kColMaxLg>(xd, ftw, itw, nr - 1, wsh, pre, load_glb, mid, store_lds);
+    round_p2<MODE_INV, false, true, MAXLG>(xd, ftw, itw, nr - 1, wsh, pre, load_glb, mid, store_lds);
     __syncthreads();
     for (int r = nr - 2; r >= 1; --r) {
-        round_p2<MODE_INV, false, false, kColMaxLg>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
+        round_p2<MODE_INV, false, false, MAXLG>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
         __syncthreads();
     }
-    round_p2<MODE_INV, true, false, kColMaxLg>(xd, ftw, itw, 0, wsh, pre, load_lds, mid, store_bits);
+    round_p2<MODE_INV, true, false, MAXLG>(xd, ftw, itw, 0, wsh, pre, load_lds, mid, store_bits);
 }
 
 // ----------------------------------------------------------------- launchers
@@ -714,8 +718,8 @@ static hipError_t set_lds_limits(int *limit) {
         const void *fns[] = {(const void *)k_rowconv<0>, (const void *)k_rowconv<1>, (const void *)k_rowconv<2>,
                              (const void *)k_rowconv<3>, (const void *)k_rowconv<4>, (const void *)k_rowconv<5>,
                              (const void *)k_rowconv<6>, (const void *)k_rowconv<7>, (const void *)k_rowconv<8>,
-                             (const void *)k_rowconv<9>, (const void *)k_rowconv<10>, (const void *)k_colfwd,
-                             (const void *)k_colinv};
+                             (const void *)k_rowconv<9>, (const void *)k_rowconv<10>, (const void *)k_colfwd<3>,
+                             (const void *)k_colfwd<4>, (const void *)k_colinv<3>, (const void *)k_colinv<4>};
         for (const void *f : fns) {
             e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
             if (e != hipSuccess) return e;
@@ -726,6 +730,16 @@ static hipError_t set_lds_limits(int *limit) {
     return hipSuccess;
 }
 
+// Largest radix-2 round (log2 of its size) of the column transform.
+static int col_max_lg(const LenPlan &hp) {
+    int mx = 0;
+    for (int r = 0; r < hp.col.nrounds; ++r) {
+        const int k = hp.col.round[r].kind;
+        if (kKindN2[k] > mx) mx = kKindN2[k];
+    }
+    return mx;
+}
+
 hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const JobArgs &ja, int njobs,
                          hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     int limit = 0;
@@ -733,8 +747,11 @@ hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const J
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)hp.col_lds * sizeof(int);
     if (lds > (size_t)limit || nsrc < 1 || nsrc > 2 || njobs < 1 || njobs > 65535) return hipErrorInvalidConfiguration;
-    hipExtLaunchKernelGGL(k_colfwd, dim3((unsigned)hp.ntiles, (unsigned)nsrc, (unsigned)njobs),
-                          dim3((unsigned)hp.col_threads), (uint32_t)lds, s, e0, e1, 0, dp, ja, hp.col.fwd_tw);
+    const dim3 grid((unsigned)hp.ntiles, (unsigned)nsrc, (unsigned)njobs), block((unsigned)hp.col_threads);
+    if (col_max_lg(hp) <= 3)
+        hipExtLaunchKernelGGL(k_colfwd<3>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, hp.col.fwd_tw);
+    else
+        hipExtLaunchKernelGGL(k_colfwd<4>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, hp.col.fwd_tw);
     return hipGetLastError();
 }
 
@@ -820,8 +837,11 @@ hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const JobArgs &ja
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)hp.col_lds * sizeof(int);
     if (lds > (size_t)limit || njobs < 1 || njobs > 65535) return hipErrorInvalidConfiguration;
-    hipExtLaunchKernelGGL(k_colinv, dim3((unsigned)hp.ntiles, (unsigned)njobs), dim3((unsigned)hp.col_threads),
-                          (uint32_t)lds, s, e0, e1, 0, dp, ja, hp.col.inv_tw);
+    const dim3 grid((unsigned)hp.ntiles, (unsigned)njobs), block((unsigned)hp.col_threads);
+    if (col_max_lg(hp) <= 3)
+        hipExtLaunchKernelGGL(k_colinv<3>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, hp.col.inv_tw);
+    else
+        hipExtLaunchKernelGGL(k_colinv<4>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, hp.col.inv_tw);
     return hipGetLastError();
 }
 

@@ -104,6 +104,30 @@ pa_status pa_modified_toeplitz_hash_batched(const pa_block *blocks, uint32_t cou
                                             void *stream);
 
 /*
+ * Graph form of a batched call, for callers that hash the same buffers
+ * again and again (a fixed ring of key/output buffers, a serving slot
+ * table).  pa_graph_create validates the blocks like the batched calls
+ * (modified = 0: pa_toeplitz_hash_batched, 1: the modified form), takes
+ * its own device job table and workspace (see pa_workspace_bytes per
+ * block), and captures every pass launch, across its concurrent stream
+ * lanes, into one HIP graph on a private stream.  pa_graph_launch replays
+ * it on `stream` with a single graph launch: each replay reads the current
+ * contents of the blocks' key and seed buffers and writes their outputs,
+ * so the pointers given at creation must stay valid and must not be
+ * reused for other data while a replay runs.  Replays of one graph must be
+ * ordered (one stream, or synchronized); different graphs are independent.
+ * The graph belongs to the device current at creation.  Errors: as for
+ * the batched calls, PA_ERR_INVALID_ARG for count = 0 or a graph of
+ * another device, PA_ERR_OUT_OF_MEMORY / PA_ERR_DEVICE from allocation or
+ * capture.
+ */
+typedef struct pa_graph_s *pa_graph_t;
+pa_status pa_graph_create(const pa_block *blocks, uint32_t count, int modified, pa_graph_t *graph);
+pa_status pa_graph_launch(pa_graph_t graph, void *stream);
+uint32_t pa_graph_block_count(pa_graph_t graph);
+pa_status pa_graph_destroy(pa_graph_t graph);
+
+/*
  * Final key length for privacy amplification (Sec. 2.1, Eq. 1): with n
  * sifted bits of which Eve may know t, and a security parameter s (her
  * information about the output is at most 2^-s / ln 2), the output length

@@ -109,6 +109,14 @@ def lib():
                 L.pa_modified_toeplitz_hash.restype = st
                 L.pa_modified_toeplitz_hash_batched.argtypes = [ctypes.POINTER(_Block), u32, vp]
                 L.pa_modified_toeplitz_hash_batched.restype = st
+                L.pa_graph_create.argtypes = [ctypes.POINTER(_Block), u32, ctypes.c_int, ctypes.POINTER(vp)]
+                L.pa_graph_create.restype = st
+                L.pa_graph_launch.argtypes = [vp, vp]
+                L.pa_graph_launch.restype = st
+                L.pa_graph_block_count.argtypes = [vp]
+                L.pa_graph_block_count.restype = u32
+                L.pa_graph_destroy.argtypes = [vp]
+                L.pa_graph_destroy.restype = st
                 L.pa_final_key_length.argtypes = [u64, u64, u64]
                 L.pa_final_key_length.restype = u64
                 L.pa_tune_set.argtypes = [u64, u32, u32, u32]
@@ -332,6 +340,44 @@ def modified_toeplitz_hash_batched(blocks, stream=None):
     arr = _blocks(blocks, lambda n, m: (n + 62) >> 6)
     _check(lib().pa_modified_toeplitz_hash_batched(arr, len(blocks), _stream_handle(stream)))
     return [b[4] for b in blocks]
+
+
+class BatchGraph:
+    """Captured batched call over fixed buffers (pa_graph_*); launch() replays it."""
+
+    def __init__(self, blocks, modified: bool = False):
+        if modified:
+            arr = _blocks(blocks, lambda n, m: (n + 62) >> 6)
+        else:
+            arr = _blocks(blocks, lambda n, m: (n + m + 62) >> 6)
+        h = ctypes.c_void_p()
+        _check(lib().pa_graph_create(arr, len(blocks), 1 if modified else 0, ctypes.byref(h)))
+        self._h = h
+        self._keep = list(blocks)   # the buffers the graph reads and writes
+
+    def launch(self, stream=None):
+        _check(lib().pa_graph_launch(self._h, _stream_handle(stream)))
+
+    @property
+    def block_count(self) -> int:
+        return int(lib().pa_graph_block_count(self._h))
+
+    def destroy(self):
+        if self._h:
+            _check(lib().pa_graph_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def final_key_length(n: int, t: int, s: int) -> int:

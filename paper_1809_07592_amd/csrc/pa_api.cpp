@@ -69,9 +69,8 @@ pa_status check_modified(const uint64_t *key, uint64_t n, const uint64_t *v, uin
     return PA_OK;
 }
 
-// Side streams per caller stream for concurrent length groups (with the
-// caller's own stream, four lanes: as many as the default hardware queues).
-constexpr int kSideStreams = 3;
+// Side streams per caller stream for concurrent length groups.
+constexpr int kSideStreams = kMaxLanes - 1;
 
 // Pinned staging slots per caller stream: a call waits only for the copy
 // out of the slot it reuses, so the host can run this many calls ahead.
@@ -155,6 +154,28 @@ pa_status join_lanes(hipStream_t s, int k) {
     return PA_OK;
 }
 
+void release_stream_state(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find({dev, (void *)s});
+    if (it == g_ws.end()) return;
+    Workspace &w = it->second;
+    for (int i = 0; i < kSideStreams; ++i) {
+        if (w.side[i]) (void)hipStreamSynchronize(w.side[i]);
+        if (w.side[i]) (void)hipStreamDestroy(w.side[i]);
+        if (w.join_ev[i]) (void)hipEventDestroy(w.join_ev[i]);
+    }
+    if (w.fork_ev) (void)hipEventDestroy(w.fork_ev);
+    for (StageSlot &sl : w.slot) {
+        if (sl.staged) (void)hipEventSynchronize(sl.staged);
+        if (sl.staged) (void)hipEventDestroy(sl.staged);
+        if (sl.pinned) (void)hipHostFree(sl.pinned);
+    }
+    if (w.ptr) (void)hipFree(w.ptr);
+    g_ws.erase(it);
+}
+
 // Copy `bytes` of host data to device address `dst` on stream s through
 // the next of the stream's pinned staging slots (waits only until the
 // previous copy out of that slot has completed before overwriting it).
@@ -190,6 +211,9 @@ struct ProfRec {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+thread_local bool t_capturing = false;
+
+void set_capturing(bool on) { t_capturing = on; }
 std::vector<ProfRec> g_prof;
 std::vector<hipEvent_t> g_event_pool;
 
@@ -225,7 +249,7 @@ hipError_t timed(const char *name, double bytes, double ops, F &&fn) {
     hipEvent_t a = nullptr, b = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
-        if (g_prof_on) {
+        if (g_prof_on && !t_capturing) {
             a = pool_event();
             b = pool_event();
             if (!a || !b) a = b = nullptr;
@@ -527,10 +551,11 @@ uint64_t pa_final_key_length(uint64_t n, uint64_t t, uint64_t s) {
 namespace pa {
 namespace rt {
 
-// Plain or modified Toeplitz over a block array (see pa_toeplitz_hash_batched).
-pa_status hash_batched(const pa_block *blocks, uint32_t count, hipStream_t s, bool modified) {
-    if (count == 0) return PA_OK;
+// Validation, length groups and plans of a block array (host only).
+pa_status prepare_batch(const pa_block *blocks, uint32_t count, bool modified, BatchPrep *bp) {
     if (!blocks) return fail(PA_ERR_INVALID_ARG, "null block array");
+    bp->modified = modified;
+    bp->blocks.assign(blocks, blocks + count);
     std::vector<uint64_t> lens(count);
     for (uint32_t i = 0; i < count; ++i) {
         const pa_block &b = blocks[i];
@@ -538,47 +563,56 @@ pa_status hash_batched(const pa_block *blocks, uint32_t count, hipStream_t s, bo
                                 : check_block(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, &lens[i]);
         if (st != PA_OK) return fail(st, "block " + std::to_string(i) + ": " + g_last_error);
     }
-    // Group blocks by transform length: one pass sequence per length class.
+    // one pass sequence per length class
     std::map<uint64_t, std::vector<uint32_t>> groups;
     for (uint32_t i = 0; i < count; ++i) groups[lens[i]].push_back(i);
-    std::vector<std::pair<uint64_t, pa::PlanRef>> plans;
+    bp->groups.clear();
     for (auto &g : groups) {
-        pa::PlanRef p{};
-        PA_TRY(plan_for(g.first, g.second.size() > 1 ? 1 : 0, &p));
-        plans.push_back({g.first, p});
+        BatchPrep::Group gr;
+        gr.L = g.first;
+        gr.members = g.second;
+        PA_TRY(plan_for(g.first, g.second.size() > 1 ? 1 : 0, &gr.plan));
+        bp->groups.push_back(std::move(gr));
     }
-    // Workspace: the job table, then 8L bytes (A and S) per block.
-    const size_t table_bytes = ((size_t)count * sizeof(pa::JobDesc) + 255) / 256 * 256;
-    size_t total = table_bytes;
-    for (uint32_t i = 0; i < count; ++i) total += (size_t)(8 * lens[i]);
-    void *ws = nullptr;
-    PA_TRY(get_workspace(s, total, &ws));
-    pa::JobDesc *dtable = (pa::JobDesc *)ws;
-    int32_t *next = (int32_t *)((char *)ws + table_bytes);
-    std::vector<pa::JobDesc> table;
-    table.reserve(count);
-    std::vector<std::pair<size_t, size_t>> spans;  // [first, count) per group, in table order
-    for (auto &g : groups) {
-        spans.push_back({table.size(), g.second.size()});
-        for (uint32_t i : g.second) {
-            const pa_block &b = blocks[i];
-            const uint64_t L = g.first;
-            table.push_back(modified ? modified_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, next, next + L)
-                                     : plain_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, next, next + L));
-            next += 2 * L;
+    // workspace: the job table, then 8L bytes (A and S) per block
+    bp->table_bytes = ((size_t)count * sizeof(pa::JobDesc) + 255) / 256 * 256;
+    bp->total_bytes = bp->table_bytes;
+    for (uint32_t i = 0; i < count; ++i) bp->total_bytes += (size_t)(8 * lens[i]);
+    return PA_OK;
+}
+
+// Job descriptors for workspace `ws` (table order: groups in length order).
+void build_table(BatchPrep &bp, void *ws) {
+    int32_t *next = (int32_t *)((char *)ws + bp.table_bytes);
+    bp.table.clear();
+    bp.table.reserve(bp.blocks.size());
+    size_t first = 0;
+    for (auto &g : bp.groups) {
+        g.first = first;
+        for (uint32_t i : g.members) {
+            const pa_block &b = bp.blocks[i];
+            bp.table.push_back(bp.modified
+                                   ? modified_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, next, next + g.L)
+                                   : plain_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, next, next + g.L));
+            next += 2 * g.L;
         }
+        first += g.members.size();
     }
-    PA_TRY(stage_upload(s, dtable, table.data(), table.size() * sizeof(pa::JobDesc)));
-    // Length groups are independent: spread them over up to 1 + kSideStreams
-    // lanes (largest work first, each to the least-loaded lane) so one
-    // group's tail overlaps the next group's passes.
-    const int ng = (int)groups.size();
+}
+
+// Launches every group's passes against the device job table `dtable`,
+// spread over up to 1 + kSideStreams lanes forked from s (largest work
+// first, each to the least-loaded lane, so one group's tail overlaps the
+// next group's passes) and joined back into s.
+pa_status launch_batch(const BatchPrep &bp, const pa::JobDesc *dtable, hipStream_t s) {
+    const int ng = (int)bp.groups.size();
+    if (ng == 0) return PA_OK;
     const int lanes = std::min(ng, 1 + kSideStreams);
     std::vector<int> order(ng), lane_of(ng, 0);
     std::vector<double> work(ng), load(lanes, 0.0);
     for (int i = 0; i < ng; ++i) {
         order[i] = i;
-        work[i] = (double)plans[i].first * (double)spans[i].second;
+        work[i] = (double)bp.groups[i].L * (double)bp.groups[i].members.size();
     }
     std::sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
     for (int i : order) {
@@ -590,24 +624,38 @@ pa_status hash_batched(const pa_block *blocks, uint32_t count, hipStream_t s, bo
     PA_TRY(fork_lanes(s, lanes, lane_s));
     pa_status st = PA_OK;
     for (int gi : order) {
-        const pa::PlanRef &p = plans[gi].second;
-        const size_t first = spans[gi].first, n = spans[gi].second;
+        const BatchPrep::Group &g = bp.groups[gi];
+        const size_t first = g.first, n = g.members.size();
         for (size_t off = 0; off < n && st == PA_OK; off += 65535) {
             const int nj = (int)std::min<size_t>(65535, n - off);
             pa::JobArgs ja{};
             ja.table = dtable + first + off;
             double in_b = 0, out_b = 0;
             for (size_t k = first + off; k < first + off + (size_t)nj; ++k) {
-                in_b += words8(table[k].n) + words8(table[k].seed_bits) + (modified ? words8(table[k].m) : 0.0);
-                out_b += words8(table[k].m);
+                const pa::JobDesc &j = bp.table[k];
+                in_b += words8(j.n) + words8(j.seed_bits) + (bp.modified ? words8(j.m) : 0.0);
+                out_b += words8(j.m);
             }
-            st = run_plain(p, ja, nj, in_b, out_b, lane_s[lane_of[gi]]);
+            st = run_plain(g.plan, ja, nj, in_b, out_b, lane_s[lane_of[gi]]);
         }
         if (st != PA_OK) break;
     }
     // join even after a failed launch so the caller's stream stays ordered
     pa_status js = join_lanes(s, lanes);
     return st != PA_OK ? st : js;
+}
+
+// Plain or modified Toeplitz over a block array (see pa_toeplitz_hash_batched).
+pa_status hash_batched(const pa_block *blocks, uint32_t count, hipStream_t s, bool modified) {
+    if (count == 0) return PA_OK;
+    BatchPrep bp;
+    PA_TRY(prepare_batch(blocks, count, modified, &bp));
+    void *ws = nullptr;
+    PA_TRY(get_workspace(s, bp.total_bytes, &ws));
+    build_table(bp, ws);
+    pa::JobDesc *dtable = (pa::JobDesc *)ws;
+    PA_TRY(stage_upload(s, dtable, bp.table.data(), bp.table.size() * sizeof(pa::JobDesc)));
+    return launch_batch(bp, dtable, s);
 }
 
 }  // namespace rt

@@ -31,4 +31,9 @@ hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int mode, const 
 hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const JobArgs &ja, int njobs, hipStream_t s,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
+// One-time per-device launch setup for a plan's kernels (LDS opt-in,
+// register counts), so that later launches make no attribute calls (for
+// example inside a stream capture).
+hipError_t warm_launch_state(const LenPlan &hp);
+
 }  // namespace pa

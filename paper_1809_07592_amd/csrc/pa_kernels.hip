@@ -730,6 +730,18 @@ static hipError_t set_lds_limits(int *limit) {
     return hipSuccess;
 }
 
+static hipError_t rowconv_regs(int fk, int *regs);
+
+hipError_t warm_launch_state(const LenPlan &hp) {
+    int limit = 0;
+    hipError_t e = set_lds_limits(&limit);
+    if (e != hipSuccess) return e;
+    const int fk = hp.row.round[0].kind;
+    if (fk < 0 || fk >= kNumKinds) return hipErrorInvalidConfiguration;
+    int regs = 0;
+    return rowconv_regs(fk, &regs);
+}
+
 // Largest radix-2 round (log2 of its size) of the column transform.
 static int col_max_lg(const LenPlan &hp) {
     int mx = 0;

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/pa.h"
 #include "pa_internal.h"
@@ -28,6 +29,10 @@
 
 namespace pa {
 namespace rt {
+
+// Concurrent stream lanes of a batched call: the caller's stream plus
+// side streams (four in all, as many as the default hardware queues).
+constexpr int kMaxLanes = 4;
 
 // Records msg as the calling thread's last error and returns s.
 pa_status fail(pa_status s, const std::string &msg);
@@ -52,9 +57,39 @@ hipError_t p3(const PlanRef &p, const JobArgs &ja, int njobs, double out_bytes, 
 // one length.
 pa_status run_plain(const PlanRef &p, const JobArgs &ja, int njobs, double in_bytes, double out_bytes,
                     hipStream_t s);
+// A validated block array grouped by transform length, with the plans of
+// the groups and the workspace layout (job table, then A and S per block).
+struct BatchPrep {
+    struct Group {
+        uint64_t L = 0;
+        PlanRef plan{};
+        std::vector<uint32_t> members;  // block indices
+        size_t first = 0;               // first table entry (after build_table)
+    };
+    bool modified = false;
+    std::vector<pa_block> blocks;
+    std::vector<Group> groups;
+    std::vector<JobDesc> table;
+    size_t table_bytes = 0, total_bytes = 0;
+};
+pa_status prepare_batch(const pa_block *blocks, uint32_t count, bool modified, BatchPrep *bp);
+// Fills bp.table for workspace `ws` (which must hold bp.total_bytes).
+void build_table(BatchPrep &bp, void *ws);
+// Launches all groups against the device copy of bp.table (lanes forked
+// from and joined back into s).
+pa_status launch_batch(const BatchPrep &bp, const JobDesc *dtable, hipStream_t s);
 // Plain (modified = false) or modified Toeplitz over a host array of
 // blocks: validation, grouping by transform length, concurrent lanes.
 pa_status hash_batched(const pa_block *blocks, uint32_t count, hipStream_t s, bool modified);
+// Lanes for k concurrent streams of work after what is already on s
+// (out[0] = s), and the join of lanes 1..k-1 back into s.
+pa_status fork_lanes(hipStream_t s, int k, hipStream_t *out);
+pa_status join_lanes(hipStream_t s, int k);
+// Drops the side streams and events kept for stream s (before s is destroyed).
+void release_stream_state(hipStream_t s);
+// While set on the calling thread, launches record no timing events
+// (stream capture).
+void set_capturing(bool on);
 // Spectrum of the first nbits seed bits into S (L residues), on stream s.
 pa_status run_seed_path(const PlanRef &p, const uint64_t *seed, uint64_t nbits, int32_t *S, hipStream_t s);
 

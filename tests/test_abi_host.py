@@ -87,6 +87,23 @@ def test_modified_rejects_before_device_work(lib, key, n, v, m, out, status):
     assert "block 0" in pa.last_error()
 
 
+def test_graph_validation(lib):
+    h = ctypes.c_void_p()
+    blocks = (pa._Block * 2)()
+    blocks[0] = pa._Block(FAKE, 100, FAKE, 10, FAKE)
+    blocks[1] = pa._Block(FAKE, 100, FAKE, 101, FAKE)
+    assert lib.pa_graph_create(blocks, 2, 0, ctypes.byref(h)) == pa.PA_ERR_INVALID_ARG
+    assert "block 1" in pa.last_error() and not h.value
+    assert lib.pa_graph_create(blocks, 0, 0, ctypes.byref(h)) == pa.PA_ERR_INVALID_ARG
+    assert lib.pa_graph_create(None, 2, 0, ctypes.byref(h)) == pa.PA_ERR_INVALID_ARG
+    assert lib.pa_graph_create(blocks, 1, 0, None) == pa.PA_ERR_INVALID_ARG
+    blocks[1] = pa._Block(FAKE, 100, FAKE, 100, FAKE)   # m = n: invalid only for the modified form
+    assert lib.pa_graph_create(blocks, 2, 1, ctypes.byref(h)) == pa.PA_ERR_INVALID_ARG
+    assert lib.pa_graph_launch(None, None) == pa.PA_ERR_INVALID_ARG
+    assert lib.pa_graph_destroy(None) == pa.PA_OK
+    assert lib.pa_graph_block_count(None) == 0
+
+
 def test_final_key_length_follows_eq1():
     # r = n - t - s (Eq. 1: s = n - t - r), clamped at 0
     assert pa.final_key_length(1_000_000, 200_000, 100) == 799_900

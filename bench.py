@@ -13,7 +13,8 @@ Also reported on the same JSON line:
   * batched: 256 blocks of the same shape in one pa_toeplitz_hash_batched
     call (aggregate input Gb/s);
   * batched_uneven: 256 blocks with n log-uniform in [2^18, 2^22] and
-    m/n uniform in [0.05, 0.5], own seed each, one batched call;
+    m/n uniform in [0.05, 0.5], own seed each, one batched call (and the
+    same call captured once as a graph and replayed: graph_Gbs);
   * modified_toeplitz: the S = (I, V) variant at the same shape, one block
     per call and 256 per batched call;
   * serving: 10,000 requests (n log-uniform in [1e5, 1e7]) against 16
@@ -140,7 +141,10 @@ def batched_uneven_run(pa, wl, torch, np, count, stream):
     bms, _ = time_steps(step, 5, 2, torch)
     bits = sum(sh.n for sh in shapes)
     lens = sorted({pa.transform_len(sh.n, sh.m) for sh in shapes})
+    with pa.BatchGraph(blocks) as g:          # the same call captured once, replayed
+        gms, _ = time_steps(lambda: g.launch(stream=stream), 5, 2, torch)
     return {"value": bits / (bms * 1e-3) / 1e9, "unit": "Gb/s", "blocks": count, "ms_per_batch": bms,
+            "graph_Gbs": bits / (gms * 1e-3) / 1e9, "graph_ms_per_batch": gms,
             "sum_n": bits, "distinct_lengths": len(lens), "min_len": lens[0], "max_len": lens[-1],
             "shapes": "n = round(2^U(18,22)), m = max(1, round(n U(0.05, 0.5))), own seed per block"}
 
@@ -336,6 +340,8 @@ def main():
         tuning["batched_geometry"] = pa.plan_info(L, *pa.tune_get(L, 1))
         bsteps = max(3, args.steps // 40)
         bms, _ = time_steps(bstep, bsteps, 2, torch)
+        with pa.BatchGraph(blocks) as bgraph:
+            gms, _ = time_steps(lambda: bgraph.launch(stream=stream), bsteps, 2, torch)
         pa.profile_enable(True)
         bstep()
         torch.cuda.synchronize()
@@ -349,7 +355,8 @@ def main():
                         "alu_frac": st["alg_ops"] / st["launches"] / avg_s / 1e12 / FP64_VALU_PEAK_TOPS}
         batched = {"value": args.batch * n / (bms * 1e-3) / 1e9, "unit": "Gb/s", "blocks": args.batch,
                    "ms_per_batch": bms, "kernels": bk,
-                   "speedup_vs_plain": args.batch * n / (bms * 1e-3) / 1e9 / value}
+                   "speedup_vs_plain": args.batch * n / (bms * 1e-3) / 1e9 / value,
+                   "graph_Gbs": args.batch * n / (gms * 1e-3) / 1e9, "graph_ms_per_batch": gms}
         del blocks
         progress("batched: %.3f ms per %d blocks, %.2f Gb/s" % (bms, args.batch, batched["value"]))
 

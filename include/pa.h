@@ -128,6 +128,30 @@ uint32_t pa_graph_block_count(pa_graph_t graph);
 pa_status pa_graph_destroy(pa_graph_t graph);
 
 /*
+ * Floating-point form for two keys that share a seed (the paper's own
+ * arithmetic: Sec. 2.3 Eq. (4) with a double-precision complex FFT, two
+ * real sequences carried by one complex transform as in Sec. 3.2, Eq.
+ * (5)-(10)).  Computes y_a = T x_a and y_b = T x_b for the n+m-1 seed bits
+ * of `seed_bits`: z = x_a + i x_b is convolved with the seed in one complex
+ * FFT of power-of-two length pa_fft_pair_transform_len(n, m) (<= 2^24),
+ * every value of the output window is rounded to the nearest integer and
+ * its parity taken.  *max_error (optional) receives the largest distance
+ * |c - round(c)| over both windows; when it is >= guard (in [0, 0.5]; the
+ * margin 1/4 is the intended value) both outputs are recomputed with the
+ * exact number-theoretic path and *fell_back (optional) is set to 1.  With
+ * the guard the results equal pa_toeplitz_hash's.  Device pointers as for
+ * pa_toeplitz_hash; the two outputs must not overlap.  Unlike the other
+ * calls this one blocks the host until the stream has finished the FFT
+ * pass, to read the error.  Uses the stream's workspace: 32 L bytes plus
+ * 2 m.
+ */
+uint64_t pa_fft_pair_transform_len(uint64_t n, uint64_t m);
+pa_status pa_toeplitz_hash_pair_fft(const uint64_t *key_a, const uint64_t *key_b, uint64_t n,
+                                    const uint64_t *seed_bits, uint64_t m, uint64_t *out_a,
+                                    uint64_t *out_b, double guard, void *stream, double *max_error,
+                                    int *fell_back);
+
+/*
  * Final key length for privacy amplification (Sec. 2.1, Eq. 1): with n
  * sifted bits of which Eve may know t, and a security parameter s (her
  * information about the output is at most 2^-s / ln 2), the output length

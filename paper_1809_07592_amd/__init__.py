@@ -117,6 +117,11 @@ def lib():
                 L.pa_graph_block_count.restype = u32
                 L.pa_graph_destroy.argtypes = [vp]
                 L.pa_graph_destroy.restype = st
+                L.pa_fft_pair_transform_len.argtypes = [u64, u64]
+                L.pa_fft_pair_transform_len.restype = u64
+                L.pa_toeplitz_hash_pair_fft.argtypes = [vp, vp, u64, vp, u64, vp, vp, ctypes.c_double, vp,
+                                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+                L.pa_toeplitz_hash_pair_fft.restype = st
                 L.pa_final_key_length.argtypes = [u64, u64, u64]
                 L.pa_final_key_length.restype = u64
                 L.pa_tune_set.argtypes = [u64, u32, u32, u32]
@@ -378,6 +383,28 @@ class BatchGraph:
             self.destroy()
         except Exception:
             pass
+
+
+def fft_pair_transform_len(n: int, m: int) -> int:
+    return int(lib().pa_fft_pair_transform_len(int(n), int(m)))
+
+
+def toeplitz_hash_pair_fft(key_a, key_b, n: int, seed, m: int, out_a=None, out_b=None, guard: float = 0.25,
+                           stream=None):
+    """Two keys with one seed through one FP64 complex FFT; returns
+    (out_a, out_b, max_error, fell_back).  Blocks until the error is known."""
+    import torch
+    if out_a is None:
+        out_a = torch.empty(max(words(m), 1), dtype=torch.int64, device=key_a.device)
+    if out_b is None:
+        out_b = torch.empty(max(words(m), 1), dtype=torch.int64, device=key_a.device)
+    err = ctypes.c_double()
+    fb = ctypes.c_int()
+    _check(lib().pa_toeplitz_hash_pair_fft(_ptr(key_a, words(n), "key_a"), _ptr(key_b, words(n), "key_b"), int(n),
+                                           _ptr(seed, words(n + m - 1), "seed"), int(m), _ptr(out_a, words(m), "out_a"),
+                                           _ptr(out_b, words(m), "out_b"), float(guard), _stream_handle(stream),
+                                           ctypes.byref(err), ctypes.byref(fb)))
+    return out_a, out_b, err.value, bool(fb.value)
 
 
 def final_key_length(n: int, t: int, s: int) -> int:

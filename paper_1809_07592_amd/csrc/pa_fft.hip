@@ -1,0 +1,205 @@
+// FP64 complex-FFT form of the hash for two keys that share a seed: the
+// floating-point route of the paper (Sec. 2.3 Eq. (4), Sec. 3.1 Fig. 2)
+// with two real sequences carried by one complex transform (Sec. 3.2,
+// Eq. (5)-(10)): z = x_a + i x_b, and since the seed is real,
+// IFFT(FFT(z) FFT(s)) = (s * x_a) + i (s * x_b).  Each convolution value is
+// then rounded to the nearest integer ("round to Boolean", Sec. 3.1) and its
+// parity taken; the largest distance to the rounded value is reported so a
+// caller can check the float result against the 1/4 margin.
+//
+// Layout: the four-step split L = R x C of the number-theoretic path (row-
+// major R x C view, no transposes): column DIF transforms (natural ->
+// bit-reversed rows) with the twist omega_L^(k1 c), row DIF transforms, the
+// pointwise product with the seed spectrum in that same order, row DIT
+// inverses (bit-reversed -> natural), the inverse twist, column DIT
+// inverses.  Transforms are radix-2 in LDS on complex doubles.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pa_fft.h"
+
+namespace pa {
+namespace fft {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(__builtin_fma(a.x, b.x, -a.y * b.y), __builtin_fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
+    return make_double2(__builtin_fma(a.x, b.x, a.y * b.y), __builtin_fma(a.y, b.x, -a.x * b.y));
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// exp(-2 pi i e / L) for 0 <= e < L from the two-level table
+__device__ __forceinline__ double2 twist(const FftPlan &p, uint32_t e) {
+    return cmul(p.tw_lo[e & 4095u], p.tw_hi[e >> 12]);
+}
+
+// Length-N DIF (natural in, bit-reversed out) on `cnt` interleaved
+// transforms in LDS: element j of transform t at x[j * stride + t].
+// tw: exp(-2 pi i k / N), k < N/2.  Ends with a barrier.
+__device__ void dif(double2 *x, int N, int lgN, int cnt, int stride, const double2 *__restrict__ tw) {
+    const int pairs = (N >> 1) * cnt;
+    for (int s = 0; s < lgN; ++s) {
+        const int half = N >> (s + 1);
+        for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
+            const int t = q % cnt, b = q / cnt;
+            const int j = b & (half - 1), blk = b >> (lgN - 1 - s);
+            const int i0 = (blk * 2 * half + j) * stride + t, i1 = i0 + half * stride;
+            const double2 u = x[i0], v = x[i1];
+            x[i0] = cadd(u, v);
+            x[i1] = cmul(csub(u, v), tw[j << s]);
+        }
+        __syncthreads();
+    }
+}
+
+// Length-N DIT inverse without scaling (bit-reversed in, natural out).
+__device__ void dit_inv(double2 *x, int N, int lgN, int cnt, int stride, const double2 *__restrict__ tw) {
+    const int pairs = (N >> 1) * cnt;
+    for (int s = lgN - 1; s >= 0; --s) {
+        const int half = N >> (s + 1);
+        for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
+            const int t = q % cnt, b = q / cnt;
+            const int j = b & (half - 1), blk = b >> (lgN - 1 - s);
+            const int i0 = (blk * 2 * half + j) * stride + t, i1 = i0 + half * stride;
+            const double2 u = x[i0], v = cmulc(x[i1], tw[j << s]);
+            x[i0] = cadd(u, v);
+            x[i1] = csub(u, v);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ double bit_at(const uint64_t *w, int64_t p, int64_t nbits) {
+    if (!w || p < 0 || p >= nbits) return 0.0;
+    return (double)((w[p >> 6] >> (p & 63)) & 1ull);
+}
+
+extern __shared__ double2 fft_lds[];
+
+// Column pass, forward: real part from bits of `a`, imaginary part from
+// bits of `b` (may be null), both read at position p - shift; W-column
+// tile of all R rows; output twisted and stored at its (bit-reversed) row.
+__global__ void __launch_bounds__(256) k_fft_colfwd(FftPlan p, const uint64_t *a, const uint64_t *b, int64_t nbits,
+                                                    int64_t shift, double2 *Z) {
+    const int W = p.W, R = p.R, C = p.C;
+    const int c0 = blockIdx.x * W;
+    double2 *x = fft_lds;
+    for (int e = threadIdx.x; e < R * W; e += blockDim.x) {
+        const int r = e / W, c = e % W;
+        const int64_t q = (int64_t)r * C + c0 + c - shift;
+        x[r * W + c] = make_double2(bit_at(a, q, nbits), bit_at(b, q, nbits));
+    }
+    __syncthreads();
+    dif(x, R, p.log2R, W, W, p.tw_r);
+    for (int e = threadIdx.x; e < R * W; e += blockDim.x) {
+        const int r = e / W, c = e % W;
+        const uint32_t k1 = __builtin_bitreverse32((uint32_t)r) >> (32 - p.log2R);
+        const uint32_t ex = (uint32_t)(((uint64_t)k1 * (uint64_t)(c0 + c)) % p.L);
+        Z[(size_t)r * C + c0 + c] = cmul(x[r * W + c], twist(p, ex));
+    }
+}
+
+// Row pass.  mode 1: Z row <- DIF(row) / L (seed spectrum).  mode 0: Z row
+// <- conj-twist( DIT^-1( DIF(row) * S row ) ).
+__global__ void __launch_bounds__(256) k_fft_row(FftPlan p, double2 *Z, const double2 *S, int mode) {
+    const int C = p.C, row = blockIdx.x;
+    double2 *x = fft_lds;
+    double2 *zr = Z + (size_t)row * C;
+    for (int c = threadIdx.x; c < C; c += blockDim.x) x[c] = zr[c];
+    __syncthreads();
+    dif(x, C, p.log2C, 1, 1, p.tw_c);
+    if (mode == 1) {
+        const double invL = 1.0 / (double)p.L;
+        for (int c = threadIdx.x; c < C; c += blockDim.x) zr[c] = make_double2(x[c].x * invL, x[c].y * invL);
+        return;
+    }
+    const double2 *sr = S + (size_t)row * C;
+    for (int c = threadIdx.x; c < C; c += blockDim.x) x[c] = cmul(x[c], sr[c]);
+    __syncthreads();
+    dit_inv(x, C, p.log2C, 1, 1, p.tw_c);
+    const uint32_t k1 = __builtin_bitreverse32((uint32_t)row) >> (32 - p.log2R);
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        const uint32_t ex = (uint32_t)(((uint64_t)k1 * (uint64_t)c) % p.L);
+        zr[c] = cmulc(x[c], twist(p, ex));
+    }
+}
+
+// Column pass, inverse: natural rows; convolution position r*C + c.  For
+// positions off0 + i, i < m: round both parts, record the distance to the
+// rounded value (max over the launch, as the bits of a nonnegative double
+// in *maxerr), and write the parities as bytes.
+__global__ void __launch_bounds__(256) k_fft_colinv(FftPlan p, const double2 *Z, int64_t off0, int64_t m,
+                                                    uint8_t *bits_a, uint8_t *bits_b, unsigned long long *maxerr) {
+    const int W = p.W, R = p.R, C = p.C;
+    const int c0 = blockIdx.x * W;
+    double2 *x = fft_lds;
+    for (int e = threadIdx.x; e < R * W; e += blockDim.x) {
+        const int r = e / W, c = e % W;
+        x[r * W + c] = Z[(size_t)r * C + c0 + c];
+    }
+    __syncthreads();
+    dit_inv(x, R, p.log2R, W, W, p.tw_r);
+    double err = 0.0;
+    for (int e = threadIdx.x; e < R * W; e += blockDim.x) {
+        const int r = e / W, c = e % W;
+        const int64_t i = (int64_t)r * C + c0 + c - off0;
+        if (i < 0 || i >= m) continue;
+        const double2 v = x[r * W + c];
+        const double ra = rint(v.x), rb = rint(v.y);
+        err = fmax(err, fmax(fabs(v.x - ra), fabs(v.y - rb)));
+        bits_a[i] = (uint8_t)((int64_t)ra & 1);
+        bits_b[i] = (uint8_t)((int64_t)rb & 1);
+    }
+    // wave maximum, then one vector atomic per wave
+    for (int o = 32; o > 0; o >>= 1) err = fmax(err, __shfl_down(err, o, 64));
+    if ((threadIdx.x & 63) == 0 && err > 0.0) atomicMax(maxerr, (unsigned long long)__double_as_longlong(err));
+}
+
+// Packs m parity bytes into ceil(m/64) little-endian words (tail zero).
+__global__ void k_fft_pack(const uint8_t *bits, int64_t m, uint64_t *out) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= (m + 63) / 64) return;
+    uint64_t v = 0;
+    for (int k = 0; k < 64; ++k) {
+        const int64_t i = w * 64 + k;
+        if (i < m) v |= (uint64_t)(bits[i] & 1u) << k;
+    }
+    out[w] = v;
+}
+
+static hipError_t lds_optin(const void *f, size_t bytes) {
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_pair(const FftPlan &p, const uint64_t *key_a, const uint64_t *key_b, int64_t n,
+                       const uint64_t *seed, int64_t m, uint64_t *out_a, uint64_t *out_b, void *ws,
+                       unsigned long long *maxerr, hipStream_t s) {
+    const size_t col_lds = (size_t)p.R * p.W * sizeof(double2), row_lds = (size_t)p.C * sizeof(double2);
+    if (col_lds > kFftMaxLds || row_lds > kFftMaxLds) return hipErrorInvalidConfiguration;
+    hipError_t e = lds_optin((const void *)k_fft_colfwd, kFftMaxLds);
+    if (e == hipSuccess) e = lds_optin((const void *)k_fft_row, kFftMaxLds);
+    if (e == hipSuccess) e = lds_optin((const void *)k_fft_colinv, kFftMaxLds);
+    if (e != hipSuccess) return e;
+    double2 *Z = (double2 *)ws, *S = Z + p.L;
+    uint8_t *bits_a = (uint8_t *)(S + p.L), *bits_b = bits_a + ((m + 255) / 256) * 256;
+    const int64_t off0 = n - 1;  // y_i = c[n - 1 + i]
+    const dim3 cgrid((unsigned)(p.C / p.W)), rgrid((unsigned)p.R), blk(256);
+    e = hipMemsetAsync(maxerr, 0, sizeof(*maxerr), s);
+    if (e != hipSuccess) return e;
+    // seed spectrum (real input), then the key pair
+    hipLaunchKernelGGL(k_fft_colfwd, cgrid, blk, col_lds, s, p, seed, (const uint64_t *)nullptr, n + m - 1,
+                       (int64_t)0, S);
+    hipLaunchKernelGGL(k_fft_row, rgrid, blk, row_lds, s, p, S, (const double2 *)nullptr, 1);
+    hipLaunchKernelGGL(k_fft_colfwd, cgrid, blk, col_lds, s, p, key_a, key_b, n, (int64_t)0, Z);
+    hipLaunchKernelGGL(k_fft_row, rgrid, blk, row_lds, s, p, Z, (const double2 *)S, 0);
+    hipLaunchKernelGGL(k_fft_colinv, cgrid, blk, col_lds, s, p, (const double2 *)Z, off0, m, bits_a, bits_b, maxerr);
+    const unsigned words = (unsigned)((m + 63) / 64);
+    hipLaunchKernelGGL(k_fft_pack, dim3((words + 255) / 256), dim3(256), 0, s, (const uint8_t *)bits_a, m, out_a);
+    hipLaunchKernelGGL(k_fft_pack, dim3((words + 255) / 256), dim3(256), 0, s, (const uint8_t *)bits_b, m, out_b);
+    return hipGetLastError();
+}
+
+}  // namespace fft
+}  // namespace pa

@@ -41,6 +41,9 @@ pa_status from_hip(hipError_t e, const char *what);
 // Host-only validation of one block; *L = its transform length.
 pa_status check_block(const uint64_t *key, uint64_t n, const uint64_t *seed, uint64_t m, const uint64_t *out,
                       uint64_t *L);
+// Library workspace of at least `bytes` for (current device, stream s);
+// growth waits for s so an older buffer is never freed under running work.
+pa_status get_workspace(hipStream_t s, size_t bytes, void **out);
 // Cached device plan of length L in the tuned geometry of batch class cls
 // (0: one block per launch, 1: several).
 pa_status plan_for(uint64_t L, int cls, PlanRef *lp);

@@ -104,6 +104,27 @@ def test_graph_validation(lib):
     assert lib.pa_graph_block_count(None) == 0
 
 
+def test_fft_pair_validation(lib):
+    err, fb = ctypes.c_double(), ctypes.c_int()
+    F2 = FAKE + 4096
+    call = lambda *a: lib.pa_toeplitz_hash_pair_fft(*a, None, ctypes.byref(err), ctypes.byref(fb))
+    assert call(FAKE, F2, 100, FAKE, 10, FAKE, FAKE, 0.25) == pa.PA_ERR_INVALID_ARG      # outputs overlap
+    assert call(FAKE, None, 100, FAKE, 10, FAKE, F2, 0.25) == pa.PA_ERR_INVALID_ARG
+    assert call(FAKE, F2, 100, FAKE, 101, FAKE, F2 + 64, 0.25) == pa.PA_ERR_INVALID_ARG  # m > n
+    assert call(FAKE, F2, 100, FAKE, 10, FAKE, F2 + 64, 0.75) == pa.PA_ERR_INVALID_ARG   # guard > 1/2
+    assert call(FAKE, F2, 100, FAKE, 10, FAKE, F2 + 64, -1.0) == pa.PA_ERR_INVALID_ARG
+    assert call(FAKE, F2, 16_000_000, FAKE, 2_000_000, FAKE, F2 + 64, 0.25) == pa.PA_ERR_UNSUPPORTED_SIZE
+
+
+def test_fft_pair_lengths(lib):
+    # power of two covering the convolution window, at least 2^12, at most 2^24
+    assert pa.fft_pair_transform_len(1, 1) == 4096
+    assert pa.fft_pair_transform_len(1_000_000, 250_000) == 2**21
+    assert pa.fft_pair_transform_len(12_800_000, 1_280_000) == 2**24
+    assert pa.fft_pair_transform_len(16_000_000, 2_000_000) == 0
+    assert pa.fft_pair_transform_len(10, 11) == 0
+
+
 def test_final_key_length_follows_eq1():
     # r = n - t - s (Eq. 1: s = n - t - r), clamped at 0
     assert pa.final_key_length(1_000_000, 200_000, 100) == 799_900

@@ -17,6 +17,8 @@ Also reported on the same JSON line:
     same call captured once as a graph and replayed: graph_Gbs);
   * modified_toeplitz: the S = (I, V) variant at the same shape, one block
     per call and 256 per batched call;
+  * fft_pair: the FP64 complex-FFT form (two keys per transform) with its
+    largest rounding error;
   * serving: 10,000 requests (n log-uniform in [1e5, 1e7]) against 16
     resident seeds under an open-loop Poisson arrival process, p50/p99/max
     latency at offered loads 0.3/0.5/0.9 and the headline 0.7 of the
@@ -166,6 +168,28 @@ def modified_run(pa, wl, torch, np, n, m, count, stream, steps):
             "batched_Gbs": count * n / (bms * 1e-3) / 1e9, "batched_blocks": count, "batched_ms": bms,
             "transform_len": pa.transform_len(n - m, m),
             "definition": "y = x[0:m] ^ V x[m:n], V m x (n-m) Toeplitz of n-1 bits (Eq. 2-3)"}
+
+
+def fft_pair_run(pa, wl, torch, np, n, m, reps):
+    """FP64 complex-FFT form: two keys sharing a seed per call (host waits
+    for the rounding-error check each call)."""
+    ka = torch.from_numpy(wl.random_bits(n, wl.rng(9, wl.ROLE_KEY, 0)).view(np.int64)).cuda()
+    kb = torch.from_numpy(wl.random_bits(n, wl.rng(9, wl.ROLE_KEY, 1)).view(np.int64)).cuda()
+    sd = torch.from_numpy(wl.random_bits(n + m - 1, wl.rng(9, wl.ROLE_SEED, 0)).view(np.int64)).cuda()
+    oa = torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")
+    ob = torch.zeros_like(oa)
+    for _ in range(3):
+        pa.toeplitz_hash_pair_fft(ka, kb, n, sd, m, oa, ob)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    worst, fallbacks = 0.0, 0
+    for _ in range(reps):
+        _, _, err, fb = pa.toeplitz_hash_pair_fft(ka, kb, n, sd, m, oa, ob)
+        worst, fallbacks = max(worst, err), fallbacks + int(fb)
+    el = (time.perf_counter() - t0) / reps
+    return {"Gbs": 2 * n / el / 1e9, "ms_per_pair": el * 1e3, "max_rounding_error": worst, "fallbacks": fallbacks,
+            "transform_len": pa.fft_pair_transform_len(n, m),
+            "definition": "two keys per complex FFT, wall time per call incl. the host-side error check"}
 
 
 def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30):
@@ -368,6 +392,8 @@ def main():
     if modified is not None:
         progress("modified Toeplitz: plain %.2f Gb/s, batched %.2f Gb/s" % (modified["plain_Gbs"],
                                                                           modified["batched_Gbs"]))
+    fftp = fft_pair_run(pa, wl, torch, np, n, m, 50)
+    progress("FFT pair: %.2f Gb/s, max rounding error %.3g" % (fftp["Gbs"], fftp["max_rounding_error"]))
     serving = serving_run(pa, wl, torch, np, args.serving, args.load) if args.serving > 0 else None
     if serving is not None:
         progress("serving: done")
@@ -383,7 +409,8 @@ def main():
                    "transform_len": pa.transform_len(n, m)},
         "wall_s_timed_region": wall,
         "roofline": roofline, "roofline_hbm": roofline_hbm, "kernels": kernels,
-        "batched": batched, "batched_uneven": uneven, "modified_toeplitz": modified, "serving": serving,
+        "batched": batched, "batched_uneven": uneven, "modified_toeplitz": modified, "fft_pair": fftp,
+        "serving": serving,
         "tuning": tuning, "cpu_baseline": cpu,
         "kernel_source_hash": kernel_source_hash(),
     }

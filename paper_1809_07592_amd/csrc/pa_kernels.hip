@@ -208,15 +208,19 @@ __device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, 
     }
 }
 
+// Rounds that keep a scheduling fence between stages: the row pass's
+// mixed first rounds (9 to 27 values), where hoisting every stage's
+// twiddle loads raises register use enough to cost occupancy.  Radix-2
+// rounds of up to 16 values schedule better without it.
+template <int N3, int N2>
+constexpr bool kStageFence = Shape<N3, N2>::RHO > 8 && Shape<N3, N2>::RHO != 16;
+
 template <int N3, int N2, int K, int NA>
 __device__ __forceinline__ void fwd_stages(RegArrN<N3, N2, NA> &v, int b, const XDesc &xd,
                                            const double2 *__restrict__ tw, int s0) {
     if constexpr (K < Shape<N3, N2>::Q) {
         fwd_stage<N3, N2, K, NA>(v, b, tw, xd.fwd_off[s0 + K]);
-        // in groups of more than 8 values, keep the next stage's twiddle
-        // loads from being hoisted above this stage (otherwise all of the
-        // round's twiddles are live at once and occupancy drops)
-        if constexpr (Shape<N3, N2>::RHO > 8) __builtin_amdgcn_sched_barrier(0);
+        if constexpr (kStageFence<N3, N2>) __builtin_amdgcn_sched_barrier(0);
         fwd_stages<N3, N2, K + 1, NA>(v, b, xd, tw, s0);
     }
 }
@@ -226,7 +230,7 @@ __device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast,
                                            const double2 *__restrict__ tw, int s0) {
     if constexpr (K >= 0) {
         inv_stage<N3, N2, K>(v, jj, jlast, tw, xd.inv_off[s0 + K]);
-        if constexpr (Shape<N3, N2>::RHO > 8) __builtin_amdgcn_sched_barrier(0);
+        if constexpr (kStageFence<N3, N2>) __builtin_amdgcn_sched_barrier(0);
         inv_stages<N3, N2, K - 1>(v, jj, jlast, xd, tw, s0);
     }
 }

@@ -15,6 +15,7 @@ Also reported on the same JSON line:
   * batched_uneven: 256 blocks with n log-uniform in [2^18, 2^22] and
     m/n uniform in [0.05, 0.5], own seed each, one batched call (and the
     same call captured once as a graph and replayed: graph_Gbs);
+  * large_block: one block of n = 12.8e6, m = 1.28e6 (plain path);
   * modified_toeplitz: the S = (I, V) variant at the same shape, one block
     per call and 256 per batched call;
   * fft_pair: the FP64 complex-FFT form (two keys per transform) with its
@@ -168,6 +169,20 @@ def modified_run(pa, wl, torch, np, n, m, count, stream, steps):
             "batched_Gbs": count * n / (bms * 1e-3) / 1e9, "batched_blocks": count, "batched_ms": bms,
             "transform_len": pa.transform_len(n - m, m),
             "definition": "y = x[0:m] ^ V x[m:n], V m x (n-m) Toeplitz of n-1 bits (Eq. 2-3)"}
+
+
+def large_block_run(pa, wl, torch, np, stream, steps):
+    """Config 3: one block of n = 12.8e6 key bits, m = 1.28e6 outputs."""
+    n, m = 12_800_000, 1_280_000
+    k, s = wl.key_and_seed(3, n, m, 0)
+    dk = torch.from_numpy(k.view(np.int64)).cuda()
+    ds = torch.from_numpy(s.view(np.int64)).cuda()
+    out = torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")
+    ms, _ = time_steps(lambda: pa.toeplitz_hash(dk, n, ds, m, out, stream=stream), steps, 3, torch)
+    L = pa.transform_len(n, m)
+    g = pa.plan_info(L, *pa.tune_get(L, 0))
+    return {"value": n / (ms * 1e-3) / 1e9, "unit": "Gb/s", "ms_per_block": ms, "n": n, "m": m, "transform_len": L,
+            "rows": g["rows"], "cols": g["cols"], "row_round_size": g["row_round_size"]}
 
 
 def fft_pair_run(pa, wl, torch, np, n, m, reps):
@@ -392,6 +407,8 @@ def main():
     if modified is not None:
         progress("modified Toeplitz: plain %.2f Gb/s, batched %.2f Gb/s" % (modified["plain_Gbs"],
                                                                           modified["batched_Gbs"]))
+    large = large_block_run(pa, wl, torch, np, stream, 20)
+    progress("config 3 (n=12.8e6): %.2f Gb/s" % large["value"])
     fftp = fft_pair_run(pa, wl, torch, np, n, m, 50)
     progress("FFT pair: %.2f Gb/s, max rounding error %.3g" % (fftp["Gbs"], fftp["max_rounding_error"]))
     serving = serving_run(pa, wl, torch, np, args.serving, args.load) if args.serving > 0 else None
@@ -409,7 +426,8 @@ def main():
                    "transform_len": pa.transform_len(n, m)},
         "wall_s_timed_region": wall,
         "roofline": roofline, "roofline_hbm": roofline_hbm, "kernels": kernels,
-        "batched": batched, "batched_uneven": uneven, "modified_toeplitz": modified, "fft_pair": fftp,
+        "batched": batched, "batched_uneven": uneven, "large_block": large, "modified_toeplitz": modified,
+        "fft_pair": fftp,
         "serving": serving,
         "tuning": tuning, "cpu_baseline": cpu,
         "kernel_source_hash": kernel_source_hash(),

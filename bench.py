@@ -171,9 +171,11 @@ def modified_run(pa, wl, torch, np, n, m, count, stream, steps):
             "definition": "y = x[0:m] ^ V x[m:n], V m x (n-m) Toeplitz of n-1 bits (Eq. 2-3)"}
 
 
-def large_block_run(pa, wl, torch, np, stream, steps):
+def large_block_run(pa, wl, torch, np, stream, steps, tune):
     """Config 3: one block of n = 12.8e6 key bits, m = 1.28e6 outputs."""
     n, m = 12_800_000, 1_280_000
+    if tune:
+        pa.autotune(pa.transform_len(n, m), count=1, reps=5, stream=stream)
     k, s = wl.key_and_seed(3, n, m, 0)
     dk = torch.from_numpy(k.view(np.int64)).cuda()
     ds = torch.from_numpy(s.view(np.int64)).cuda()
@@ -407,7 +409,7 @@ def main():
     if modified is not None:
         progress("modified Toeplitz: plain %.2f Gb/s, batched %.2f Gb/s" % (modified["plain_Gbs"],
                                                                           modified["batched_Gbs"]))
-    large = large_block_run(pa, wl, torch, np, stream, 20)
+    large = large_block_run(pa, wl, torch, np, stream, 20, not args.no_tune)
     progress("config 3 (n=12.8e6): %.2f Gb/s" % large["value"])
     fftp = fft_pair_run(pa, wl, torch, np, n, m, 50)
     progress("FFT pair: %.2f Gb/s, max rounding error %.3g" % (fftp["Gbs"], fftp["max_rounding_error"]))

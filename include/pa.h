@@ -124,6 +124,12 @@ pa_status pa_modified_toeplitz_hash_batched(const pa_block *blocks, uint32_t cou
 typedef struct pa_graph_s *pa_graph_t;
 pa_status pa_graph_create(const pa_block *blocks, uint32_t count, int modified, pa_graph_t *graph);
 pa_status pa_graph_launch(pa_graph_t graph, void *stream);
+/* Points the graph at other buffers without capturing again: `blocks`
+ * must form the same length groups as at creation (same count, and per
+ * transform length the same number of blocks; shapes within a group may
+ * differ), else PA_ERR_INVALID_ARG.  The new job table is copied on
+ * `stream`, so replays launched on that stream afterwards use it. */
+pa_status pa_graph_update(pa_graph_t graph, const pa_block *blocks, uint32_t count, void *stream);
 uint32_t pa_graph_block_count(pa_graph_t graph);
 pa_status pa_graph_destroy(pa_graph_t graph);
 

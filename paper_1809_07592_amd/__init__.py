@@ -113,6 +113,8 @@ def lib():
                 L.pa_graph_create.restype = st
                 L.pa_graph_launch.argtypes = [vp, vp]
                 L.pa_graph_launch.restype = st
+                L.pa_graph_update.argtypes = [vp, ctypes.POINTER(_Block), u32, vp]
+                L.pa_graph_update.restype = st
                 L.pa_graph_block_count.argtypes = [vp]
                 L.pa_graph_block_count.restype = u32
                 L.pa_graph_destroy.argtypes = [vp]
@@ -351,14 +353,22 @@ class BatchGraph:
     """Captured batched call over fixed buffers (pa_graph_*); launch() replays it."""
 
     def __init__(self, blocks, modified: bool = False):
-        if modified:
-            arr = _blocks(blocks, lambda n, m: (n + 62) >> 6)
-        else:
-            arr = _blocks(blocks, lambda n, m: (n + m + 62) >> 6)
+        self._modified = bool(modified)
+        arr = self._arr(blocks)
         h = ctypes.c_void_p()
         _check(lib().pa_graph_create(arr, len(blocks), 1 if modified else 0, ctypes.byref(h)))
         self._h = h
         self._keep = list(blocks)   # the buffers the graph reads and writes
+
+    def _arr(self, blocks):
+        if self._modified:
+            return _blocks(blocks, lambda n, m: (n + 62) >> 6)
+        return _blocks(blocks, lambda n, m: (n + m + 62) >> 6)
+
+    def update(self, blocks, stream=None):
+        """Point the graph at other buffers (same length groups)."""
+        _check(lib().pa_graph_update(self._h, self._arr(blocks), len(blocks), _stream_handle(stream)))
+        self._keep = list(blocks)
 
     def launch(self, stream=None):
         _check(lib().pa_graph_launch(self._h, _stream_handle(stream)))

@@ -7,6 +7,8 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/pa.h"
 #include "pa_kernels.h"
@@ -21,6 +23,9 @@ struct pa_graph_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint32_t count = 0;
+    bool modified = false;
+    // length-group signature the launches were captured for: (L, blocks)
+    std::vector<std::pair<uint64_t, size_t>> groups;
 };
 
 namespace {
@@ -55,6 +60,8 @@ pa_status pa_graph_create(const pa_block *blocks, uint32_t count, int modified, 
     pa_graph_s *g = new (std::nothrow) pa_graph_s();
     if (!g) return fail(PA_ERR_OUT_OF_MEMORY, "host allocation");
     g->count = count;
+    g->modified = modified != 0;
+    for (const auto &gr : bp.groups) g->groups.push_back({gr.L, gr.members.size()});
     auto bail = [&](pa_status st) {
         destroy_graph(g);
         return st;
@@ -106,6 +113,24 @@ pa_status pa_graph_launch(pa_graph_t graph, void *stream) {
     if (dev != graph->device) return fail(PA_ERR_INVALID_ARG, "graph belongs to another device");
     PA_HIP(hipGraphLaunch(graph->exec, (hipStream_t)stream), "hipGraphLaunch");
     return PA_OK;
+}
+
+pa_status pa_graph_update(pa_graph_t graph, const pa_block *blocks, uint32_t count, void *stream) {
+    if (!graph) return fail(PA_ERR_INVALID_ARG, "null graph");
+    int dev = 0;
+    PA_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != graph->device) return fail(PA_ERR_INVALID_ARG, "graph belongs to another device");
+    if (count != graph->count) return fail(PA_ERR_INVALID_ARG, "block count differs from the graph's");
+    BatchPrep bp;
+    PA_TRY(prepare_batch(blocks, count, graph->modified, &bp));
+    bool same = bp.groups.size() == graph->groups.size();
+    for (size_t i = 0; same && i < bp.groups.size(); ++i)
+        same = bp.groups[i].L == graph->groups[i].first && bp.groups[i].members.size() == graph->groups[i].second;
+    if (!same) return fail(PA_ERR_INVALID_ARG, "blocks need other transform lengths than the graph was built for");
+    // Same groups give the same table layout (descriptors and 2L residues
+    // per block, in group order); the captured launches keep their plans.
+    build_table(bp, graph->buf);
+    return stage_upload((hipStream_t)stream, graph->buf, bp.table.data(), bp.table.size() * sizeof(pa::JobDesc));
 }
 
 uint32_t pa_graph_block_count(pa_graph_t graph) { return graph ? graph->count : 0; }

@@ -96,3 +96,36 @@ def test_replay_on_a_side_stream_and_recreate():
         for b in blocks:
             b[4].zero_()
         torch.cuda.synchronize()
+
+
+def test_update_points_the_graph_at_new_buffers():
+    shapes = _shapes(65, 8, 13, 17, False)
+    def make(cfg):
+        ins = [wl.key_and_seed(cfg, n, m, i) for i, (n, m) in enumerate(shapes)]
+        bl = [(dev(k), n, dev(s), m, torch.zeros(wl.words(m), dtype=torch.int64, device="cuda"))
+              for (k, s), (n, m) in zip(ins, shapes)]
+        return ins, bl
+    ins1, bl1 = make(66)
+    ins2, bl2 = make(67)
+    with pa.BatchGraph(bl1) as g:
+        g.launch()
+        g.update(bl2)             # same shapes, other buffers
+        g.launch()
+        torch.cuda.synchronize()
+        for (k, s), (n, m), b in zip(ins2, shapes, bl2):
+            assert np.array_equal(host(b[4], m), oracle.toeplitz_hash(k, n, s, m))
+        for (k, s), (n, m), b in zip(ins1, shapes, bl1):
+            assert np.array_equal(host(b[4], m), oracle.toeplitz_hash(k, n, s, m))
+        # reordered blocks form the same groups; a different length does not
+        g.update(bl1[::-1])
+        g.launch()
+        torch.cuda.synchronize()
+        for (k, s), (n, m), b in zip(ins1, shapes, bl1):
+            assert np.array_equal(host(b[4], m), oracle.toeplitz_hash(k, n, s, m))
+        n0, m0 = shapes[0]
+        k0, s0 = wl.key_and_seed(68, 4 * n0, m0, 0)
+        bad = [(dev(k0), 4 * n0, dev(s0), m0, torch.zeros(wl.words(m0), dtype=torch.int64, device="cuda"))] + bl1[1:]
+        with pytest.raises(pa.PAError):
+            g.update(bad)
+        with pytest.raises(pa.PAError):
+            g.update(bl1[:-1])

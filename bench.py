@@ -171,6 +171,16 @@ def modified_run(pa, wl, torch, np, n, m, count, stream, steps):
             "definition": "y = x[0:m] ^ V x[m:n], V m x (n-m) Toeplitz of n-1 bits (Eq. 2-3)"}
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy GB/s (bytes read + written): the practical
+    HBM ceiling beside the 8 TB/s vendor figure."""
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    ms, _ = time_steps(lambda: b.copy_(a), reps, 2, torch)
+    del a, b
+    return {"GBs": 2 * nbytes / (ms * 1e-3) / 1e9, "bytes_copied": nbytes, "ms": ms}
+
+
 def large_block_run(pa, wl, torch, np, stream, steps, tune):
     """Config 3: one block of n = 12.8e6 key bits, m = 1.28e6 outputs."""
     n, m = 12_800_000, 1_280_000
@@ -416,6 +426,8 @@ def main():
     serving = serving_run(pa, wl, torch, np, args.serving, args.load) if args.serving > 0 else None
     if serving is not None:
         progress("serving: done")
+    copy = copy_bandwidth(torch)
+    progress("device copy: %.0f GB/s" % copy["GBs"])
     cpu = None if args.no_cpu else cpu_baseline(key, seed, n, m)
     if cpu is not None:
         progress("cpu baseline: %.4g %s" % (cpu["value"], cpu["unit"]))
@@ -431,7 +443,9 @@ def main():
         "batched": batched, "batched_uneven": uneven, "large_block": large, "modified_toeplitz": modified,
         "fft_pair": fftp,
         "serving": serving,
-        "tuning": tuning, "cpu_baseline": cpu,
+        "tuning": tuning, "copy_bandwidth": copy, "cpu_baseline": cpu,
+        "context": {"paper_Mbps": 116, "paper_setting": "Virtex-6 FPGA at 200 MHz, modified Toeplitz, float FFT, "
+                    "n = 2^20 (input rate; a different variant and hardware, so not a target)"},
         "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(line))

@@ -67,6 +67,9 @@ constexpr int kMaxStages = 24;
 // spectrum) up to 8.
 constexpr int kColMaxLg = 4;
 constexpr int kRowMaxLg = 3;
+// Largest first row round whose kernel carries the seed and key rows
+// together (the plan prefers such first rounds when the length allows).
+constexpr int kRowDualFirstMax = 12;
 
 struct RoundDesc {
     int kind;        // index into kKind*

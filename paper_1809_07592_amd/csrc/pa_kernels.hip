@@ -542,7 +542,7 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
     // rounds together (shared twiddles, two independent chains), and the
     // last round multiplies the key by the reduced seed spectrum in
     // registers before its inverse.
-    constexpr bool kDual = Shape<kKindN3[FK], kKindN2[FK]>::RHO <= 12;
+    constexpr bool kDual = Shape<kKindN3[FK], kKindN2[FK]>::RHO <= kRowDualFirstMax;
     if (kDual && mode == 2) {
         auto load_tw2 = [&](TwCtx t, const Geo &g, int l) PA_INLINE -> double2 {
             const int off = (g.q0 + (l << g.jl)) * 4;

@@ -102,9 +102,16 @@ static int kind_of(int n3, int n2) {
 // smallest round is largest (fewest idle threads when a work item is one
 // group).  maxlg is 4 (16 values per thread) for the column transforms and 3
 // for the row transforms, whose kernel holds more state per thread.
-static std::vector<std::pair<int, int>> split_rounds(int n3, int n2, int maxlg) {
+// first_max > 0: prefer splits whose first round holds at most first_max
+// values, even at the cost of one more round (the row pass carries the
+// seed and key rows together only for such first rounds).
+static std::vector<std::pair<int, int>> split_rounds(int n3, int n2, int maxlg, int first_max = 0) {
     const int cap1[4] = {maxlg, maxlg - 1, 1, 0};
-    const int c1 = cap1[n3];
+    int c1 = cap1[n3];
+    const int p3 = n3 == 0 ? 1 : n3 == 1 ? 3 : n3 == 2 ? 9 : 27;
+    if (first_max > 0 && p3 <= first_max) {
+        while (c1 > 0 && (p3 << c1) > first_max) --c1;
+    }
     if (n2 <= c1 && (n3 > 0 || n2 > 0)) return {{n3, n2}};
     const int nr = 1 + (n2 - c1 + maxlg - 1) / maxlg;
     std::vector<std::pair<int, int>> best;
@@ -148,7 +155,7 @@ struct XTables {
 
 // Descriptor and (optionally) twiddle tables of a length-N transform; pure
 // host code.
-static XDesc describe_xdesc(int N, int maxlg, XTables *tabs) {
+static XDesc describe_xdesc(int N, int maxlg, XTables *tabs, int first_max = 0) {
     XDesc x{};
     x.N = N;
     uint64_t tmp = (uint64_t)N;
@@ -160,7 +167,7 @@ static XDesc describe_xdesc(int N, int maxlg, XTables *tabs) {
     x.nstages = (int)radix.size();
     if (x.nstages > kMaxStages) throw std::runtime_error("too many stages");
 
-    auto rounds = split_rounds(k3, k2, maxlg);
+    auto rounds = split_rounds(k3, k2, maxlg, first_max);
     if ((int)rounds.size() > kMaxRounds) throw std::runtime_error("too many rounds");
     x.nrounds = (int)rounds.size();
     int s = 0;
@@ -288,7 +295,7 @@ void plan_geometry(uint64_t L, int log2R, int Wreq, LenPlan &lp, XTables *ct, XT
     lp.C = (int)(L >> a);
     if ((uint64_t)lp.R * (uint64_t)lp.C != L || lp.C % 64) throw std::runtime_error("bad four-step split");
     lp.col = describe_xdesc(lp.R, kColMaxLg, ct);
-    lp.row = describe_xdesc(lp.C, kRowMaxLg, rt);
+    lp.row = describe_xdesc(lp.C, kRowMaxLg, rt, kRowDualFirstMax);
     if (lp.row.nrounds < 2) throw std::runtime_error("row transform needs at least two rounds");
     const int rho_c0 = lp.col.round[0].M >> lp.col.round[0].jl_log2;
     // Column tile width: the extraction ballots need whole waves per item

@@ -501,9 +501,9 @@ pa_status pa_plan_describe(uint64_t transform_len, uint32_t log2_rows, uint32_t 
     r.col_rounds = (uint32_t)lp.col.nrounds;
     r.row_rounds = (uint32_t)lp.row.nrounds;
     for (int i = 0; i < lp.col.nrounds; ++i)
-        r.col_round_size[i] = (uint32_t)(lp.col.round[i].M >> lp.col.round[i].jl_log2);
+        r.col_round_size[i] = (uint32_t)(lp.col.round[i].M / lp.col.round[i].J);
     for (int i = 0; i < lp.row.nrounds; ++i)
-        r.row_round_size[i] = (uint32_t)(lp.row.round[i].M >> lp.row.round[i].jl_log2);
+        r.row_round_size[i] = (uint32_t)(lp.row.round[i].M / lp.row.round[i].J);
     *info = r;
     return PA_OK;
 }

@@ -74,7 +74,8 @@ constexpr int kRowDualFirstMax = 12;
 struct RoundDesc {
     int kind;        // index into kKind*
     int s0;          // first elementary stage of the round
-    int jl_log2;     // log2 of J_last (stride of the round's last stage)
+    int jl_log2;     // log2 of J_last when it is a power of two (every round but possibly the first)
+    int J;           // J_last, the stride of the round's last stage (first row round: 3 * 2^k allowed)
     int M;           // block size at the round's first stage = RHO * J_last
     int ngroups;     // N / RHO
 };

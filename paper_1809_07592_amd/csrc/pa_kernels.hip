@@ -240,7 +240,7 @@ __device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast,
 // A round visits work items (group g of tile column c).  Each item builds a
 // context with pre(c, b, jj), loads its RHO elements with load(ctx, G, l),
 // runs the round's stages and hands the group to store(ctx, v, G).
-// Element l of the group is transform position G.q0 + (l << G.jl) of tile
+// Element l of the group is transform position G.q0 + l * G.J of tile
 // column G.c; in the padded LDS tile it is at G.lbase + l * G.lstep (the
 // padding q + (q >> lgpad) is affine in l: the stride of every round but
 // the last is a multiple of 2^lgpad, and the last round's block is exactly
@@ -253,7 +253,7 @@ __device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast,
 enum { MODE_FWD = 0, MODE_INV = 1, MODE_CONV = 2 };
 
 struct Geo {
-    int q0, jl, c, lbase, lstep;
+    int q0, J, c, lbase, lstep;
 };
 
 // Opaque copy: stops the compiler from keeping every element address of a
@@ -268,7 +268,7 @@ __device__ __forceinline__ Geo launder(Geo g) {
 // and CONV modes): load returns the (seed, key) pair of element l, both
 // are transformed, mid/store receive both arrays, and in CONV mode only the
 // key array (index 1) is inverse-transformed.
-template <int MODE, int N3, int N2, bool FIRST, bool LAST, int NA = 1, class Pre, class Load, class Mid,
+template <int MODE, int N3, int N2, bool FIRST, bool LAST, int NA = 1, bool GENJ = false, class Pre, class Load, class Mid,
           class Store>
 __device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, const double2 *__restrict__ ftw,
                                          const double2 *__restrict__ itw, int wsh, Pre &pre, Load &load, Mid &mid,
@@ -278,7 +278,9 @@ __device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, c
     const int items = rd.ngroups << wsh;
     const int jl = LAST ? 0 : rd.jl_log2;
     const int lgp = xd.lgpad;
-    const int J = 1 << jl;
+    // GENJ: the first round's stride may be 3 * 2^k (a multiple of 2^lgp, so
+    // the padded LDS index stays affine in l); other strides are powers of two
+    const int J = LAST ? 1 : ((FIRST && GENJ) ? rd.J : 1 << jl);
     const int lstep = LAST ? W : ((J + (J >> lgp)) << wsh);
     // the block index b = item >> (wsh + jl) is the same on all 64 lanes of
     // a wave when wsh + jl >= 6: its twiddles then come from scalar loads
@@ -287,9 +289,9 @@ __device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, c
         const int c = item & (W - 1);
         const int g = item >> wsh;
         const int b = FIRST ? 0 : (g >> jl);
-        const int jj = LAST ? 0 : (g & (J - 1));
+        const int jj = LAST ? 0 : (FIRST ? g : (g & (J - 1)));
         const int q0 = FIRST ? jj : (b * rd.M + jj);
-        Geo G{q0, jl, c, ((q0 + (q0 >> lgp)) << wsh) + c, lstep};
+        Geo G{q0, J, c, ((q0 + (q0 >> lgp)) << wsh) + c, lstep};
         auto ctx = pre(c, b, jj);
         RegArrN<N3, N2, NA> v;
 #pragma unroll
@@ -329,12 +331,22 @@ __device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, c
 
 // Round r of a transform whose rounds are pure radix-2 (kinds 0..3); MAXLG
 // bounds the kinds the plan can give this pass (kColMaxLg / kRowMaxLg).
-template <int MODE, bool FIRST, bool LAST, int MAXLG, int NA = 1, class Pre, class Load, class Mid, class Store>
+// MIX: the plan may also give this pass rounds that hold the last radix-3
+// stage (kinds 3 and 6, after a 9-value first round).
+template <int MODE, bool FIRST, bool LAST, int MAXLG, int NA = 1, bool MIX = false, class Pre, class Load, class Mid,
+          class Store>
 __device__ __forceinline__ void round_p2(const XDesc &xd, const double2 *__restrict__ ftw,
                                          const double2 *__restrict__ itw, int r, int wsh, Pre &pre, Load &load,
                                          Mid &mid, Store &store) {
     const RoundDesc &rd = xd.round[r];
     switch (rd.kind) {
+        case 4:
+            if constexpr (MIX) round_io<MODE, 1, 0, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store);
+            break;
+        case 5:
+            if constexpr (MIX) round_io<MODE, 1, 1, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store);
+            break;
+
         case 0: round_io<MODE, 0, 1, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
         case 1: round_io<MODE, 0, 2, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
         case 2: round_io<MODE, 0, 3, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
@@ -351,7 +363,10 @@ template <int MODE, int FK, bool LAST, int NA = 1, class Pre, class Load, class 
 __device__ __forceinline__ void round_fk(const XDesc &xd, const double2 *__restrict__ ftw,
                                          const double2 *__restrict__ itw, int wsh, Pre &pre, Load &load, Mid &mid,
                                          Store &store) {
-    round_io<MODE, kKindN3[FK], kKindN2[FK], true, LAST, NA>(xd.round[0], xd, ftw, itw, wsh, pre, load, mid, store);
+    // a 9-value first row round leaves a stride of 3 * 2^k
+    constexpr bool kGenJ = kKindN3[FK] == 2;
+    round_io<MODE, kKindN3[FK], kKindN2[FK], true, LAST, NA, kGenJ>(xd.round[0], xd, ftw, itw, wsh, pre, load, mid,
+                                                                  store);
 }
 
 template <class V>
@@ -428,7 +443,7 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
     auto mid = [&](NoCtx, auto &, Geo) PA_INLINE {};
     auto load_bits = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double {
         // branch-free: a negative p reads out of range (0); bits >= nbits are masked
-        const int p = (g.q0 + (l << g.jl)) * C + c0 + g.c - shift;
+        const int p = (g.q0 + (l * g.J)) * C + c0 + g.c - shift;
         const int pr = p + ro;
         const unsigned w = (unsigned)ld32(bits, (pr >> 5) * 4);
         const unsigned bit = (w >> (pr & 31)) & ((unsigned)p < (unsigned)nbits ? 1u : 0u);
@@ -443,7 +458,7 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
     };
     auto store_glb = [&](NoCtx, auto &v, Geo g) PA_INLINE {
 #pragma unroll
-        for (int l = 0; l < group_size(v); ++l) st32(out, ((g.q0 + (l << g.jl)) * C + c0 + g.c) * 4, (int)v[l]);
+        for (int l = 0; l < group_size(v); ++l) st32(out, ((g.q0 + (l * g.J)) * C + c0 + g.c) * 4, (int)v[l]);
     };
     const int nr = xd.nrounds;
     if (nr == 1) {
@@ -477,6 +492,9 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
                                                  const double2 *__restrict__ ftw, const double2 *__restrict__ itw) {
     const LenPlan &lp = *plan;
     const XDesc &xd = lp.row;
+    // a 9-value first round may be followed by a round with the last
+    // radix-3 stage (lengths with 27 | C)
+    constexpr bool kMix = kKindN3[FK] == 2;
     const JobDesc job = job_of(ja, blockIdx.y);
     const int C = lp.C, nr = xd.nrounds;
     const uint32_t row = blockIdx.x;
@@ -505,7 +523,7 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
     // 1 .. last-1 in LDS; the last round is left to the caller.
     auto forward_head = [&](rsrc_t src, int *lds) PA_INLINE {
         auto load_tw = [&](TwCtx t, const Geo &g, int l) PA_INLINE -> double {
-            const double x = (double)ld32(src, (g.q0 + (l << g.jl)) * 4);
+            const double x = (double)ld32(src, (g.q0 + (l * g.J)) * 4);
             const double y = mulmod(x, t.beta.x, t.beta.y);
             const double2 al = ld_tw(rs_af, l);
             return mulmod(y, al.x, al.y);
@@ -518,7 +536,7 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
         round_fk<MODE_FWD, FK, false>(xd, ftw, itw, 0, pre_fwd, load_tw, mid_none, store_l);
         __syncthreads();
         for (int r = 1; r < nr - 1; ++r) {
-            round_p2<MODE_FWD, false, false, kRowMaxLg>(xd, ftw, itw, r, 0, pre_none, load_l, mid_none, store_l);
+            round_p2<MODE_FWD, false, false, kRowMaxLg, 1, kMix>(xd, ftw, itw, r, 0, pre_none, load_l, mid_none, store_l);
             __syncthreads();
         }
     };
@@ -532,9 +550,9 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
         forward_head(rowS, lds_a);
         auto store_g = [&](NoCtx, auto &v, Geo g) PA_INLINE {
 #pragma unroll
-            for (int l = 0; l < group_size(v); ++l) st32(rowS, (g.q0 + (l << g.jl)) * 4, (int)reduce_sym(v[l]));
+            for (int l = 0; l < group_size(v); ++l) st32(rowS, (g.q0 + (l * g.J)) * 4, (int)reduce_sym(v[l]));
         };
-        round_p2<MODE_FWD, false, true, kRowMaxLg>(xd, ftw, itw, nr - 1, 0, pre_none, load_la, mid_none, store_g);
+        round_p2<MODE_FWD, false, true, kRowMaxLg, 1, kMix>(xd, ftw, itw, nr - 1, 0, pre_none, load_la, mid_none, store_g);
         return;
     }
     // Plain path with a first round of at most 12 values: each work item
@@ -545,7 +563,7 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
     constexpr bool kDual = Shape<kKindN3[FK], kKindN2[FK]>::RHO <= kRowDualFirstMax;
     if (kDual && mode == 2) {
         auto load_tw2 = [&](TwCtx t, const Geo &g, int l) PA_INLINE -> double2 {
-            const int off = (g.q0 + (l << g.jl)) * 4;
+            const int off = (g.q0 + (l * g.J)) * 4;
             const double xs = (double)ld32(rowS, off), xa = (double)ld32(rowA, off);
             const double2 al = ld_tw(rs_af, l);
             const double ys = mulmod(xs, t.beta.x, t.beta.y), ya = mulmod(xa, t.beta.x, t.beta.y);
@@ -573,10 +591,10 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
         round_fk<MODE_FWD, FK, false, 2>(xd, ftw, itw, 0, pre_fwd, load_tw2, mid_none, store_l2);
         __syncthreads();
         for (int r = 1; r < nr - 1; ++r) {
-            round_p2<MODE_FWD, false, false, kRowMaxLg, 2>(xd, ftw, itw, r, 0, pre_none, load_l2, mid_none, store_l2);
+            round_p2<MODE_FWD, false, false, kRowMaxLg, 2, kMix>(xd, ftw, itw, r, 0, pre_none, load_l2, mid_none, store_l2);
             __syncthreads();
         }
-        round_p2<MODE_CONV, false, true, kRowMaxLg, 2>(xd, ftw, itw, nr - 1, 0, pre_none, load_l2, mid_mul2,
+        round_p2<MODE_CONV, false, true, kRowMaxLg, 2, kMix>(xd, ftw, itw, nr - 1, 0, pre_none, load_l2, mid_mul2,
                                                         store_la);
     } else {
         if (mode == 2) {
@@ -586,7 +604,7 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
 #pragma unroll
                 for (int l = 0; l < group_size(v); ++l) lds_s[g.lbase + l * g.lstep] = (int)reduce_sym(v[l]);
             };
-            round_p2<MODE_FWD, false, true, kRowMaxLg>(xd, ftw, itw, nr - 1, 0, pre_none, load_ls, mid_none, store_ls);
+            round_p2<MODE_FWD, false, true, kRowMaxLg, 1, kMix>(xd, ftw, itw, nr - 1, 0, pre_none, load_ls, mid_none, store_ls);
             // the key's last forward round reads the seed spectrum from LDS; the
             // barrier at the end of the key's round 0 orders the two.
         }
@@ -595,15 +613,15 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
         auto mid_mul = [&](NoCtx, auto &v, Geo g) PA_INLINE {
 #pragma unroll
             for (int l = 0; l < group_size(v); ++l) {
-                const double s = (double)(from_lds ? lds_s[g.lbase + l * g.lstep] : ld32(rowH, (g.q0 + (l << g.jl)) * 4));
+                const double s = (double)(from_lds ? lds_s[g.lbase + l * g.lstep] : ld32(rowH, (g.q0 + (l * g.J)) * 4));
                 v[l] = mulmod(v[l], s, s * kPinv);
             }
         };
-        round_p2<MODE_CONV, false, true, kRowMaxLg>(xd, ftw, itw, nr - 1, 0, pre_none, load_la, mid_mul, store_la);
+        round_p2<MODE_CONV, false, true, kRowMaxLg, 1, kMix>(xd, ftw, itw, nr - 1, 0, pre_none, load_la, mid_mul, store_la);
     }
     __syncthreads();
     for (int r = nr - 2; r >= 1; --r) {
-        round_p2<MODE_INV, false, false, kRowMaxLg>(xd, ftw, itw, r, 0, pre_none, load_la, mid_none, store_la);
+        round_p2<MODE_INV, false, false, kRowMaxLg, 1, kMix>(xd, ftw, itw, r, 0, pre_none, load_la, mid_none, store_la);
         __syncthreads();
     }
     auto store_tw = [&](TwCtx t, auto &v, Geo g) PA_INLINE {
@@ -611,7 +629,7 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
         for (int l = 0; l < group_size(v); ++l) {
             const double2 al = ld_tw(rs_ai, l);
             const double y = mulmod(v[l], al.x, al.y);
-            st32(rowA, (g.q0 + (l << g.jl)) * 4, (int)mulmod(y, t.beta.x, t.beta.y));
+            st32(rowA, (g.q0 + (l * g.J)) * 4, (int)mulmod(y, t.beta.x, t.beta.y));
         }
     };
     round_fk<MODE_INV, FK, false>(xd, ftw, itw, 0, pre_inv, load_la, mid_none, store_tw);
@@ -641,7 +659,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     auto pre = [&](int, int, int) PA_INLINE { return NoCtx{}; };
     auto mid = [&](NoCtx, auto &, Geo) PA_INLINE {};
     auto load_glb = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double {
-        return (double)ld32(ain, ((g.q0 + (l << g.jl)) * C + c0 + g.c) * 4);
+        return (double)ld32(ain, ((g.q0 + (l * g.J)) * C + c0 + g.c) * 4);
     };
     auto load_lds = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double { return (double)lds[g.lbase + l * g.lstep]; };
     auto store_lds = [&](NoCtx, auto &v, Geo g) PA_INLINE {
@@ -674,7 +692,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
         for (int l = 0; l < group_size(v); ++l) par |= ((uint32_t)(int)canonical(v[l]) & 1u) << l;
 #pragma unroll
         for (int l = 0; l < group_size(v); ++l) {
-            const int pos = (g.q0 + (l << g.jl)) * C + c0 + g.c - off;
+            const int pos = (g.q0 + (l * g.J)) * C + c0 + g.c - off;
             const uint64_t mask = __ballot(((par >> l) & 1u) && pos >= 0 && pos < mm);
             if (g.c == 0 && pos >= 0 && pos < olim) {
                 const uint64_t x = (do_xor && pos < mm) ? xor_chunk(pos) : 0ull;

@@ -112,6 +112,29 @@ static std::vector<std::pair<int, int>> split_rounds(int n3, int n2, int maxlg, 
     if (first_max > 0 && p3 <= first_max) {
         while (c1 > 0 && (p3 << c1) > first_max) --c1;
     }
+    if (first_max > 0 && n3 == 3 && n2 >= 1) {
+        // 27 = 9 * 3: a 9-value first round, then the last radix-3 stage
+        // with at most one radix-2 stage (a round of 3 or 6 values: larger
+        // ones cost the two-row kernel its registers), then radix-2 rounds
+        std::vector<std::pair<int, int>> best;
+        int best_nr = 1 << 30;
+        double best_min = -1;
+        for (int f2 = 0; f2 <= 1 && f2 <= n2; ++f2) {
+            const int rem = n2 - f2;
+            const int rest = (rem + maxlg - 1) / maxlg;
+            std::vector<std::pair<int, int>> cand{{2, 0}, {1, f2}};
+            for (int r = 0; r < rest; ++r) cand.push_back({0, rem / rest + (r < rem % rest ? 1 : 0)});
+            const int nrc = (int)cand.size();
+            double mn = 1e30;
+            for (auto &c : cand) mn = std::min(mn, std::pow(3.0, c.first) * std::pow(2.0, c.second));
+            if (nrc < best_nr || (nrc == best_nr && mn > best_min)) {
+                best_nr = nrc;
+                best_min = mn;
+                best = cand;
+            }
+        }
+        return best;
+    }
     if (n2 <= c1 && (n3 > 0 || n2 > 0)) return {{n3, n2}};
     const int nr = 1 + (n2 - c1 + maxlg - 1) / maxlg;
     std::vector<std::pair<int, int>> best;
@@ -182,7 +205,10 @@ static XDesc describe_xdesc(int N, int maxlg, XTables *tabs, int first_max = 0) 
         rd.s0 = s;
         rd.M = (int)((uint64_t)N / P);
         int jl = rd.M / rho;
-        if (jl * rho != rd.M || (jl & (jl - 1))) throw std::runtime_error("round stride not a power of two");
+        // every round but the first needs a power-of-two stride (its block
+        // index is a shift of the item); the first may be 3 * 2^k
+        if (jl * rho != rd.M || (r > 0 && (jl & (jl - 1)))) throw std::runtime_error("round stride not a power of two");
+        rd.J = jl;
         rd.jl_log2 = __builtin_ctz((unsigned)jl);
         rd.ngroups = N / rho;
         s += n3 + n2;
@@ -190,7 +216,7 @@ static XDesc describe_xdesc(int N, int maxlg, XTables *tabs, int first_max = 0) 
     }
     {
         const RoundDesc &last = x.round[x.nrounds - 1];
-        int rho_last = last.M >> last.jl_log2;
+        int rho_last = last.M / last.J;
         x.lgpad = __builtin_ctz((unsigned)rho_last);
         if (rho_last & (rho_last - 1)) x.lgpad = 4;  // single mixed round: any pad works
     }
@@ -297,7 +323,7 @@ void plan_geometry(uint64_t L, int log2R, int Wreq, LenPlan &lp, XTables *ct, XT
     lp.col = describe_xdesc(lp.R, kColMaxLg, ct);
     lp.row = describe_xdesc(lp.C, kRowMaxLg, rt, kRowDualFirstMax);
     if (lp.row.nrounds < 2) throw std::runtime_error("row transform needs at least two rounds");
-    const int rho_c0 = lp.col.round[0].M >> lp.col.round[0].jl_log2;
+    const int rho_c0 = lp.col.round[0].M / lp.col.round[0].J;
     // Column tile width: the extraction ballots need whole waves per item
     // of the first column round (W * R / rho_c0 >= 64); beyond that as wide
     // as possible while leaving >= 256 tiles and <= 16K elements per tile.
@@ -325,7 +351,7 @@ void plan_geometry(uint64_t L, int log2R, int Wreq, LenPlan &lp, XTables *ct, XT
     lp.row_lds = lp.C + (lp.C >> lp.row.lgpad);
     if (lp.col_lds * 4 > 160 * 1024 || lp.row_lds * 4 > 160 * 1024) throw std::runtime_error("tile does not fit in LDS");
     lp.fused_ok = 2 * lp.row_lds * 4 <= 160 * 1024;
-    lp.rho0 = lp.row.round[0].M >> lp.row.round[0].jl_log2;
+    lp.rho0 = lp.row.round[0].M / lp.row.round[0].J;
 }
 
 // ---------------------------------------------------------------- tuning

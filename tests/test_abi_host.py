@@ -209,10 +209,17 @@ def _check_geometry(d, L):
         prod *= r
     assert prod == R
     prod = 1
-    for i, r in enumerate(d["row_round_size"]):
-        # rows: radix-2 rounds of at most 8 after a first round that takes
-        # all radix-3 stages (at most 27)
-        assert r <= 27 and (i == 0 or r in (2, 4, 8))
+    rr = d["row_round_size"]
+    for i, r in enumerate(rr):
+        # rows: a first round of at most 12 values that takes the radix-3
+        # stages, except that 27 | C splits as 9 then 3 or 6; then radix-2
+        # rounds of at most 8
+        if i == 0:
+            assert r <= 12
+        elif i == 1 and rr[0] == 9 and C % 27 == 0:
+            assert r in (3, 6)
+        else:
+            assert r in (2, 4, 8)
         prod *= r
     assert prod == C and d["row_rounds"] >= 2
     # the output-packing ballots need the first column round to cover

@@ -244,6 +244,28 @@ def test_batched_groups_join_back_into_the_callers_stream():
                 b[4].zero_()
 
 
+def _shape_for(L, ratio=0.25):
+    n = int(L * 0.79) // 64 * 64
+    while pa.transform_len(n, max(1, int(n * ratio))) != L:
+        n -= 64
+    return n, max(1, int(n * ratio))
+
+
+@pytest.mark.parametrize("k", [8, 9, 10, 12, 13])
+def test_lengths_with_27_split_first_rounds(k):
+    # 27 | C: the row transform starts with a 9-value round, then a round
+    # holding the last radix-3 stage (the first round's stride is 3 * 2^j)
+    L = 27 * 2**k
+    info = pa.plan_info(L)
+    assert info["row_round_size"][0] == 9 and info["row_round_size"][1] in (3, 6)
+    n, m = _shape_for(L)
+    key, seed = wl.key_and_seed(26, n, m, k)
+    want = oracle.toeplitz_hash(key, n, seed, m)
+    assert np.array_equal(gpu_hash(key, n, seed, m), want)
+    with pa.Plan(dev(seed), n + m - 1, transform_len=L) as plan:     # seed-spectrum and plan passes
+        assert np.array_equal(host(plan.hash(dev(key), n, m))[: want.size], want)
+
+
 def test_profile_records_every_kernel():
     n, m = 300_000, 60_000
     key, seed = wl.key_and_seed(23, n, m, 0)

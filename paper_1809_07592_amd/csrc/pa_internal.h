@@ -50,10 +50,13 @@ constexpr double kW3i = (double)csym(cpowmod(kGen, 2 * ((kP - 1) / 3)));
 constexpr double kW3ip = kW3i / kPd;
 
 // Round kinds: a round is a group of consecutive elementary stages applied
-// in registers to RHO = 3^n3 * 2^n2 elements.  All radix-3 stages of a
-// transform sit in its first round (so later strides are powers of two);
-// every later round is pure radix-2 with at most 16 elements (larger
-// register groups make the compiler keep a whole round's twiddles live).
+// in registers to RHO = 3^n3 * 2^n2 elements.  The radix-3 stages of a
+// transform come first: all in its first round (so later strides are
+// powers of two), except that a row transform with 27 | C takes a 9-value
+// first round (stride 3 * 2^k) and the last radix-3 stage in a 3- or
+// 6-value second round.  Later rounds are pure radix-2 with at most 16
+// values (columns) or 8 (rows).  Row first rounds hold at most 12 values;
+// kinds 8..10 (18, 27, 24) are described for completeness but not planned.
 constexpr int kNumKinds = 11;
 // (n3, n2) per kind; kinds 0..3 are the pure radix-2 ones
 constexpr int kKindN3[kNumKinds] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3, 1};

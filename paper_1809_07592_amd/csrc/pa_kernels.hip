@@ -555,13 +555,13 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
         round_p2<MODE_FWD, false, true, kRowMaxLg, 1, kMix>(xd, ftw, itw, nr - 1, 0, pre_none, load_la, mid_none, store_g);
         return;
     }
-    // Plain path with a first round of at most 12 values: each work item
-    // carries the seed and key groups of one position through the forward
-    // rounds together (shared twiddles, two independent chains), and the
-    // last round multiplies the key by the reduced seed spectrum in
-    // registers before its inverse.
-    constexpr bool kDual = Shape<kKindN3[FK], kKindN2[FK]>::RHO <= kRowDualFirstMax;
-    if (kDual && mode == 2) {
+    // Plain path: each work item carries the seed and key groups of one
+    // position through the forward rounds together (shared twiddles, two
+    // independent chains), and the last round multiplies the key by the
+    // reduced seed spectrum in registers before its inverse.  (Plans keep
+    // the first row round at <= 12 values so that two groups fit.)
+    static_assert(Shape<kKindN3[FK], kKindN2[FK]>::RHO <= kRowDualFirstMax, "row first round too large");
+    if (mode == 2) {
         auto load_tw2 = [&](TwCtx t, const Geo &g, int l) PA_INLINE -> double2 {
             const int off = (g.q0 + (l * g.J)) * 4;
             const double xs = (double)ld32(rowS, off), xa = (double)ld32(rowA, off);
@@ -597,23 +597,12 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
         round_p2<MODE_CONV, false, true, kRowMaxLg, 2, kMix>(xd, ftw, itw, nr - 1, 0, pre_none, load_l2, mid_mul2,
                                                         store_la);
     } else {
-        if (mode == 2) {
-            forward_head(rowS, lds_s);
-            auto load_ls = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double { return (double)lds_s[g.lbase + l * g.lstep]; };
-            auto store_ls = [&](NoCtx, auto &v, Geo g) PA_INLINE {
-#pragma unroll
-                for (int l = 0; l < group_size(v); ++l) lds_s[g.lbase + l * g.lstep] = (int)reduce_sym(v[l]);
-            };
-            round_p2<MODE_FWD, false, true, kRowMaxLg, 1, kMix>(xd, ftw, itw, nr - 1, 0, pre_none, load_ls, mid_none, store_ls);
-            // the key's last forward round reads the seed spectrum from LDS; the
-            // barrier at the end of the key's round 0 orders the two.
-        }
+        // plan path (mode 0): the key row against the resident spectrum
         forward_head(rowA, lds_a);
-        const bool from_lds = mode == 2;
         auto mid_mul = [&](NoCtx, auto &v, Geo g) PA_INLINE {
 #pragma unroll
             for (int l = 0; l < group_size(v); ++l) {
-                const double s = (double)(from_lds ? lds_s[g.lbase + l * g.lstep] : ld32(rowH, (g.q0 + (l * g.J)) * 4));
+                const double s = (double)ld32(rowH, (g.q0 + (l * g.J)) * 4);
                 v[l] = mulmod(v[l], s, s * kPinv);
             }
         };
@@ -738,10 +727,9 @@ static hipError_t set_lds_limits(int *limit) {
         }
         const int maxb = optin < 160 * 1024 ? optin : 160 * 1024;
         const void *fns[] = {(const void *)k_rowconv<0>, (const void *)k_rowconv<1>, (const void *)k_rowconv<2>,
-                             (const void *)k_rowconv<3>, (const void *)k_rowconv<4>, (const void *)k_rowconv<5>,
-                             (const void *)k_rowconv<6>, (const void *)k_rowconv<7>, (const void *)k_rowconv<8>,
-                             (const void *)k_rowconv<9>, (const void *)k_rowconv<10>, (const void *)k_colfwd<3>,
-                             (const void *)k_colfwd<4>, (const void *)k_colinv<3>, (const void *)k_colinv<4>};
+                             (const void *)k_rowconv<4>, (const void *)k_rowconv<5>, (const void *)k_rowconv<6>,
+                             (const void *)k_rowconv<7>, (const void *)k_colfwd<3>, (const void *)k_colfwd<4>,
+                             (const void *)k_colinv<3>, (const void *)k_colinv<4>};
         for (const void *f : fns) {
             e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
             if (e != hipSuccess) return e;
@@ -790,16 +778,27 @@ hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const J
 }
 
 // VGPRs per thread of k_rowconv<fk> (cached; from the code object).
+// The row pass is instantiated for the first-round kinds plans give it:
+// radix-2 rounds of 2, 4, 8 and the radix-3 kinds of 3, 6, 12, 9 values.
+static const void *rowconv_fn(int fk) {
+    switch (fk) {
+        case 0: return (const void *)k_rowconv<0>;
+        case 1: return (const void *)k_rowconv<1>;
+        case 2: return (const void *)k_rowconv<2>;
+        case 4: return (const void *)k_rowconv<4>;
+        case 5: return (const void *)k_rowconv<5>;
+        case 6: return (const void *)k_rowconv<6>;
+        case 7: return (const void *)k_rowconv<7>;
+        default: return nullptr;
+    }
+}
+
 static hipError_t rowconv_regs(int fk, int *regs) {
     static int cache[kNumKinds];
+    if (!rowconv_fn(fk)) return hipErrorInvalidConfiguration;
     if (cache[fk] == 0) {
-        static const void *fns[kNumKinds] = {
-            (const void *)k_rowconv<0>, (const void *)k_rowconv<1>, (const void *)k_rowconv<2>,
-            (const void *)k_rowconv<3>, (const void *)k_rowconv<4>, (const void *)k_rowconv<5>,
-            (const void *)k_rowconv<6>, (const void *)k_rowconv<7>, (const void *)k_rowconv<8>,
-            (const void *)k_rowconv<9>, (const void *)k_rowconv<10>};
         hipFuncAttributes a{};
-        hipError_t e = hipFuncGetAttributes(&a, fns[fk]);
+        hipError_t e = hipFuncGetAttributes(&a, rowconv_fn(fk));
         if (e != hipSuccess) return e;
         cache[fk] = a.numRegs > 0 ? a.numRegs : 128;
     }
@@ -857,7 +856,7 @@ hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int mode, const 
         hipExtLaunchKernelGGL(k_rowconv<K>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, mode, hp.row.fwd_tw, \
                               hp.row.inv_tw);                                                            \
         break;
-        PA_FK(0) PA_FK(1) PA_FK(2) PA_FK(3) PA_FK(4) PA_FK(5) PA_FK(6) PA_FK(7) PA_FK(8) PA_FK(9) PA_FK(10)
+        PA_FK(0) PA_FK(1) PA_FK(2) PA_FK(4) PA_FK(5) PA_FK(6) PA_FK(7)
 #undef PA_FK
         default: return hipErrorInvalidConfiguration;
     }

@@ -35,15 +35,15 @@ __device__ __forceinline__ double2 twist(const FftPlan &p, uint32_t e) {
     return cmul(p.tw_lo[e & 4095u], p.tw_hi[e >> 12]);
 }
 
-// Length-N DIF (natural in, bit-reversed out) on `cnt` interleaved
+// Length-N DIF (natural in, bit-reversed out) on cnt = 2^lgc interleaved
 // transforms in LDS: element j of transform t at x[j * stride + t].
 // tw: exp(-2 pi i k / N), k < N/2.  Ends with a barrier.
-__device__ void dif(double2 *x, int N, int lgN, int cnt, int stride, const double2 *__restrict__ tw) {
-    const int pairs = (N >> 1) * cnt;
+__device__ void dif(double2 *x, int N, int lgN, int lgc, int stride, const double2 *__restrict__ tw) {
+    const int pairs = (N >> 1) << lgc, cmask = (1 << lgc) - 1;
     for (int s = 0; s < lgN; ++s) {
         const int half = N >> (s + 1);
         for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
-            const int t = q % cnt, b = q / cnt;
+            const int t = q & cmask, b = q >> lgc;
             const int j = b & (half - 1), blk = b >> (lgN - 1 - s);
             const int i0 = (blk * 2 * half + j) * stride + t, i1 = i0 + half * stride;
             const double2 u = x[i0], v = x[i1];
@@ -55,12 +55,12 @@ __device__ void dif(double2 *x, int N, int lgN, int cnt, int stride, const doubl
 }
 
 // Length-N DIT inverse without scaling (bit-reversed in, natural out).
-__device__ void dit_inv(double2 *x, int N, int lgN, int cnt, int stride, const double2 *__restrict__ tw) {
-    const int pairs = (N >> 1) * cnt;
+__device__ void dit_inv(double2 *x, int N, int lgN, int lgc, int stride, const double2 *__restrict__ tw) {
+    const int pairs = (N >> 1) << lgc, cmask = (1 << lgc) - 1;
     for (int s = lgN - 1; s >= 0; --s) {
         const int half = N >> (s + 1);
         for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
-            const int t = q % cnt, b = q / cnt;
+            const int t = q & cmask, b = q >> lgc;
             const int j = b & (half - 1), blk = b >> (lgN - 1 - s);
             const int i0 = (blk * 2 * half + j) * stride + t, i1 = i0 + half * stride;
             const double2 u = x[i0], v = cmulc(x[i1], tw[j << s]);
@@ -81,20 +81,20 @@ extern __shared__ double2 fft_lds[];
 // Column pass, forward: real part from bits of `a`, imaginary part from
 // bits of `b` (may be null), both read at position p - shift; W-column
 // tile of all R rows; output twisted and stored at its (bit-reversed) row.
-__global__ void __launch_bounds__(256) k_fft_colfwd(FftPlan p, const uint64_t *a, const uint64_t *b, int64_t nbits,
+__global__ void __launch_bounds__(1024) k_fft_colfwd(FftPlan p, const uint64_t *a, const uint64_t *b, int64_t nbits,
                                                     int64_t shift, double2 *Z) {
-    const int W = p.W, R = p.R, C = p.C;
+    const int W = p.W, lgW = __builtin_ctz((unsigned)W), R = p.R, C = p.C;
     const int c0 = blockIdx.x * W;
     double2 *x = fft_lds;
     for (int e = threadIdx.x; e < R * W; e += blockDim.x) {
-        const int r = e / W, c = e % W;
+        const int r = e >> lgW, c = e & (W - 1);
         const int64_t q = (int64_t)r * C + c0 + c - shift;
-        x[r * W + c] = make_double2(bit_at(a, q, nbits), bit_at(b, q, nbits));
+        x[e] = make_double2(bit_at(a, q, nbits), bit_at(b, q, nbits));
     }
     __syncthreads();
-    dif(x, R, p.log2R, W, W, p.tw_r);
+    dif(x, R, p.log2R, lgW, W, p.tw_r);
     for (int e = threadIdx.x; e < R * W; e += blockDim.x) {
-        const int r = e / W, c = e % W;
+        const int r = e >> lgW, c = e & (W - 1);
         const uint32_t k1 = __builtin_bitreverse32((uint32_t)r) >> (32 - p.log2R);
         const uint32_t ex = (uint32_t)(((uint64_t)k1 * (uint64_t)(c0 + c)) % p.L);
         Z[(size_t)r * C + c0 + c] = cmul(x[r * W + c], twist(p, ex));
@@ -103,13 +103,13 @@ __global__ void __launch_bounds__(256) k_fft_colfwd(FftPlan p, const uint64_t *a
 
 // Row pass.  mode 1: Z row <- DIF(row) / L (seed spectrum).  mode 0: Z row
 // <- conj-twist( DIT^-1( DIF(row) * S row ) ).
-__global__ void __launch_bounds__(256) k_fft_row(FftPlan p, double2 *Z, const double2 *S, int mode) {
+__global__ void __launch_bounds__(1024) k_fft_row(FftPlan p, double2 *Z, const double2 *S, int mode) {
     const int C = p.C, row = blockIdx.x;
     double2 *x = fft_lds;
     double2 *zr = Z + (size_t)row * C;
     for (int c = threadIdx.x; c < C; c += blockDim.x) x[c] = zr[c];
     __syncthreads();
-    dif(x, C, p.log2C, 1, 1, p.tw_c);
+    dif(x, C, p.log2C, 0, 1, p.tw_c);
     if (mode == 1) {
         const double invL = 1.0 / (double)p.L;
         for (int c = threadIdx.x; c < C; c += blockDim.x) zr[c] = make_double2(x[c].x * invL, x[c].y * invL);
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(256) k_fft_row(FftPlan p, double2 *Z, const do
     const double2 *sr = S + (size_t)row * C;
     for (int c = threadIdx.x; c < C; c += blockDim.x) x[c] = cmul(x[c], sr[c]);
     __syncthreads();
-    dit_inv(x, C, p.log2C, 1, 1, p.tw_c);
+    dit_inv(x, C, p.log2C, 0, 1, p.tw_c);
     const uint32_t k1 = __builtin_bitreverse32((uint32_t)row) >> (32 - p.log2R);
     for (int c = threadIdx.x; c < C; c += blockDim.x) {
         const uint32_t ex = (uint32_t)(((uint64_t)k1 * (uint64_t)c) % p.L);
@@ -130,20 +130,20 @@ __global__ void __launch_bounds__(256) k_fft_row(FftPlan p, double2 *Z, const do
 // positions off0 + i, i < m: round both parts, record the distance to the
 // rounded value (max over the launch, as the bits of a nonnegative double
 // in *maxerr), and write the parities as bytes.
-__global__ void __launch_bounds__(256) k_fft_colinv(FftPlan p, const double2 *Z, int64_t off0, int64_t m,
+__global__ void __launch_bounds__(1024) k_fft_colinv(FftPlan p, const double2 *Z, int64_t off0, int64_t m,
                                                     uint8_t *bits_a, uint8_t *bits_b, unsigned long long *maxerr) {
-    const int W = p.W, R = p.R, C = p.C;
+    const int W = p.W, lgW = __builtin_ctz((unsigned)W), R = p.R, C = p.C;
     const int c0 = blockIdx.x * W;
     double2 *x = fft_lds;
     for (int e = threadIdx.x; e < R * W; e += blockDim.x) {
-        const int r = e / W, c = e % W;
-        x[r * W + c] = Z[(size_t)r * C + c0 + c];
+        const int r = e >> lgW, c = e & (W - 1);
+        x[e] = Z[(size_t)r * C + c0 + c];
     }
     __syncthreads();
-    dit_inv(x, R, p.log2R, W, W, p.tw_r);
+    dit_inv(x, R, p.log2R, lgW, W, p.tw_r);
     double err = 0.0;
     for (int e = threadIdx.x; e < R * W; e += blockDim.x) {
-        const int r = e / W, c = e % W;
+        const int r = e >> lgW, c = e & (W - 1);
         const int64_t i = (int64_t)r * C + c0 + c - off0;
         if (i < 0 || i >= m) continue;
         const double2 v = x[r * W + c];
@@ -157,16 +157,21 @@ __global__ void __launch_bounds__(256) k_fft_colinv(FftPlan p, const double2 *Z,
     if ((threadIdx.x & 63) == 0 && err > 0.0) atomicMax(maxerr, (unsigned long long)__double_as_longlong(err));
 }
 
-// Packs m parity bytes into ceil(m/64) little-endian words (tail zero).
+// Packs m parity bytes into ceil(m/64) little-endian words (tail zero);
+// the byte array is padded to a multiple of 256 bytes.
 __global__ void k_fft_pack(const uint8_t *bits, int64_t m, uint64_t *out) {
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= (m + 63) / 64) return;
+    const uint64_t *b8 = (const uint64_t *)bits + w * 8;  // 64 bytes of 0/1
     uint64_t v = 0;
-    for (int k = 0; k < 64; ++k) {
-        const int64_t i = w * 64 + k;
-        if (i < m) v |= (uint64_t)(bits[i] & 1u) << k;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint64_t x = b8[k];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v |= ((x >> (8 * j)) & 1ull) << (8 * k + j);
     }
-    out[w] = v;
+    const int64_t tail = m - w * 64;
+    out[w] = tail >= 64 ? v : (v & ((1ull << tail) - 1ull));
 }
 
 static hipError_t lds_optin(const void *f, size_t bytes) {
@@ -185,7 +190,7 @@ hipError_t launch_pair(const FftPlan &p, const uint64_t *key_a, const uint64_t *
     double2 *Z = (double2 *)ws, *S = Z + p.L;
     uint8_t *bits_a = (uint8_t *)(S + p.L), *bits_b = bits_a + ((m + 255) / 256) * 256;
     const int64_t off0 = n - 1;  // y_i = c[n - 1 + i]
-    const dim3 cgrid((unsigned)(p.C / p.W)), rgrid((unsigned)p.R), blk(256);
+    const dim3 cgrid((unsigned)(p.C / p.W)), rgrid((unsigned)p.R), blk(1024);
     e = hipMemsetAsync(maxerr, 0, sizeof(*maxerr), s);
     if (e != hipSuccess) return e;
     // seed spectrum (real input), then the key pair

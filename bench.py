@@ -26,8 +26,8 @@ Also reported on the same JSON line:
     measured saturated capacity; every served result compared with the
     same request run alone;
   * roofline of the dominant kernel, from HIP events the library records
-    with each launch on its own stream (algorithmic bytes and fp64
-    operations per launch / average duration);
+    with each launch on its own stream, over a repeat of the timed steps
+    (algorithmic bytes and fp64 operations per launch / average duration);
   * cpu_baseline: the CPU oracle (packed AND + popcount parity) timed on
     this host's cores on full blocks of the same workload.
 
@@ -96,7 +96,7 @@ def time_steps(fn, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def cpu_baseline(key, seed, n, m, budget_s=12.0):
+def cpu_baseline(key, seed, n, m, budget_s=12.0, max_reps=1000):
     import oracle
     oracle.build()
     threads = oracle.max_threads()
@@ -106,7 +106,7 @@ def cpu_baseline(key, seed, n, m, budget_s=12.0):
         oracle.toeplitz_hash(key, n, seed, m, threads=threads)
         reps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or reps >= 200:
+        if el >= budget_s or reps >= max_reps:
             break
     t1 = time.perf_counter()
     oracle.toeplitz_hash(key, n, seed, m, threads=1)
@@ -342,7 +342,11 @@ def main():
     value = n / (ms * 1e-3) / 1e9
     progress("plain path: %.3f ms/step, %.2f Gb/s" % (ms, value))
 
-    # per-kernel timing of the same steps (separate, profiled pass)
+    # Per-kernel timing: the same steps again with the library's event
+    # recording on (HIP events carried by each kernel launch on its stream,
+    # hipExtLaunchKernel).  A separate pass, because recording events costs
+    # the host about 10 us per launch, which would throttle the 40 us step.
+    pa.profile_collect()
     pa.profile_enable(True)
     for _ in range(args.steps):
         step()

@@ -348,10 +348,33 @@ pa_status run_plain(const pa::PlanRef &p, const pa::JobArgs &ja, int njobs, doub
 }
 
 pa_status plan_for(uint64_t L, int cls, pa::PlanRef *lp) {
+    // per-thread memo of the last lookups (plans live until the process
+    // ends, so a cached reference stays valid; a tuning change invalidates)
+    struct Memo {
+        uint64_t L = 0, version = 0;
+        int cls = -1, dev = -1;
+        pa::PlanRef ref{};
+    };
+    thread_local Memo memo[4];
+    thread_local unsigned memo_next = 0;
+    int dev = 0;
+    PA_HIP(hipGetDevice(&dev), "hipGetDevice");
+    const uint64_t ver = pa::tune_version();
+    for (const Memo &mm : memo)
+        if (mm.L == L && mm.cls == cls && mm.dev == dev && mm.version == ver) {
+            *lp = mm.ref;
+            return PA_OK;
+        }
     try {
         int a = 0, w = 0;
         pa::tuned_geometry(L, cls, &a, &w);
         *lp = pa::get_len_plan(L, a, w);
+        Memo &mm = memo[memo_next++ % 4];
+        mm.L = L;
+        mm.cls = cls;
+        mm.dev = dev;
+        mm.version = ver;
+        mm.ref = *lp;
     } catch (const std::bad_alloc &) {
         return fail(PA_ERR_OUT_OF_MEMORY, "allocating transform tables");
     } catch (const std::exception &e) {

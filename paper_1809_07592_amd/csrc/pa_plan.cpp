@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <memory>
@@ -358,6 +359,9 @@ void plan_geometry(uint64_t L, int log2R, int Wreq, LenPlan &lp, XTables *ct, XT
 
 static std::mutex g_tune_mu;
 static std::map<std::pair<uint64_t, int>, std::pair<int, int>> g_tuned;  // (L, class) -> (log2R, W)
+static std::atomic<uint64_t> g_tune_version{1};                       // bumped on every table change
+
+uint64_t tune_version() { return g_tune_version.load(std::memory_order_acquire); }
 
 void tuned_geometry(uint64_t L, int cls, int *log2R, int *W) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -371,11 +375,13 @@ void set_tuned_geometry(uint64_t L, int cls, int log2R, int W) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (log2R == 0 && W == 0) {
         g_tuned.erase({L, cls});
+        g_tune_version.fetch_add(1, std::memory_order_acq_rel);
         return;
     }
     LenPlan lp;
     plan_geometry(L, log2R, W, lp);  // throws for an invalid geometry
     g_tuned[{L, cls}] = {lp.log2R, lp.W};
+    g_tune_version.fetch_add(1, std::memory_order_acq_rel);
 }
 
 std::vector<TunedEntry> tuned_entries() {

@@ -50,5 +50,7 @@ struct TunedEntry {
     int cls, log2R, W;
 };
 std::vector<TunedEntry> tuned_entries();
+// Changes whenever the tuning table does (for caches of plan lookups).
+uint64_t tune_version();
 
 }  // namespace pa

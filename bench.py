@@ -432,6 +432,9 @@ def main():
         progress("serving: done")
     copy = copy_bandwidth(torch)
     progress("device copy: %.0f GB/s" % copy["GBs"])
+    alu = pa.alu_probe(stream)
+    alu["fma_frac_of_peak"] = alu["fma_Tops"] / FP64_VALU_PEAK_TOPS
+    progress("fp64 FMA: %.1f T/s, modular products: %.0f G/s" % (alu["fma_Tops"], alu["mulmod_Gops"]))
     cpu = None if args.no_cpu else cpu_baseline(key, seed, n, m)
     if cpu is not None:
         progress("cpu baseline: %.4g %s" % (cpu["value"], cpu["unit"]))
@@ -447,7 +450,7 @@ def main():
         "batched": batched, "batched_uneven": uneven, "large_block": large, "modified_toeplitz": modified,
         "fft_pair": fftp,
         "serving": serving,
-        "tuning": tuning, "copy_bandwidth": copy, "cpu_baseline": cpu,
+        "tuning": tuning, "copy_bandwidth": copy, "alu_probe": alu, "cpu_baseline": cpu,
         "context": {"paper_Mbps": 116, "paper_setting": "Virtex-6 FPGA at 200 MHz, modified Toeplitz, float FFT, "
                     "n = 2^20 (input rate; a different variant and hardware, so not a target)"},
         "kernel_source_hash": kernel_source_hash(),

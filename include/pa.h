@@ -267,6 +267,16 @@ pa_status pa_tune_save(const char *path);
 pa_status pa_tune_load(const char *path);
 
 /*
+ * Measured vector-ALU ceilings of the current device (the roofline's ALU
+ * roof as achieved rather than as specified): *fma_tops receives the rate
+ * of independent fp64 FMAs (T per second, an FMA counted once) and
+ * *mulmod_gops the rate of the exact three-FMA modular products the
+ * transforms use (G per second), both over every CU at full occupancy.
+ * Runs two short kernels on `stream` and waits for them; about 10 ms.
+ */
+pa_status pa_alu_probe(void *stream, double *fma_tops, double *mulmod_gops);
+
+/*
  * Kernel timing (tracing).  While enabled, the library records a pair of
  * HIP events with every kernel it launches, carrying that kernel's own
  * start and end timestamps on the launch's stream, and notes the launch's algorithmic HBM bytes (what the

@@ -124,6 +124,8 @@ def lib():
                 L.pa_toeplitz_hash_pair_fft.argtypes = [vp, vp, u64, vp, u64, vp, vp, ctypes.c_double, vp,
                                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
                 L.pa_toeplitz_hash_pair_fft.restype = st
+                L.pa_alu_probe.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+                L.pa_alu_probe.restype = st
                 L.pa_final_key_length.argtypes = [u64, u64, u64]
                 L.pa_final_key_length.restype = u64
                 L.pa_tune_set.argtypes = [u64, u32, u32, u32]
@@ -415,6 +417,13 @@ def toeplitz_hash_pair_fft(key_a, key_b, n: int, seed, m: int, out_a=None, out_b
                                            _ptr(out_b, words(m), "out_b"), float(guard), _stream_handle(stream),
                                            ctypes.byref(err), ctypes.byref(fb)))
     return out_a, out_b, err.value, bool(fb.value)
+
+
+def alu_probe(stream=None) -> dict:
+    """Measured fp64 FMA rate (T/s) and exact modular-product rate (G/s)."""
+    f, m = ctypes.c_double(), ctypes.c_double()
+    _check(lib().pa_alu_probe(_stream_handle(stream), ctypes.byref(f), ctypes.byref(m)))
+    return {"fma_Tops": f.value, "mulmod_Gops": m.value}
 
 
 def final_key_length(n: int, t: int, s: int) -> int:

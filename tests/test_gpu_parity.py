@@ -282,3 +282,11 @@ def test_profile_records_every_kernel():
     for st in prof.values():
         assert st["launches"] == 3 and st["avg_ms"] > 0 and st["alg_bytes"] > 0 and st["alg_ops"] > 0
     assert pa.profile_collect() == {}
+
+
+def test_alu_probe_rates_are_plausible():
+    r = pa.alu_probe()
+    # an FMA rate within reach of the 39.3 T/s issue peak, and a modular
+    # product costing about three FMAs
+    assert 5.0 < r["fma_Tops"] < 45.0
+    assert 0.15 < r["mulmod_Gops"] * 1e-3 / r["fma_Tops"] < 0.5

@@ -12,7 +12,7 @@
 // bit-reversed rows) with the twist omega_L^(k1 c), row DIF transforms, the
 // pointwise product with the seed spectrum in that same order, row DIT
 // inverses (bit-reversed -> natural), the inverse twist, column DIT
-// inverses.  Transforms are radix-2 in LDS on complex doubles.
+// inverses.  Transforms run two radix-2 stages per LDS pass on complex doubles.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -37,35 +37,78 @@ __device__ __forceinline__ double2 twist(const FftPlan &p, uint32_t e) {
 
 // Length-N DIF (natural in, bit-reversed out) on cnt = 2^lgc interleaved
 // transforms in LDS: element j of transform t at x[j * stride + t].
-// tw: exp(-2 pi i k / N), k < N/2.  Ends with a barrier.
+// tw: exp(-2 pi i k / N), k < N/2.  Stages s and s+1 are done together
+// (four points per work item: one LDS pass per two stages); an odd last
+// stage alone.  Ends with a barrier.
 __device__ void dif(double2 *x, int N, int lgN, int lgc, int stride, const double2 *__restrict__ tw) {
-    const int pairs = (N >> 1) << lgc, cmask = (1 << lgc) - 1;
-    for (int s = 0; s < lgN; ++s) {
-        const int half = N >> (s + 1);
-        for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
+    const int cmask = (1 << lgc) - 1;
+    int s = 0;
+    for (; s + 1 < lgN; s += 2) {
+        const int half = N >> (s + 1), q4 = half >> 1;     // items: N/4 per transform
+        const int items = (N >> 2) << lgc;
+        for (int q = threadIdx.x; q < items; q += blockDim.x) {
             const int t = q & cmask, b = q >> lgc;
-            const int j = b & (half - 1), blk = b >> (lgN - 1 - s);
-            const int i0 = (blk * 2 * half + j) * stride + t, i1 = i0 + half * stride;
+            const int j = b & (q4 - 1), blk = b >> (lgN - 2 - s);
+            const int i0 = (blk * 2 * half + j) * stride + t;
+            const int d = q4 * stride;
+            const double2 x0 = x[i0], x1 = x[i0 + d], x2 = x[i0 + 2 * d], x3 = x[i0 + 3 * d];
+            const double2 y0 = cadd(x0, x2), y2 = cmul(csub(x0, x2), tw[j << s]);
+            const double2 y1 = cadd(x1, x3), y3 = cmul(csub(x1, x3), tw[(j + q4) << s]);
+            const double2 w2 = tw[j << (s + 1)];
+            x[i0] = cadd(y0, y1);
+            x[i0 + d] = cmul(csub(y0, y1), w2);
+            x[i0 + 2 * d] = cadd(y2, y3);
+            x[i0 + 3 * d] = cmul(csub(y2, y3), w2);
+        }
+        __syncthreads();
+    }
+    if (s < lgN) {  // last stage (half = 1): plain radix-2
+        const int pairs = (N >> 1) << lgc;
+        for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
+            const int t = q & cmask, blk = q >> lgc;
+            const int i0 = (blk * 2) * stride + t, i1 = i0 + stride;
             const double2 u = x[i0], v = x[i1];
             x[i0] = cadd(u, v);
-            x[i1] = cmul(csub(u, v), tw[j << s]);
+            x[i1] = csub(u, v);  // twiddle index 0
         }
         __syncthreads();
     }
 }
 
-// Length-N DIT inverse without scaling (bit-reversed in, natural out).
+// Length-N DIT inverse without scaling (bit-reversed in, natural out); the
+// exact mirror of dif: an odd first stage alone, then stage pairs.
 __device__ void dit_inv(double2 *x, int N, int lgN, int lgc, int stride, const double2 *__restrict__ tw) {
-    const int pairs = (N >> 1) << lgc, cmask = (1 << lgc) - 1;
-    for (int s = lgN - 1; s >= 0; --s) {
-        const int half = N >> (s + 1);
+    const int cmask = (1 << lgc) - 1;
+    int s = lgN - 1;
+    if ((lgN & 1) != 0) {  // stage lgN-1 (half = 1) alone
+        const int pairs = (N >> 1) << lgc;
         for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
-            const int t = q & cmask, b = q >> lgc;
-            const int j = b & (half - 1), blk = b >> (lgN - 1 - s);
-            const int i0 = (blk * 2 * half + j) * stride + t, i1 = i0 + half * stride;
-            const double2 u = x[i0], v = cmulc(x[i1], tw[j << s]);
+            const int t = q & cmask, blk = q >> lgc;
+            const int i0 = (blk * 2) * stride + t, i1 = i0 + stride;
+            const double2 u = x[i0], v = x[i1];
             x[i0] = cadd(u, v);
             x[i1] = csub(u, v);
+        }
+        __syncthreads();
+        --s;
+    }
+    for (; s >= 1; s -= 2) {
+        // stages s (half h) then s-1 (half 2h) on blocks of 4h
+        const int h = N >> (s + 1);
+        const int items = (N >> 2) << lgc;
+        for (int q = threadIdx.x; q < items; q += blockDim.x) {
+            const int t = q & cmask, b = q >> lgc;
+            const int j = b & (h - 1), blk = b >> (lgN - 1 - s);
+            const int i0 = (blk * 4 * h + j) * stride + t;
+            const int d = h * stride;
+            const double2 w1 = tw[j << s];
+            const double2 x0 = x[i0], x1 = cmulc(x[i0 + d], w1), x2 = x[i0 + 2 * d], x3 = cmulc(x[i0 + 3 * d], w1);
+            const double2 y0 = cadd(x0, x1), y1 = csub(x0, x1), y2 = cadd(x2, x3), y3 = csub(x2, x3);
+            const double2 v2 = cmulc(y2, tw[j << (s - 1)]), v3 = cmulc(y3, tw[(j + h) << (s - 1)]);
+            x[i0] = cadd(y0, v2);
+            x[i0 + 2 * d] = csub(y0, v2);
+            x[i0 + d] = cadd(y1, v3);
+            x[i0 + 3 * d] = csub(y1, v3);
         }
         __syncthreads();
     }

@@ -67,14 +67,14 @@ extern "C" pa_status pa_alu_probe(void *stream, double *fma_tops, double *mulmod
     float ms_fma = 0, ms_mm = 0;
     for (int pass = 0; pass < 2 && st == PA_OK; ++pass) {  // pass 0 warms up
         hipLaunchKernelGGL(pa::k_probe_fma, dim3(blocks), dim3(256), 0, s, 1.0000001, 1e-9, sink);
-        hipEventRecord(a, s);
+        if (hipEventRecord(a, s) != hipSuccess) st = PA_ERR_DEVICE;
         hipLaunchKernelGGL(pa::k_probe_fma, dim3(blocks), dim3(256), 0, s, 1.0000001, 1e-9, sink);
-        hipEventRecord(b, s);
-        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms_fma, a, b) != hipSuccess) st = PA_ERR_DEVICE;
-        hipEventRecord(a, s);
+        if (hipEventRecord(b, s) != hipSuccess) st = PA_ERR_DEVICE;
+        if (st != PA_OK || hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms_fma, a, b) != hipSuccess) st = PA_ERR_DEVICE;
+        if (hipEventRecord(a, s) != hipSuccess) st = PA_ERR_DEVICE;
         hipLaunchKernelGGL(pa::k_probe_mulmod, dim3(blocks), dim3(256), 0, s, w, wp, sink);
-        hipEventRecord(b, s);
-        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms_mm, a, b) != hipSuccess) st = PA_ERR_DEVICE;
+        if (hipEventRecord(b, s) != hipSuccess) st = PA_ERR_DEVICE;
+        if (st != PA_OK || hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms_mm, a, b) != hipSuccess) st = PA_ERR_DEVICE;
     }
     if (st == PA_OK && hipGetLastError() != hipSuccess) st = PA_ERR_DEVICE;
     const double threads = (double)blocks * 256.0, work = threads * pa::kChains * pa::kProbeIters;

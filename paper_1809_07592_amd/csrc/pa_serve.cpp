@@ -7,9 +7,11 @@
 // pool can hold their workspace and fewer than max_inflight are running;
 // (3) launches all newly admitted requests as one batched plan-path pass
 // sequence (key column pass, row convolution against the resident seed
-// spectrum, extraction; one launch per pass and transform length) on the
-// next stream.  Batches of successive iterations run on different streams,
-// so work admitted while earlier work is on the device overlaps with it.
+// spectrum, extraction; one launch per pass and transform length, smallest
+// length first) on the next stream.  Each length group completes on its own
+// event, so small requests do not wait for a large one admitted with them.
+// Batches of successive iterations run on different streams, so work
+// admitted while earlier work is on the device overlaps with it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -89,9 +91,19 @@ struct Req {
     bool done = false;
 };
 
-struct Batch {
+// One length group of a batch.  Groups run in order on the batch's stream,
+// smallest length first; a group's requests complete when the event
+// recorded after its last pass fires, not when the whole batch does.
+struct Part {
     std::vector<Req *> reqs;
     hipEvent_t ev = nullptr;
+    bool done = false;
+};
+
+struct Batch {
+    std::vector<Req *> reqs;
+    std::vector<Part> parts;  // in stream order
+    size_t parts_done = 0;
     Clock::time_point sim_done;
 };
 
@@ -140,8 +152,12 @@ struct pa_server_s {
     pa_server_stats st{};
     std::string error;  // first scheduler failure
 
+    std::vector<hipEvent_t> spare_events;  // completion events for reuse
+
     void loop();
     bool retire_locked();
+    hipError_t take_event(hipEvent_t *ev);
+    void complete_locked(Req *r, Clock::time_point t);
     pa_status launch(std::vector<Req *> &batch_reqs, Batch *b);
     pa_status spectrum_for(uint32_t seed, uint64_t L, const Spectrum **out);
 };
@@ -172,8 +188,21 @@ pa_status pa_server_s::spectrum_for(uint32_t seed, uint64_t L, const Spectrum **
     return PA_OK;
 }
 
+hipError_t pa_server_s::take_event(hipEvent_t *ev) {
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!spare_events.empty()) {
+            *ev = spare_events.back();
+            spare_events.pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipEventCreateWithFlags(ev, hipEventDisableTiming);
+}
+
 // Launches the admitted requests (already holding workspace offsets) as
-// one batch; fills b->ev.
+// one batch; fills b->parts, one per length group, each with the event
+// recorded after the group's last pass.
 pa_status pa_server_s::launch(std::vector<Req *> &rs, Batch *b) {
     StreamCtx &sc = streams[next_stream];
     next_stream = (next_stream + 1) % streams.size();
@@ -182,6 +211,7 @@ pa_status pa_server_s::launch(std::vector<Req *> &rs, Batch *b) {
     struct Group {
         pa::PlanRef plan;
         size_t count;
+        std::vector<Req *> reqs;
     };
     std::vector<Group> groups;
     std::vector<std::pair<Req *, const Spectrum *>> order;
@@ -202,9 +232,9 @@ pa_status pa_server_s::launch(std::vector<Req *> &rs, Batch *b) {
         j.Shat = o.second->S;
         table.push_back(j);
         if (groups.empty() || groups.back().plan.host != o.second->plan.host)
-            groups.push_back({o.second->plan, 1});
-        else
-            groups.back().count++;
+            groups.push_back({o.second->plan, 0, {}});
+        groups.back().count++;
+        groups.back().reqs.push_back(r);
     }
     if (table.size() > sc.cap) return fail(PA_ERR_DEVICE, "job table overflow");
     if (sc.staged) {
@@ -230,12 +260,31 @@ pa_status pa_server_s::launch(std::vector<Req *> &rs, Batch *b) {
         e = p1(p, 1, ja, nj, in_b, sc.s);
         if (e == hipSuccess) e = p2(p, 0, ja, nj, sc.s);
         if (e == hipSuccess) e = p3(p, ja, nj, out_b, sc.s);
-        if (e != hipSuccess) return from_hip(e, "batch launch");
+        Part part;
+        part.reqs = std::move(g.reqs);
+        if (e == hipSuccess) e = take_event(&part.ev);
+        if (e == hipSuccess) {
+            b->parts.push_back(std::move(part));
+            e = hipEventRecord(b->parts.back().ev, sc.s);
+        }
+        if (e != hipSuccess) {
+            // let the passes already queued finish before the caller hands
+            // their workspace back to the pool
+            (void)hipStreamSynchronize(sc.s);
+            return from_hip(e, "batch launch");
+        }
         first += g.count;
     }
-    e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(b->ev, sc.s);
-    return from_hip(e, "batch event");
+    return PA_OK;
+}
+
+void pa_server_s::complete_locked(Req *r, Clock::time_point t) {
+    r->t_done = t;
+    r->done = true;
+    pool->release(r->ws_off, r->need);
+    st.completed++;
+    st.inflight--;
+    st.input_bits_completed += r->n;
 }
 
 // Retires finished batches (lock held).  Returns true if any finished.
@@ -244,27 +293,31 @@ bool pa_server_s::retire_locked() {
     const auto now = Clock::now();
     for (size_t i = 0; i < running.size();) {
         Batch &b = running[i];
-        bool fin;
-        if (sim)
-            fin = now >= b.sim_done;
-        else
-            fin = hipEventQuery(b.ev) == hipSuccess;
-        if (!fin) {
-            ++i;
+        if (sim) {
+            if (now >= b.sim_done) {
+                for (Req *r : b.reqs) complete_locked(r, now);
+                b.parts_done = b.parts.size();
+                any = true;
+            }
+        } else {
+            // parts finish in stream order: stop at the first one still running
+            while (b.parts_done < b.parts.size()) {
+                Part &pt = b.parts[b.parts_done];
+                if (hipEventQuery(pt.ev) != hipSuccess) break;
+                const auto t = Clock::now();
+                for (Req *r : pt.reqs) complete_locked(r, t);
+                spare_events.push_back(pt.ev);
+                pt.ev = nullptr;
+                pt.done = true;
+                b.parts_done++;
+                any = true;
+            }
+        }
+        if (b.parts_done == b.parts.size()) {
+            running.erase(running.begin() + (long)i);
             continue;
         }
-        const auto t = Clock::now();
-        for (Req *r : b.reqs) {
-            r->t_done = t;
-            r->done = true;
-            pool->release(r->ws_off, r->need);
-            st.completed++;
-            st.inflight--;
-            st.input_bits_completed += r->n;
-        }
-        if (b.ev) (void)hipEventDestroy(b.ev);
-        running.erase(running.begin() + (long)i);
-        any = true;
+        ++i;
     }
     st.bytes_in_flight = pool->used();
     return any;
@@ -303,6 +356,7 @@ void pa_server_s::loop() {
             double us = 0;
             for (Req *r : admitted) us += (double)r->n / std::max(cfg.sim_bits_per_us, 1e-9);
             b.sim_done = Clock::now() + std::chrono::microseconds((int64_t)us);
+            b.parts.resize(1);
         } else {
             pa_status stt = launch(b.reqs, &b);
             if (stt != PA_OK) {
@@ -315,6 +369,8 @@ void pa_server_s::loop() {
                     pool->release(r->ws_off, r->need);
                     st.inflight--;
                 }
+                for (Part &pt : b.parts)
+                    if (pt.ev) spare_events.push_back(pt.ev);
                 cv_done.notify_all();
                 continue;
             }
@@ -476,6 +532,7 @@ pa_status pa_server_destroy(pa_server_t s) {
             if (sc.pinned) (void)hipHostFree(sc.pinned);
             if (sc.s) (void)hipStreamDestroy(sc.s);
         }
+        for (hipEvent_t ev : s->spare_events) (void)hipEventDestroy(ev);
         for (auto &sd : s->seeds)
             for (auto &kv : sd.spectra) (void)hipFree(kv.second.S);
         if (s->plan_stream) (void)hipStreamDestroy(s->plan_stream);

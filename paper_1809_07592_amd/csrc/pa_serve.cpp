@@ -104,6 +104,7 @@ struct Batch {
     std::vector<Req *> reqs;
     std::vector<Part> parts;  // in stream order
     size_t parts_done = 0;
+    size_t stream = 0;        // index into the server's streams
     Clock::time_point sim_done;
 };
 
@@ -138,7 +139,7 @@ struct pa_server_s {
     std::unique_ptr<Pool> pool;
     std::vector<StreamCtx> streams;
     hipStream_t plan_stream = nullptr;
-    size_t next_stream = 0;
+    std::vector<uint64_t> stream_bits;  // input bits queued or running per stream
     std::vector<Seed> seeds;
 
     std::mutex mu;
@@ -157,7 +158,7 @@ struct pa_server_s {
     void loop();
     bool retire_locked();
     hipError_t take_event(hipEvent_t *ev);
-    void complete_locked(Req *r, Clock::time_point t);
+    void complete_locked(Req *r, Clock::time_point t, size_t stream);
     pa_status launch(std::vector<Req *> &batch_reqs, Batch *b);
     pa_status spectrum_for(uint32_t seed, uint64_t L, const Spectrum **out);
 };
@@ -204,8 +205,7 @@ hipError_t pa_server_s::take_event(hipEvent_t *ev) {
 // one batch; fills b->parts, one per length group, each with the event
 // recorded after the group's last pass.
 pa_status pa_server_s::launch(std::vector<Req *> &rs, Batch *b) {
-    StreamCtx &sc = streams[next_stream];
-    next_stream = (next_stream + 1) % streams.size();
+    StreamCtx &sc = streams[b->stream];
     std::vector<pa::JobDesc> table;
     // one pass sequence per (length, geometry) group, in table order
     struct Group {
@@ -278,7 +278,8 @@ pa_status pa_server_s::launch(std::vector<Req *> &rs, Batch *b) {
     return PA_OK;
 }
 
-void pa_server_s::complete_locked(Req *r, Clock::time_point t) {
+void pa_server_s::complete_locked(Req *r, Clock::time_point t, size_t stream) {
+    stream_bits[stream] -= r->n;
     r->t_done = t;
     r->done = true;
     pool->release(r->ws_off, r->need);
@@ -295,7 +296,7 @@ bool pa_server_s::retire_locked() {
         Batch &b = running[i];
         if (sim) {
             if (now >= b.sim_done) {
-                for (Req *r : b.reqs) complete_locked(r, now);
+                for (Req *r : b.reqs) complete_locked(r, now, b.stream);
                 b.parts_done = b.parts.size();
                 any = true;
             }
@@ -305,7 +306,7 @@ bool pa_server_s::retire_locked() {
                 Part &pt = b.parts[b.parts_done];
                 if (hipEventQuery(pt.ev) != hipSuccess) break;
                 const auto t = Clock::now();
-                for (Req *r : pt.reqs) complete_locked(r, t);
+                for (Req *r : pt.reqs) complete_locked(r, t, b.stream);
                 spare_events.push_back(pt.ev);
                 pt.ev = nullptr;
                 pt.done = true;
@@ -352,6 +353,13 @@ void pa_server_s::loop() {
         }
         Batch b;
         b.reqs = admitted;
+        {
+            // the stream with the least input queued or running, so a batch
+            // does not wait behind a large one while another stream is idle
+            std::lock_guard<std::mutex> lk(mu);
+            b.stream = (size_t)(std::min_element(stream_bits.begin(), stream_bits.end()) - stream_bits.begin());
+            for (Req *r : admitted) stream_bits[b.stream] += r->n;
+        }
         if (sim) {
             double us = 0;
             for (Req *r : admitted) us += (double)r->n / std::max(cfg.sim_bits_per_us, 1e-9);
@@ -368,6 +376,7 @@ void pa_server_s::loop() {
                     r->t_done = Clock::now();
                     pool->release(r->ws_off, r->need);
                     st.inflight--;
+                    stream_bits[b.stream] -= r->n;
                 }
                 for (Part &pt : b.parts)
                     if (pt.ev) spare_events.push_back(pt.ev);
@@ -397,6 +406,7 @@ pa_status pa_server_create(const pa_server_config *cfg, pa_server_t *server) {
     s->sim = cfg->executor == PA_EXEC_SIMULATED;
     s->pool.reset(new Pool(cfg->hbm_budget_bytes / kAlign * kAlign));
     s->st.budget_bytes = s->pool->size();
+    s->stream_bits.assign(cfg->streams, 0);
     if (!s->sim) {
         hipError_t e = hipGetDevice(&s->device);
         if (e == hipSuccess) e = hipMalloc(&s->pool_base, (size_t)s->pool->size());

@@ -13,6 +13,7 @@
 // Batches of successive iterations run on different streams, so work
 // admitted while earlier work is on the device overlaps with it.
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <chrono>
@@ -237,20 +238,29 @@ pa_status pa_server_s::launch(std::vector<Req *> &rs, Batch *b) {
         groups.back().reqs.push_back(r);
     }
     if (table.size() > sc.cap) return fail(PA_ERR_DEVICE, "job table overflow");
-    if (sc.staged) {
-        hipError_t e = hipEventSynchronize(sc.staged);
-        if (e != hipSuccess) return from_hip(e, "staging wait");
+    // a group of one request passes its descriptor in the kernel arguments;
+    // only groups of several need the table in device memory
+    const bool need_table =
+        std::any_of(groups.begin(), groups.end(), [](const Group &g) { return g.count > 1; });
+    hipError_t e = hipSuccess;
+    if (need_table) {
+        if (sc.staged) {
+            e = hipEventSynchronize(sc.staged);
+            if (e != hipSuccess) return from_hip(e, "staging wait");
+        }
+        memcpy(sc.pinned, table.data(), table.size() * sizeof(pa::JobDesc));
+        e = hipMemcpyAsync(sc.dtable, sc.pinned, table.size() * sizeof(pa::JobDesc), hipMemcpyHostToDevice, sc.s);
+        if (e == hipSuccess) e = hipEventRecord(sc.staged, sc.s);
+        if (e != hipSuccess) return from_hip(e, "job table upload");
     }
-    memcpy(sc.pinned, table.data(), table.size() * sizeof(pa::JobDesc));
-    hipError_t e = hipMemcpyAsync(sc.dtable, sc.pinned, table.size() * sizeof(pa::JobDesc), hipMemcpyHostToDevice,
-                                  sc.s);
-    if (e == hipSuccess) e = hipEventRecord(sc.staged, sc.s);
-    if (e != hipSuccess) return from_hip(e, "job table upload");
     size_t first = 0;
     for (auto &g : groups) {
         const pa::PlanRef &p = g.plan;
         pa::JobArgs ja{};
-        ja.table = sc.dtable + first;
+        if (g.count == 1)
+            ja.one = table[first];
+        else
+            ja.table = sc.dtable + first;
         const int nj = (int)g.count;
         double in_b = 0, out_b = 0;
         for (size_t k = first; k < first + g.count; ++k) {
@@ -326,6 +336,9 @@ bool pa_server_s::retire_locked() {
 
 void pa_server_s::loop() {
     if (!sim) (void)hipSetDevice(device);
+    // timed waits below poll running work every few microseconds; the
+    // default 50 us timer slack would stretch each of them several times
+    (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     for (;;) {
         std::vector<Req *> admitted;
         {
@@ -347,7 +360,7 @@ void pa_server_s::loop() {
             st.peak_inflight = std::max(st.peak_inflight, st.inflight);
             if (admitted.empty()) {
                 // nothing to launch: wait for a submission, or poll running work
-                cv_work.wait_for(lk, std::chrono::microseconds(running.empty() ? 2000 : 20));
+                cv_work.wait_for(lk, std::chrono::microseconds(running.empty() ? 2000 : 10));
                 continue;
             }
         }

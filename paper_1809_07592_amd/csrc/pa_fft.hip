@@ -114,59 +114,75 @@ __device__ void dit_inv(double2 *x, int N, int lgN, int lgc, int stride, const d
     }
 }
 
-__device__ __forceinline__ double bit_at(const uint64_t *w, int64_t p, int64_t nbits) {
-    if (!w || p < 0 || p >= nbits) return 0.0;
-    return (double)((w[p >> 6] >> (p & 63)) & 1ull);
-}
-
 extern __shared__ double2 fft_lds[];
 
-// Column pass, forward: real part from bits of `a`, imaginary part from
-// bits of `b` (may be null), both read at position p - shift; W-column
-// tile of all R rows; output twisted and stored at its (bit-reversed) row.
-__global__ void __launch_bounds__(1024) k_fft_colfwd(FftPlan p, const uint64_t *a, const uint64_t *b, int64_t nbits,
-                                                    int64_t shift, double2 *Z) {
+// Column pass, forward.  blockIdx.y = 0: the seed (real input, `nseed`
+// bits) into S; blockIdx.y = 1: real part from the bits of `a`, imaginary
+// part from the bits of `b`, `n` bits each, into Z.  W-column tile of all R
+// rows; W divides 64 and c0 is a multiple of W, so the W bits of a row sit
+// in one word.  Output twisted by omega_L^(k1 c) and stored at its
+// (bit-reversed) row.  Workgroup (0, 0) also clears *maxerr for the
+// inverse pass later on the stream.
+__global__ void __launch_bounds__(1024) k_fft_colfwd(FftPlan p, const uint64_t *seed, int64_t nseed,
+                                                    const uint64_t *a, const uint64_t *b, int64_t n, double2 *S,
+                                                    double2 *Z, unsigned long long *maxerr) {
     const int W = p.W, lgW = __builtin_ctz((unsigned)W), R = p.R, C = p.C;
     const int c0 = blockIdx.x * W;
+    const bool pair = blockIdx.y != 0;
+    const uint64_t *ra = pair ? a : seed, *rb = pair ? b : nullptr;
+    const int64_t nbits = pair ? n : nseed;
+    double2 *out = pair ? Z : S;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *maxerr = 0ull;
     double2 *x = fft_lds;
-    for (int e = threadIdx.x; e < R * W; e += blockDim.x) {
-        const int r = e >> lgW, c = e & (W - 1);
-        const int64_t q = (int64_t)r * C + c0 + c - shift;
-        x[e] = make_double2(bit_at(a, q, nbits), bit_at(b, q, nbits));
+    const uint64_t wmask = W == 64 ? ~0ull : ((1ull << W) - 1ull);
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        const int64_t q = (int64_t)r * C + c0;  // first bit of the row's tile
+        uint64_t va = 0, vb = 0;
+        if (q < nbits) {
+            const int sh = (int)(q & 63);
+            va = ra[q >> 6] >> sh;
+            if (rb) vb = rb[q >> 6] >> sh;
+            const int64_t left = nbits - q;  // bits of the tile inside the input
+            const uint64_t keep = left >= W ? wmask : ((1ull << left) - 1ull);
+            va &= keep;
+            vb &= keep;
+        }
+        for (int c = 0; c < W; ++c)
+            x[r * W + c] = make_double2((double)((va >> c) & 1ull), (double)((vb >> c) & 1ull));
     }
     __syncthreads();
     dif(x, R, p.log2R, lgW, W, p.tw_r);
     for (int e = threadIdx.x; e < R * W; e += blockDim.x) {
         const int r = e >> lgW, c = e & (W - 1);
         const uint32_t k1 = __builtin_bitreverse32((uint32_t)r) >> (32 - p.log2R);
-        const uint32_t ex = (uint32_t)(((uint64_t)k1 * (uint64_t)(c0 + c)) % p.L);
-        Z[(size_t)r * C + c0 + c] = cmul(x[r * W + c], twist(p, ex));
+        // k1 < R and c0 + c < C, so the exponent is below L
+        out[(size_t)r * C + c0 + c] = cmul(x[e], twist(p, k1 * (uint32_t)(c0 + c)));
     }
 }
 
-// Row pass.  mode 1: Z row <- DIF(row) / L (seed spectrum).  mode 0: Z row
-// <- conj-twist( DIT^-1( DIF(row) * S row ) ).
-__global__ void __launch_bounds__(1024) k_fft_row(FftPlan p, double2 *Z, const double2 *S, int mode) {
+// Row pass: the seed row (S) and the pair row (Z) interleaved in LDS
+// (element c of transform t at 2c + t).  Both DIF, the pair times the seed
+// spectrum / L, DIT inverse of the pair, inverse twist; Z row overwritten.
+__global__ void __launch_bounds__(1024) k_fft_row(FftPlan p, const double2 *S, double2 *Z) {
     const int C = p.C, row = blockIdx.x;
     double2 *x = fft_lds;
-    double2 *zr = Z + (size_t)row * C;
-    for (int c = threadIdx.x; c < C; c += blockDim.x) x[c] = zr[c];
-    __syncthreads();
-    dif(x, C, p.log2C, 0, 1, p.tw_c);
-    if (mode == 1) {
-        const double invL = 1.0 / (double)p.L;
-        for (int c = threadIdx.x; c < C; c += blockDim.x) zr[c] = make_double2(x[c].x * invL, x[c].y * invL);
-        return;
-    }
     const double2 *sr = S + (size_t)row * C;
-    for (int c = threadIdx.x; c < C; c += blockDim.x) x[c] = cmul(x[c], sr[c]);
-    __syncthreads();
-    dit_inv(x, C, p.log2C, 0, 1, p.tw_c);
-    const uint32_t k1 = __builtin_bitreverse32((uint32_t)row) >> (32 - p.log2R);
+    double2 *zr = Z + (size_t)row * C;
     for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        const uint32_t ex = (uint32_t)(((uint64_t)k1 * (uint64_t)c) % p.L);
-        zr[c] = cmulc(x[c], twist(p, ex));
+        x[2 * c] = sr[c];
+        x[2 * c + 1] = zr[c];
     }
+    __syncthreads();
+    dif(x, C, p.log2C, 1, 2, p.tw_c);
+    const double invL = 1.0 / (double)p.L;
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        const double2 sp = x[2 * c];
+        x[2 * c + 1] = cmul(x[2 * c + 1], make_double2(sp.x * invL, sp.y * invL));
+    }
+    __syncthreads();
+    dit_inv(x + 1, C, p.log2C, 0, 2, p.tw_c);
+    const uint32_t k1 = __builtin_bitreverse32((uint32_t)row) >> (32 - p.log2R);
+    for (int c = threadIdx.x; c < C; c += blockDim.x) zr[c] = cmulc(x[2 * c + 1], twist(p, k1 * (uint32_t)c));
 }
 
 // Column pass, inverse: natural rows; convolution position r*C + c.  For
@@ -201,11 +217,12 @@ __global__ void __launch_bounds__(1024) k_fft_colinv(FftPlan p, const double2 *Z
 }
 
 // Packs m parity bytes into ceil(m/64) little-endian words (tail zero);
-// the byte array is padded to a multiple of 256 bytes.
-__global__ void k_fft_pack(const uint8_t *bits, int64_t m, uint64_t *out) {
+// blockIdx.y selects the byte array (bits_a + y * stride) and output.  The
+// byte arrays are padded to a multiple of 256 bytes.
+__global__ void k_fft_pack(const uint8_t *bits, int64_t stride, int64_t m, uint64_t *out_a, uint64_t *out_b) {
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= (m + 63) / 64) return;
-    const uint64_t *b8 = (const uint64_t *)bits + w * 8;  // 64 bytes of 0/1
+    const uint64_t *b8 = (const uint64_t *)(bits + blockIdx.y * stride) + w * 8;  // 64 bytes of 0/1
     uint64_t v = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -214,7 +231,7 @@ __global__ void k_fft_pack(const uint8_t *bits, int64_t m, uint64_t *out) {
         for (int j = 0; j < 8; ++j) v |= ((x >> (8 * j)) & 1ull) << (8 * k + j);
     }
     const int64_t tail = m - w * 64;
-    out[w] = tail >= 64 ? v : (v & ((1ull << tail) - 1ull));
+    (blockIdx.y ? out_b : out_a)[w] = tail >= 64 ? v : (v & ((1ull << tail) - 1ull));
 }
 
 static hipError_t lds_optin(const void *f, size_t bytes) {
@@ -224,28 +241,27 @@ static hipError_t lds_optin(const void *f, size_t bytes) {
 hipError_t launch_pair(const FftPlan &p, const uint64_t *key_a, const uint64_t *key_b, int64_t n,
                        const uint64_t *seed, int64_t m, uint64_t *out_a, uint64_t *out_b, void *ws,
                        unsigned long long *maxerr, hipStream_t s) {
-    const size_t col_lds = (size_t)p.R * p.W * sizeof(double2), row_lds = (size_t)p.C * sizeof(double2);
+    const size_t col_lds = (size_t)p.R * p.W * sizeof(double2), row_lds = 2 * (size_t)p.C * sizeof(double2);
     if (col_lds > kFftMaxLds || row_lds > kFftMaxLds) return hipErrorInvalidConfiguration;
     hipError_t e = lds_optin((const void *)k_fft_colfwd, kFftMaxLds);
     if (e == hipSuccess) e = lds_optin((const void *)k_fft_row, kFftMaxLds);
     if (e == hipSuccess) e = lds_optin((const void *)k_fft_colinv, kFftMaxLds);
     if (e != hipSuccess) return e;
     double2 *Z = (double2 *)ws, *S = Z + p.L;
-    uint8_t *bits_a = (uint8_t *)(S + p.L), *bits_b = bits_a + ((m + 255) / 256) * 256;
+    const int64_t bstride = ((m + 255) / 256) * 256;
+    uint8_t *bits_a = (uint8_t *)(S + p.L), *bits_b = bits_a + bstride;
     const int64_t off0 = n - 1;  // y_i = c[n - 1 + i]
-    const dim3 cgrid((unsigned)(p.C / p.W)), rgrid((unsigned)p.R), blk(1024);
-    e = hipMemsetAsync(maxerr, 0, sizeof(*maxerr), s);
-    if (e != hipSuccess) return e;
-    // seed spectrum (real input), then the key pair
-    hipLaunchKernelGGL(k_fft_colfwd, cgrid, blk, col_lds, s, p, seed, (const uint64_t *)nullptr, n + m - 1,
-                       (int64_t)0, S);
-    hipLaunchKernelGGL(k_fft_row, rgrid, blk, row_lds, s, p, S, (const double2 *)nullptr, 1);
-    hipLaunchKernelGGL(k_fft_colfwd, cgrid, blk, col_lds, s, p, key_a, key_b, n, (int64_t)0, Z);
-    hipLaunchKernelGGL(k_fft_row, rgrid, blk, row_lds, s, p, Z, (const double2 *)S, 0);
-    hipLaunchKernelGGL(k_fft_colinv, cgrid, blk, col_lds, s, p, (const double2 *)Z, off0, m, bits_a, bits_b, maxerr);
+    const unsigned tiles = (unsigned)(p.C / p.W);
+    // column pass over the seed (y = 0) and the key pair (y = 1); dual row
+    // pass; inverse column pass; packing of both outputs
+    hipLaunchKernelGGL(k_fft_colfwd, dim3(tiles, 2), dim3(1024), col_lds, s, p, seed, n + m - 1, key_a, key_b, n, S, Z,
+                       maxerr);
+    hipLaunchKernelGGL(k_fft_row, dim3((unsigned)p.R), dim3(1024), row_lds, s, p, (const double2 *)S, Z);
+    hipLaunchKernelGGL(k_fft_colinv, dim3(tiles), dim3(1024), col_lds, s, p, (const double2 *)Z, off0, m, bits_a,
+                       bits_b, maxerr);
     const unsigned words = (unsigned)((m + 63) / 64);
-    hipLaunchKernelGGL(k_fft_pack, dim3((words + 255) / 256), dim3(256), 0, s, (const uint8_t *)bits_a, m, out_a);
-    hipLaunchKernelGGL(k_fft_pack, dim3((words + 255) / 256), dim3(256), 0, s, (const uint8_t *)bits_b, m, out_b);
+    hipLaunchKernelGGL(k_fft_pack, dim3((words + 255) / 256, 2), dim3(256), 0, s, (const uint8_t *)bits_a, bstride, m,
+                       out_a, out_b);
     return hipGetLastError();
 }
 

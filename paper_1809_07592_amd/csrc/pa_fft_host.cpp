@@ -36,7 +36,8 @@ bool fft_geometry(int lg, FftPlan *p) {
     int W = 16;
     while (W > 1 && ((size_t)p->R * W * 16 > kFftMaxLds || W > p->C)) W >>= 1;
     p->W = W;
-    return (size_t)p->R * W * 16 <= kFftMaxLds && (size_t)p->C * 16 <= kFftMaxLds;
+    // a column tile, and two rows (the seed's and the pair's) in a row pass
+    return (size_t)p->R * W * 16 <= kFftMaxLds && 2 * (size_t)p->C * 16 <= kFftMaxLds;
 }
 
 size_t fft_workspace(uint64_t L, uint64_t m) { return (size_t)(32 * L) + 2 * (size_t)((m + 255) / 256 * 256); }

@@ -314,7 +314,12 @@ bool pa_server_s::retire_locked() {
             // parts finish in stream order: stop at the first one still running
             while (b.parts_done < b.parts.size()) {
                 Part &pt = b.parts[b.parts_done];
-                if (hipEventQuery(pt.ev) != hipSuccess) break;
+                const hipError_t q = hipEventQuery(pt.ev);
+                if (q == hipErrorNotReady) break;
+                if (q != hipSuccess && error.empty())
+                    // a failed device: complete the part anyway (outputs
+                    // unspecified) so that no waiter blocks for good
+                    error = std::string("completion event: ") + hipGetErrorString(q);
                 const auto t = Clock::now();
                 for (Req *r : pt.reqs) complete_locked(r, t, b.stream);
                 spare_events.push_back(pt.ev);

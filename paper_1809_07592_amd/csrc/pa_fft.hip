@@ -135,8 +135,13 @@ __global__ void __launch_bounds__(1024) k_fft_colfwd(FftPlan p, const uint64_t *
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *maxerr = 0ull;
     double2 *x = fft_lds;
     const uint64_t wmask = W == 64 ? ~0ull : ((1ull << W) - 1ull);
-    for (int r = threadIdx.x; r < R; r += blockDim.x) {
-        const int64_t q = (int64_t)r * C + c0;  // first bit of the row's tile
+    // each wave takes 64 rows (R is a multiple of 64): lane l reads the
+    // tile bits of row rbase + l, then the wave writes the 64 W elements of
+    // those rows in order, lane l taking element k * 64 + l and its row's
+    // bits from the lane that read them (contiguous LDS stores)
+    const int lane = (int)(threadIdx.x & 63);
+    for (int rbase = (int)(threadIdx.x & ~63u); rbase < R; rbase += (int)blockDim.x) {
+        const int64_t q = (int64_t)(rbase + lane) * C + c0;  // first bit of the row's tile
         uint64_t va = 0, vb = 0;
         if (q < nbits) {
             const int sh = (int)(q & 63);
@@ -147,8 +152,14 @@ __global__ void __launch_bounds__(1024) k_fft_colfwd(FftPlan p, const uint64_t *
             va &= keep;
             vb &= keep;
         }
-        for (int c = 0; c < W; ++c)
-            x[r * W + c] = make_double2((double)((va >> c) & 1ull), (double)((vb >> c) & 1ull));
+        // 32-bit halves suffice: W <= 16 bits per row
+        const unsigned ua = (unsigned)va, ub = (unsigned)vb;
+        for (int k = 0; k < W; ++k) {
+            const int e = k * 64 + lane;            // element of the 64-row slab
+            const int src = e >> lgW, c = e & (W - 1);
+            const unsigned wa = (unsigned)__shfl((int)ua, src, 64), wb = (unsigned)__shfl((int)ub, src, 64);
+            x[rbase * W + e] = make_double2((double)((wa >> c) & 1u), (double)((wb >> c) & 1u));
+        }
     }
     __syncthreads();
     dif(x, R, p.log2R, lgW, W, p.tw_r);
@@ -211,9 +222,18 @@ __global__ void __launch_bounds__(1024) k_fft_colinv(FftPlan p, const double2 *Z
         bits_a[i] = (uint8_t)((int64_t)ra & 1);
         bits_b[i] = (uint8_t)((int64_t)rb & 1);
     }
-    // wave maximum, then one vector atomic per wave
+    // wave maximum, workgroup maximum through LDS (the tile is no longer
+    // read), then one vector atomic per workgroup: same-address atomics
+    // from every wave of the launch would serialize
     for (int o = 32; o > 0; o >>= 1) err = fmax(err, __shfl_down(err, o, 64));
-    if ((threadIdx.x & 63) == 0 && err > 0.0) atomicMax(maxerr, (unsigned long long)__double_as_longlong(err));
+    __syncthreads();
+    double *wmax = (double *)fft_lds;
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = err;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (unsigned w = 1; w < (blockDim.x + 63) / 64; ++w) err = fmax(err, wmax[w]);
+        if (err > 0.0) atomicMax(maxerr, (unsigned long long)__double_as_longlong(err));
+    }
 }
 
 // Packs m parity bytes into ceil(m/64) little-endian words (tail zero);

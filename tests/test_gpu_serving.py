@@ -55,3 +55,34 @@ def test_served_results_equal_alone_and_oracle():
         assert np.array_equal(served, alone.cpu().numpy().view(np.uint64)[: wl.words(m)]), i
         if i % 10 == 0:
             assert np.array_equal(served, oracle.toeplitz_hash(key, n, seeds[sid], m)), i
+
+
+def test_small_request_does_not_wait_for_a_large_one():
+    """A small request submitted right after a large one completes first,
+    whether the scheduler batches the two together (each length group
+    completes on its own event) or not (the batch goes to a free stream)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    n_big, m_big = 8_000_000, 2_000_000
+    n_small, m_small = 50_000, 10_000
+    seed = wl.random_bits(n_big + m_big, wl.rng(32, wl.ROLE_SEED, 0))
+    dseed = dev(seed)
+    pairs = []
+    with pa.Server(1 << 30, max_inflight=64, streams=2) as srv:
+        sid = srv.register_seed(dseed, seed.size * 64)
+        for i in range(6):
+            kb = dev(wl.random_bits(n_big, wl.rng(32, wl.ROLE_KEY, 2 * i)))
+            ks = dev(wl.random_bits(n_small, wl.rng(32, wl.ROLE_KEY, 2 * i + 1)))
+            ob = torch.zeros(wl.words(m_big), dtype=torch.int64, device="cuda")
+            os_ = torch.zeros(wl.words(m_small), dtype=torch.int64, device="cuda")
+            tb = srv.submit(sid, kb, n_big, m_big, ob)
+            ts = srv.submit(sid, ks, n_small, m_small, os_)
+            pairs.append((tb, ts, kb, ks, ob, os_))
+            srv.drain()
+        for tb, ts, *_ in pairs:
+            # submitted later and finished sooner: completed first
+            assert srv.latency_us(ts) < srv.latency_us(tb)
+    torch.cuda.synchronize()
+    for _, _, kb, ks, ob, os_ in pairs:
+        assert torch.equal(ob, pa.toeplitz_hash(kb, n_big, dseed, m_big))
+        assert torch.equal(os_, pa.toeplitz_hash(ks, n_small, dseed, m_small))

@@ -12,7 +12,8 @@
 // bit-reversed rows) with the twist omega_L^(k1 c), row DIF transforms, the
 // pointwise product with the seed spectrum in that same order, row DIT
 // inverses (bit-reversed -> natural), the inverse twist, column DIT
-// inverses.  Transforms run two radix-2 stages per LDS pass on complex doubles.
+// inverses.  Transforms merge two or three radix-2 stages per LDS pass on
+// complex doubles.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -35,84 +36,104 @@ __device__ __forceinline__ double2 twist(const FftPlan &p, uint32_t e) {
     return cmul(p.tw_lo[e & 4095u], p.tw_hi[e >> 12]);
 }
 
-// Length-N DIF (natural in, bit-reversed out) on cnt = 2^lgc interleaved
-// transforms in LDS: element j of transform t at x[j * stride + t].
-// tw: exp(-2 pi i k / N), k < N/2.  Stages s and s+1 are done together
-// (four points per work item: one LDS pass per two stages); an odd last
-// stage alone.  Ends with a barrier.
-__device__ void dif(double2 *x, int N, int lgN, int lgc, int stride, const double2 *__restrict__ tw) {
-    const int cmask = (1 << lgc) - 1;
-    int s = 0;
-    for (; s + 1 < lgN; s += 2) {
-        const int half = N >> (s + 1), q4 = half >> 1;     // items: N/4 per transform
-        const int items = (N >> 2) << lgc;
-        for (int q = threadIdx.x; q < items; q += blockDim.x) {
-            const int t = q & cmask, b = q >> lgc;
-            const int j = b & (q4 - 1), blk = b >> (lgN - 2 - s);
-            const int i0 = (blk * 2 * half + j) * stride + t;
-            const int d = q4 * stride;
-            const double2 x0 = x[i0], x1 = x[i0 + d], x2 = x[i0 + 2 * d], x3 = x[i0 + 3 * d];
-            const double2 y0 = cadd(x0, x2), y2 = cmul(csub(x0, x2), tw[j << s]);
-            const double2 y1 = cadd(x1, x3), y3 = cmul(csub(x1, x3), tw[(j + q4) << s]);
-            const double2 w2 = tw[j << (s + 1)];
-            x[i0] = cadd(y0, y1);
-            x[i0 + d] = cmul(csub(y0, y1), w2);
-            x[i0 + 2 * d] = cadd(y2, y3);
-            x[i0 + 3 * d] = cmul(csub(y2, y3), w2);
+// Transforms on cnt = 2^lgc interleaved sequences in LDS: element j of
+// transform t at x[j * stride + t].  tw: exp(-2 pi i k / N), k < N/2.
+// A pass merges LG consecutive radix-2 stages: each work item holds the
+// 2^LG points j + k q (k < 2^LG) of one block of 2^LG q points in
+// registers, so the data crosses LDS once per LG stages.
+
+// DIF stages s .. s+LG-1 (half N >> (s+u+1) at stage s+u).  Ends with a barrier.
+template <int LG>
+__device__ __forceinline__ void dif_pass(double2 *x, int lgN, int lgc, int stride, const double2 *__restrict__ tw,
+                                         int s) {
+    constexpr int P = 1 << LG;
+    const int cmask = (1 << lgc) - 1, lq = lgN - s - LG, q = 1 << lq;
+    const int items = (1 << (lgN - LG)) << lgc;
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+        const int t = it & cmask, b = it >> lgc;
+        const int j = b & (q - 1), blk = b >> lq;
+        const int i0 = ((blk << (lq + LG)) + j) * stride + t, d = q * stride;
+        double2 v[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) v[k] = x[i0 + k * d];
+#pragma unroll
+        for (int u = 0; u < LG; ++u) {
+            const int h = P >> (u + 1);  // partner distance, in points
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                if ((k & h) != 0) continue;
+                // position of point k inside its stage-(s+u) half-block
+                const double2 w = tw[(j + (k & (2 * h - 1)) * q) << (s + u)];
+                const double2 a = v[k], c = v[k + h];
+                v[k] = cadd(a, c);
+                v[k + h] = cmul(csub(a, c), w);
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < P; ++k) x[i0 + k * d] = v[k];
     }
-    if (s < lgN) {  // last stage (half = 1): plain radix-2
-        const int pairs = (N >> 1) << lgc;
-        for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
-            const int t = q & cmask, blk = q >> lgc;
-            const int i0 = (blk * 2) * stride + t, i1 = i0 + stride;
-            const double2 u = x[i0], v = x[i1];
-            x[i0] = cadd(u, v);
-            x[i1] = csub(u, v);  // twiddle index 0
-        }
-        __syncthreads();
-    }
+    __syncthreads();
 }
 
-// Length-N DIT inverse without scaling (bit-reversed in, natural out); the
-// exact mirror of dif: an odd first stage alone, then stage pairs.
-__device__ void dit_inv(double2 *x, int N, int lgN, int lgc, int stride, const double2 *__restrict__ tw) {
-    const int cmask = (1 << lgc) - 1;
-    int s = lgN - 1;
-    if ((lgN & 1) != 0) {  // stage lgN-1 (half = 1) alone
-        const int pairs = (N >> 1) << lgc;
-        for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
-            const int t = q & cmask, blk = q >> lgc;
-            const int i0 = (blk * 2) * stride + t, i1 = i0 + stride;
-            const double2 u = x[i0], v = x[i1];
-            x[i0] = cadd(u, v);
-            x[i1] = csub(u, v);
+// DIT inverse stages s_hi, s_hi-1, .., s_hi-LG+1 (half N >> (s_hi-u+1) at
+// stage s_hi-u), without scaling.  Ends with a barrier.
+template <int LG>
+__device__ __forceinline__ void dit_pass(double2 *x, int lgN, int lgc, int stride, const double2 *__restrict__ tw,
+                                         int s_hi) {
+    constexpr int P = 1 << LG;
+    const int cmask = (1 << lgc) - 1, lq = lgN - 1 - s_hi, q = 1 << lq;
+    const int items = (1 << (lgN - LG)) << lgc;
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+        const int t = it & cmask, b = it >> lgc;
+        const int j = b & (q - 1), blk = b >> lq;
+        const int i0 = ((blk << (lq + LG)) + j) * stride + t, d = q * stride;
+        double2 v[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) v[k] = x[i0 + k * d];
+#pragma unroll
+        for (int u = 0; u < LG; ++u) {
+            const int h = 1 << u;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                if ((k & h) != 0) continue;
+                const double2 w = tw[(j + (k & (2 * h - 1)) * q) << (s_hi - u)];
+                const double2 a = v[k], c = cmulc(v[k + h], w);
+                v[k] = cadd(a, c);
+                v[k + h] = csub(a, c);
+            }
         }
-        __syncthreads();
-        --s;
+#pragma unroll
+        for (int k = 0; k < P; ++k) x[i0 + k * d] = v[k];
     }
-    for (; s >= 1; s -= 2) {
-        // stages s (half h) then s-1 (half 2h) on blocks of 4h
-        const int h = N >> (s + 1);
-        const int items = (N >> 2) << lgc;
-        for (int q = threadIdx.x; q < items; q += blockDim.x) {
-            const int t = q & cmask, b = q >> lgc;
-            const int j = b & (h - 1), blk = b >> (lgN - 1 - s);
-            const int i0 = (blk * 4 * h + j) * stride + t;
-            const int d = h * stride;
-            const double2 w1 = tw[j << s];
-            const double2 x0 = x[i0], x1 = cmulc(x[i0 + d], w1), x2 = x[i0 + 2 * d], x3 = cmulc(x[i0 + 3 * d], w1);
-            const double2 y0 = cadd(x0, x1), y1 = csub(x0, x1), y2 = cadd(x2, x3), y3 = csub(x2, x3);
-            const double2 v2 = cmulc(y2, tw[j << (s - 1)]), v3 = cmulc(y3, tw[(j + h) << (s - 1)]);
-            x[i0] = cadd(y0, v2);
-            x[i0 + 2 * d] = csub(y0, v2);
-            x[i0 + d] = cadd(y1, v3);
-            x[i0 + 3 * d] = csub(y1, v3);
-        }
-        __syncthreads();
-    }
+    __syncthreads();
 }
+
+// Length-2^lgN DIF (natural in, bit-reversed out): passes of MAXLG stages,
+// then one of the remaining ones.  MAXLG (2 or 3) trades LDS passes against
+// the work items a pass offers: a pass has 2^(lgN-LG+lgc) of them.
+template <int MAXLG>
+__device__ __forceinline__ void dif(double2 *x, int lgN, int lgc, int stride, const double2 *__restrict__ tw) {
+    int s = 0;
+    for (; lgN - s >= MAXLG; s += MAXLG) dif_pass<MAXLG>(x, lgN, lgc, stride, tw, s);
+    if (lgN - s == 2) dif_pass<2>(x, lgN, lgc, stride, tw, s);
+    if (lgN - s == 1) dif_pass<1>(x, lgN, lgc, stride, tw, s);
+}
+
+// Length-2^lgN DIT inverse without scaling (bit-reversed in, natural out):
+// the top lgN mod MAXLG stages first, then passes of MAXLG.
+template <int MAXLG>
+__device__ __forceinline__ void dit_inv(double2 *x, int lgN, int lgc, int stride, const double2 *__restrict__ tw) {
+    int s_hi = lgN - 1;
+    const int r = lgN % MAXLG;
+    if (r == 2) dit_pass<2>(x, lgN, lgc, stride, tw, s_hi);
+    if (r == 1) dit_pass<1>(x, lgN, lgc, stride, tw, s_hi);
+    for (s_hi -= r; s_hi >= MAXLG - 1; s_hi -= MAXLG) dit_pass<MAXLG>(x, lgN, lgc, stride, tw, s_hi);
+}
+
+// Column tiles offer R/8 * W items at three stages per pass (1024 for
+// R = 1024, W = 8); a row pass two rows (or one) of C <= 4096, so rows merge
+// two stages to keep the 1024 threads busy.
+constexpr int kColStages = 3, kRowStages = 2;
 
 extern __shared__ double2 fft_lds[];
 
@@ -162,7 +183,7 @@ __global__ void __launch_bounds__(1024) k_fft_colfwd(FftPlan p, const uint64_t *
         }
     }
     __syncthreads();
-    dif(x, R, p.log2R, lgW, W, p.tw_r);
+    dif<kColStages>(x, p.log2R, lgW, W, p.tw_r);
     for (int e = threadIdx.x; e < R * W; e += blockDim.x) {
         const int r = e >> lgW, c = e & (W - 1);
         const uint32_t k1 = __builtin_bitreverse32((uint32_t)r) >> (32 - p.log2R);
@@ -184,14 +205,14 @@ __global__ void __launch_bounds__(1024) k_fft_row(FftPlan p, const double2 *S, d
         x[2 * c + 1] = zr[c];
     }
     __syncthreads();
-    dif(x, C, p.log2C, 1, 2, p.tw_c);
+    dif<kRowStages>(x, p.log2C, 1, 2, p.tw_c);
     const double invL = 1.0 / (double)p.L;
     for (int c = threadIdx.x; c < C; c += blockDim.x) {
         const double2 sp = x[2 * c];
         x[2 * c + 1] = cmul(x[2 * c + 1], make_double2(sp.x * invL, sp.y * invL));
     }
     __syncthreads();
-    dit_inv(x + 1, C, p.log2C, 0, 2, p.tw_c);
+    dit_inv<kRowStages>(x + 1, p.log2C, 0, 2, p.tw_c);
     const uint32_t k1 = __builtin_bitreverse32((uint32_t)row) >> (32 - p.log2R);
     for (int c = threadIdx.x; c < C; c += blockDim.x) zr[c] = cmulc(x[2 * c + 1], twist(p, k1 * (uint32_t)c));
 }
@@ -210,7 +231,7 @@ __global__ void __launch_bounds__(1024) k_fft_colinv(FftPlan p, const double2 *Z
         x[e] = Z[(size_t)r * C + c0 + c];
     }
     __syncthreads();
-    dit_inv(x, R, p.log2R, lgW, W, p.tw_r);
+    dit_inv<kColStages>(x, p.log2R, lgW, W, p.tw_r);
     double err = 0.0;
     for (int e = threadIdx.x; e < R * W; e += blockDim.x) {
         const int r = e >> lgW, c = e & (W - 1);

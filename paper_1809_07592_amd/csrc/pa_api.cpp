@@ -92,6 +92,10 @@ struct Workspace {
     hipStream_t side[kSideStreams] = {};
     hipEvent_t fork_ev = nullptr;
     hipEvent_t join_ev[kSideStreams] = {};
+    // pinned host words for small device-to-host results read back on this
+    // stream (a copy to pageable memory is staged by the runtime)
+    void *readback = nullptr;
+    std::mutex readback_mu;  // held from the copy into `readback` until it is read
 };
 std::mutex g_ws_mu;
 std::map<std::pair<int, void *>, Workspace> g_ws;
@@ -172,8 +176,29 @@ void release_stream_state(hipStream_t s) {
         if (sl.staged) (void)hipEventDestroy(sl.staged);
         if (sl.pinned) (void)hipHostFree(sl.pinned);
     }
+    if (w.readback) (void)hipHostFree(w.readback);
     if (w.ptr) (void)hipFree(w.ptr);
     g_ws.erase(it);
+}
+
+// The stream's pinned readback area (kReadbackBytes), allocated on first
+// use, with its lock taken into *hold.
+pa_status get_readback(hipStream_t s, void **out, std::unique_lock<std::mutex> *hold) {
+    int dev = 0;
+    PA_HIP(hipGetDevice(&dev), "hipGetDevice");
+    Workspace *w = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        w = &g_ws[{dev, (void *)s}];  // map nodes keep their address
+    }
+    std::unique_lock<std::mutex> rl(w->readback_mu);
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        if (!w->readback) PA_HIP(hipHostMalloc(&w->readback, kReadbackBytes, hipHostMallocDefault), "hipHostMalloc");
+    }
+    *out = w->readback;
+    *hold = std::move(rl);
+    return PA_OK;
 }
 
 // Copy `bytes` of host data to device address `dst` on stream s through

@@ -140,11 +140,14 @@ pa_status pa_toeplitz_hash_pair_fft(const uint64_t *key_a, const uint64_t *key_b
     unsigned long long *dmax = (unsigned long long *)((char *)ws + ws_bytes);
     PA_HIP(pa::fft::launch_pair(p, key_a, key_b, (int64_t)n, seed, (int64_t)m, out_a, out_b, ws, dmax, s),
            "FFT pair launch");
-    unsigned long long bitsv = 0;
-    PA_HIP(hipMemcpyAsync(&bitsv, dmax, sizeof(bitsv), hipMemcpyDeviceToHost, s), "error readback");
+    void *rb = nullptr;
+    std::unique_lock<std::mutex> rb_hold;
+    PA_TRY(get_readback(s, &rb, &rb_hold));
+    PA_HIP(hipMemcpyAsync(rb, dmax, sizeof(unsigned long long), hipMemcpyDeviceToHost, s), "error readback");
     PA_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
     double err = 0.0;
-    memcpy(&err, &bitsv, sizeof(err));
+    memcpy(&err, rb, sizeof(err));
+    rb_hold.unlock();
     if (max_error) *max_error = err;
     const bool fallback = err >= guard;
     if (fell_back) *fell_back = fallback ? 1 : 0;

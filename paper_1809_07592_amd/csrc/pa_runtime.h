@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -47,6 +48,11 @@ pa_status get_workspace(hipStream_t s, size_t bytes, void **out);
 // Copies host data to device address dst on stream s through the stream's
 // pinned staging slots (stream-ordered; the host may reuse src at once).
 pa_status stage_upload(hipStream_t s, void *dst, const void *src, size_t bytes);
+// Pinned host memory of the stream for small results copied back and read
+// after a synchronization of that stream; valid until release_stream_state.
+// *hold keeps other callers on the same stream out until the value is read.
+constexpr size_t kReadbackBytes = 256;
+pa_status get_readback(hipStream_t s, void **out, std::unique_lock<std::mutex> *hold);
 // Cached device plan of length L in the tuned geometry of batch class cls
 // (0: one block per launch, 1: several).
 pa_status plan_for(uint64_t L, int cls, PlanRef *lp);

@@ -19,7 +19,7 @@ Also reported on the same JSON line:
   * modified_toeplitz: the S = (I, V) variant at the same shape, one block
     per call and 256 per batched call;
   * fft_pair: the FP64 complex-FFT form (two keys per transform) with its
-    largest rounding error;
+    largest rounding error and its call-level HBM fraction;
   * serving: 10,000 requests (n log-uniform in [1e5, 1e7]) against 16
     resident seeds under an open-loop Poisson arrival process, p50/p99/max
     latency at offered loads 0.3/0.5/0.9 and the headline 0.7 of the
@@ -214,9 +214,17 @@ def fft_pair_run(pa, wl, torch, np, n, m, reps):
         _, _, err, fb = pa.toeplitz_hash_pair_fft(ka, kb, n, sd, m, oa, ob)
         worst, fallbacks = max(worst, err), fallbacks + int(fb)
     el = (time.perf_counter() - t0) / reps
+    L = pa.fft_pair_transform_len(n, m)
+    # algorithmic HBM bytes of one call: complex doubles (16 B) written by
+    # the column pass (seed and pair, 2L), read (2L) and written (L) by the
+    # row pass, read (L) by the inverse column pass; plus the bit arrays, two
+    # parity byte arrays and their packing
+    alg = 16.0 * 6 * L + (2 * n + (n + m - 1)) / 8.0 + 2 * m * 2 + 2 * m / 8.0
     return {"Gbs": 2 * n / el / 1e9, "ms_per_pair": el * 1e3, "max_rounding_error": worst, "fallbacks": fallbacks,
-            "transform_len": pa.fft_pair_transform_len(n, m),
-            "definition": "two keys per complex FFT, wall time per call incl. the host-side error check"}
+            "transform_len": L, "alg_bytes_per_call": alg, "hbm_GBs_call": alg / el / 1e9,
+            "hbm_frac_call": alg / el / 1e9 / HBM_PEAK_GBS,
+            "definition": "two keys per complex FFT, wall time per call incl. the host-side error check; "
+                          "hbm_* use that wall time"}
 
 
 def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30):
@@ -426,7 +434,8 @@ def main():
     large = large_block_run(pa, wl, torch, np, stream, 20, not args.no_tune)
     progress("config 3 (n=12.8e6): %.2f Gb/s" % large["value"])
     fftp = fft_pair_run(pa, wl, torch, np, n, m, 50)
-    progress("FFT pair: %.2f Gb/s, max rounding error %.3g" % (fftp["Gbs"], fftp["max_rounding_error"]))
+    progress("FFT pair: %.2f Gb/s, %.2f of HBM peak per call, max rounding error %.3g"
+             % (fftp["Gbs"], fftp["hbm_frac_call"], fftp["max_rounding_error"]))
     serving = serving_run(pa, wl, torch, np, args.serving, args.load) if args.serving > 0 else None
     if serving is not None:
         progress("serving: done")

@@ -148,8 +148,9 @@ pa_status pa_graph_destroy(pa_graph_t graph);
  * the guard the results equal pa_toeplitz_hash's.  Device pointers as for
  * pa_toeplitz_hash; the two outputs must not overlap.  Unlike the other
  * calls this one blocks the host until the stream has finished the FFT
- * pass, to read the error.  Uses the stream's workspace: 32 L bytes plus
- * 2 m.
+ * pass, to read the error.  Uses the stream's workspace (32 L bytes plus
+ * 2 m) and 256 bytes of pinned host memory kept per stream for the error
+ * read-back; concurrent calls on one stream wait for each other's read.
  */
 uint64_t pa_fft_pair_transform_len(uint64_t n, uint64_t m);
 pa_status pa_toeplitz_hash_pair_fft(const uint64_t *key_a, const uint64_t *key_b, uint64_t n,

@@ -131,9 +131,10 @@ __device__ __forceinline__ void dit_inv(double2 *x, int lgN, int lgc, int stride
 }
 
 // Column tiles offer R/8 * W items at three stages per pass (1024 for
-// R = 1024, W = 8); a row pass two rows (or one) of C <= 4096, so rows merge
-// two stages to keep the 1024 threads busy.
-constexpr int kColStages = 3, kRowStages = 2;
+// R = 1024, W = 8).  The row pass runs 512 threads: its forward passes over
+// the seed and pair rows merge three stages (C/8 * 2 items), its inverse
+// over the pair row alone two (C/4 items).
+constexpr int kColStages = 3, kRowFwdStages = 3, kRowInvStages = 2, kRowThreads = 512;
 
 extern __shared__ double2 fft_lds[];
 
@@ -195,7 +196,7 @@ __global__ void __launch_bounds__(1024) k_fft_colfwd(FftPlan p, const uint64_t *
 // Row pass: the seed row (S) and the pair row (Z) interleaved in LDS
 // (element c of transform t at 2c + t).  Both DIF, the pair times the seed
 // spectrum / L, DIT inverse of the pair, inverse twist; Z row overwritten.
-__global__ void __launch_bounds__(1024) k_fft_row(FftPlan p, const double2 *S, double2 *Z) {
+__global__ void __launch_bounds__(kRowThreads) k_fft_row(FftPlan p, const double2 *S, double2 *Z) {
     const int C = p.C, row = blockIdx.x;
     double2 *x = fft_lds;
     const double2 *sr = S + (size_t)row * C;
@@ -205,14 +206,14 @@ __global__ void __launch_bounds__(1024) k_fft_row(FftPlan p, const double2 *S, d
         x[2 * c + 1] = zr[c];
     }
     __syncthreads();
-    dif<kRowStages>(x, p.log2C, 1, 2, p.tw_c);
+    dif<kRowFwdStages>(x, p.log2C, 1, 2, p.tw_c);
     const double invL = 1.0 / (double)p.L;
     for (int c = threadIdx.x; c < C; c += blockDim.x) {
         const double2 sp = x[2 * c];
         x[2 * c + 1] = cmul(x[2 * c + 1], make_double2(sp.x * invL, sp.y * invL));
     }
     __syncthreads();
-    dit_inv<kRowStages>(x + 1, p.log2C, 0, 2, p.tw_c);
+    dit_inv<kRowInvStages>(x + 1, p.log2C, 0, 2, p.tw_c);
     const uint32_t k1 = __builtin_bitreverse32((uint32_t)row) >> (32 - p.log2R);
     for (int c = threadIdx.x; c < C; c += blockDim.x) zr[c] = cmulc(x[2 * c + 1], twist(p, k1 * (uint32_t)c));
 }
@@ -297,7 +298,7 @@ hipError_t launch_pair(const FftPlan &p, const uint64_t *key_a, const uint64_t *
     // pass; inverse column pass; packing of both outputs
     hipLaunchKernelGGL(k_fft_colfwd, dim3(tiles, 2), dim3(1024), col_lds, s, p, seed, n + m - 1, key_a, key_b, n, S, Z,
                        maxerr);
-    hipLaunchKernelGGL(k_fft_row, dim3((unsigned)p.R), dim3(1024), row_lds, s, p, (const double2 *)S, Z);
+    hipLaunchKernelGGL(k_fft_row, dim3((unsigned)p.R), dim3(kRowThreads), row_lds, s, p, (const double2 *)S, Z);
     hipLaunchKernelGGL(k_fft_colinv, dim3(tiles), dim3(1024), col_lds, s, p, (const double2 *)Z, off0, m, bits_a,
                        bits_b, maxerr);
     const unsigned words = (unsigned)((m + 63) / 64);

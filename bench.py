@@ -227,7 +227,7 @@ def fft_pair_run(pa, wl, torch, np, n, m, reps):
                           "hbm_* use that wall time"}
 
 
-def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30):
+def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30, streams=4, max_inflight=512):
     """Open-loop Poisson serving run (see module docstring)."""
     n_seeds, seed_bits = 16, 1 << 24
     seeds = [torch.from_numpy(wl.random_bits(seed_bits, wl.rng(5, wl.ROLE_SEED, i)).view(np.int64)).cuda()
@@ -260,7 +260,7 @@ def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30):
         return el, lat
 
     bits = sum(r.n for r in reqs)
-    with pa.Server(budget_bytes, max_inflight=512, streams=4) as srv:
+    with pa.Server(budget_bytes, max_inflight=max_inflight, streams=streams) as srv:
         ids = [srv.register_seed(sd, seed_bits) for sd in seeds]
         run(srv, ids, None)                    # warm-up: builds the resident seed spectra
         run_sat_el, _ = run(srv, ids, None)    # saturated (all submitted at once): capacity
@@ -286,7 +286,8 @@ def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30):
     return {"requests": len(reqs), "offered_load": load, "arrival_rate_per_s": rate, "value": bits / el / 1e9,
             "unit": "Gb/s", "saturated_Gbs": cap_gbs, "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()), "makespan_s": el,
-            "budget_GiB": budget_bytes / 2**30, "peak_inflight": st["peak_inflight"], "batches": st["batches"],
+            "budget_GiB": budget_bytes / 2**30, "streams": streams, "max_inflight": max_inflight,
+            "peak_inflight": st["peak_inflight"], "batches": st["batches"],
             "peak_bytes_in_flight": st["peak_bytes_in_flight"], "mismatches_vs_alone": mism,
             "load_sweep": sweep, "latency": "completion minus scheduled Poisson arrival (open loop)"}
 

@@ -330,7 +330,7 @@ def main():
                     help="only run a 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (independent blocks shard by routing whole blocks to "
+        print("bench.py: measures one GPU only (independent blocks shard by routing whole blocks to "
               "GPUs; no collective is involved); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -16,6 +16,7 @@ Also reported on the same JSON line:
     m/n uniform in [0.05, 0.5], own seed each, one batched call (and the
     same call captured once as a graph and replayed: graph_Gbs);
   * large_block: one block of n = 12.8e6, m = 1.28e6 (plain path);
+  * small_block: one block of n = 262,144, m = 65,536 (plain path);
   * modified_toeplitz: the S = (I, V) variant at the same shape, one block
     per call and 256 per batched call;
   * plan_path: the same block against a resident seed spectrum (key passes
@@ -30,6 +31,9 @@ Also reported on the same JSON line:
   * roofline of the dominant kernel, from HIP events the library records
     with each launch on its own stream, over a repeat of the timed steps
     (algorithmic bytes and fp64 operations per launch / average duration);
+  * parity: the timed outputs of the headline block, the small and the
+    large block and every block of the 256-block batch, compared word for word with
+    the CPU oracle;
   * cpu_baseline: the CPU oracle (packed AND + popcount parity) timed on
     this host's cores on full blocks of the same workload.
 
@@ -98,24 +102,36 @@ def time_steps(fn, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def cpu_baseline(key, seed, n, m, budget_s=12.0, max_reps=1000):
+def cpu_baseline(key, seed, n, m, run_s=4.0, runs=3):
+    """The CPU oracle, built for this host's CPU (-march=native), timed on
+    all cores of this process's affinity: `runs` runs of back-to-back full
+    blocks of about run_s seconds each, the median run's rate reported; plus
+    one block on one thread.  Returns (baseline dict, the oracle's output
+    for the block)."""
     import oracle
-    oracle.build()
-    threads = oracle.max_threads()
-    oracle.toeplitz_hash(key, n, seed, m, threads=threads)  # warm the allocator/threads
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        oracle.toeplitz_hash(key, n, seed, m, threads=threads)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or reps >= max_reps:
-            break
+    oracle.select_native()
+    threads = len(os.sched_getaffinity(0))
+    want = oracle.toeplitz_hash(key, n, seed, m, threads=threads)  # also warms the thread pool
+    rates, samples = [], []
+    for _ in range(runs):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            oracle.toeplitz_hash(key, n, seed, m, threads=threads)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= run_s:
+                break
+        rates.append(n * reps / el / 1e9)
+        samples.append("%d blocks in %.2f s" % (reps, el))
     t1 = time.perf_counter()
     oracle.toeplitz_hash(key, n, seed, m, threads=1)
     one = time.perf_counter() - t1
-    return {"value": n * reps / el / 1e9, "unit": "Gb/s", "cores": threads, "kind": "oracle",
-            "sample": "%d full blocks of n=%d, m=%d (all %d outputs each), %.1f s" % (reps, n, m, m, el),
-            "one_thread_Gbs": n / one / 1e9, "cpu_model": cpu_model()}
+    rates_sorted = sorted(rates)
+    return ({"value": rates_sorted[len(rates) // 2], "unit": "Gb/s", "cores": threads, "kind": "oracle",
+             "sample": "median of %d runs of back-to-back full blocks of n=%d, m=%d (all %d outputs each): %s"
+                       % (runs, n, m, m, "; ".join(samples)),
+             "runs_Gbs": rates, "one_thread_Gbs": n / one / 1e9, "cpu_model": cpu_model(),
+             "build": "gcc -O3 -march=native -fopenmp"}, want)
 
 
 def cpu_model() -> str:
@@ -184,7 +200,7 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
 
 
 def large_block_run(pa, wl, torch, np, stream, steps, tune):
-    """Config 3: one block of n = 12.8e6 key bits, m = 1.28e6 outputs."""
+    """One large block: n = 12.8e6 key bits, m = 1.28e6 outputs."""
     n, m = 12_800_000, 1_280_000
     if tune:
         pa.autotune(pa.transform_len(n, m), count=1, reps=5, stream=stream)
@@ -195,8 +211,42 @@ def large_block_run(pa, wl, torch, np, stream, steps, tune):
     ms, _ = time_steps(lambda: pa.toeplitz_hash(dk, n, ds, m, out, stream=stream), steps, 3, torch)
     L = pa.transform_len(n, m)
     g = pa.plan_info(L, *pa.tune_get(L, 0))
-    return {"value": n / (ms * 1e-3) / 1e9, "unit": "Gb/s", "ms_per_block": ms, "n": n, "m": m, "transform_len": L,
-            "rows": g["rows"], "cols": g["cols"], "row_round_size": g["row_round_size"]}
+    res = {"value": n / (ms * 1e-3) / 1e9, "unit": "Gb/s", "ms_per_block": ms, "n": n, "m": m, "transform_len": L,
+           "rows": g["rows"], "cols": g["cols"], "row_round_size": g["row_round_size"]}
+    return res, (k, s, n, m, out.cpu().numpy().view(np.uint64)[: wl.words(m)].copy())
+
+
+def small_block_run(pa, wl, torch, np, stream, steps, tune):
+    """One small block: n = 262,144 key bits, m = 65,536 outputs
+    (several column tiles and row groups; every array fits in cache)."""
+    n, m = 262_144, 65_536
+    L = pa.transform_len(n, m)
+    if tune:
+        pa.autotune(L, count=1, reps=20, stream=stream)
+    k, s = wl.key_and_seed(1, n, m, 0)
+    dk = torch.from_numpy(k.view(np.int64)).cuda()
+    ds = torch.from_numpy(s.view(np.int64)).cuda()
+    out = torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")
+    ms, _ = time_steps(lambda: pa.toeplitz_hash(dk, n, ds, m, out, stream=stream), steps, 10, torch)
+    g = pa.plan_info(L, *pa.tune_get(L, 0))
+    res = {"value": n / (ms * 1e-3) / 1e9, "unit": "Gb/s", "ms_per_block": ms, "n": n, "m": m, "transform_len": L,
+           "rows": g["rows"], "cols": g["cols"]}
+    return res, (k, s, n, m, out.cpu().numpy().view(np.uint64)[: wl.words(m)].copy())
+
+
+def oracle_parity(cases):
+    """Word-for-word comparison of timed GPU outputs with the CPU oracle:
+    cases maps a name to a list of (key, seed, n, m, gpu_out) host arrays."""
+    import numpy as np
+    import oracle
+    res = {}
+    for name, items in cases.items():
+        bad = 0
+        for k, s, n, m, got in items:
+            if not np.array_equal(got, oracle.toeplitz_hash(k, n, s, m)):
+                bad += 1
+        res[name] = {"blocks": len(items), "differing_blocks": bad, "equal": bad == 0}
+    return res
 
 
 def plan_run(pa, wl, torch, np, n, m, steps, stream):
@@ -422,10 +472,12 @@ def main():
 
     # batched: args.batch blocks of the same shape in one submission
     batched = None
+    batched_io = []
     if args.batch > 0:
         blocks = []
         for i in range(args.batch):
             k_i, s_i = wl.key_and_seed(4, n, m, i)
+            batched_io.append((k_i, s_i, n, m))
             blocks.append((torch.from_numpy(k_i.view(np.int64)).cuda(), n, torch.from_numpy(s_i.view(np.int64)).cuda(),
                            m, torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")))
 
@@ -440,6 +492,8 @@ def main():
         tuning["batched_geometry"] = pa.plan_info(L, *pa.tune_get(L, 1))
         bsteps = max(3, args.steps // 40)
         bms, _ = time_steps(bstep, bsteps, 2, torch)
+        batched_io = [io + (b[4].cpu().numpy().view(np.uint64)[: wl.words(m)].copy(),)
+                      for io, b in zip(batched_io, blocks)]
         with pa.BatchGraph(blocks) as bgraph:
             gms, _ = time_steps(lambda: bgraph.launch(stream=stream), bsteps, 2, torch)
         pa.profile_enable(True)
@@ -470,8 +524,10 @@ def main():
                                                                           modified["batched_Gbs"]))
     planr = plan_run(pa, wl, torch, np, n, m, args.steps, stream)
     progress("plan path: %.2f Gb/s (spectrum built once in %.2f ms)" % (planr["Gbs"], planr["spectrum_build_ms"]))
-    large = large_block_run(pa, wl, torch, np, stream, 20, not args.no_tune)
-    progress("config 3 (n=12.8e6): %.2f Gb/s" % large["value"])
+    large, large_io = large_block_run(pa, wl, torch, np, stream, 20, not args.no_tune)
+    progress("large block (n=12.8e6): %.2f Gb/s" % large["value"])
+    small, small_io = small_block_run(pa, wl, torch, np, stream, args.steps, not args.no_tune)
+    progress("small block (n=262144): %.2f Gb/s" % small["value"])
     fftp = fft_pair_run(pa, wl, torch, np, n, m, 50)
     progress("FFT pair: %.2f Gb/s, %.2f of HBM peak per call, max rounding error %.3g"
              % (fftp["Gbs"], fftp["hbm_frac_call"], fftp["max_rounding_error"]))
@@ -483,9 +539,23 @@ def main():
     alu = pa.alu_probe(stream)
     alu["fma_frac_of_peak"] = alu["fma_Tops"] / FP64_VALU_PEAK_TOPS
     progress("fp64 FMA: %.1f T/s, modular products: %.0f G/s" % (alu["fma_Tops"], alu["mulmod_Gops"]))
-    cpu = None if args.no_cpu else cpu_baseline(key, seed, n, m)
-    if cpu is not None:
+    # the timed outputs against the CPU oracle, word for word
+    plain_out = out.cpu().numpy().view(np.uint64)[: wl.words(m)].copy()
+    cases = {"small_block_n262144": [small_io], "large_block_n12800000": [large_io]}
+    if batched_io:
+        cases["batched_256_n1e6"] = batched_io
+    parity = oracle_parity(cases)
+    if args.no_cpu:
+        import oracle
+        want = oracle.toeplitz_hash(key, n, seed, m)
+        cpu = None
+    else:
+        cpu, want = cpu_baseline(key, seed, n, m)
         progress("cpu baseline: %.4g %s" % (cpu["value"], cpu["unit"]))
+    parity = dict({"headline_block_n1000000": {"blocks": 1, "differing_blocks": int(not np.array_equal(plain_out, want)),
+                                              "equal": bool(np.array_equal(plain_out, want))}}, **parity)
+    parity_ok = all(v["equal"] for v in parity.values())
+    progress("parity against the oracle: %s" % ("all equal" if parity_ok else parity))
     line = {
         "metric": METRIC, "value": value, "unit": "Gb/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -494,8 +564,9 @@ def main():
                                "Bernoulli(0.5) key and seed bits, packed uint64", "n": n, "m": m,
                    "transform_len": pa.transform_len(n, m)},
         "wall_s_timed_region": wall,
+        "parity": parity_ok, "parity_detail": parity,
         "roofline": roofline, "roofline_hbm": roofline_hbm, "kernels": kernels,
-        "batched": batched, "batched_uneven": uneven, "large_block": large, "modified_toeplitz": modified,
+        "batched": batched, "batched_uneven": uneven, "large_block": large, "small_block": small, "modified_toeplitz": modified,
         "plan_path": planr, "fft_pair": fftp,
         "serving": serving,
         "tuning": tuning, "copy_bandwidth": copy, "alu_probe": alu, "cpu_baseline": cpu,

@@ -19,26 +19,44 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "toeplitz_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_NATIVE_PATH = os.path.join(_HERE, "liboracle_native.so")
 _lib = None
+_lib_path = None
 
 
-def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc/OpenMP (portable x86-64-v3 code)."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-shared", "-fPIC",
+def build(force: bool = False, native: bool = False) -> str:
+    """Compile the oracle with gcc/OpenMP.  The default build is portable
+    x86-64-v3 code (it may be built on one machine and run on another);
+    native=True builds liboracle_native.so for the CPU it is compiled on
+    (-march=native), for timing the oracle on the machine that runs it."""
+    path = _NATIVE_PATH if native else _LIB_PATH
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O3", "-march=native" if native else "-march=x86-64-v3", "-fopenmp", "-shared", "-fPIC",
                "-std=c99", "-Wall", "-Wextra", "-o", tmp, _SRC]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+        os.replace(tmp, path)
+    return path
+
+
+def select_native() -> str:
+    """Compile for the CPU of this machine (always, since a build from
+    another machine may use instructions this one lacks) and switch every
+    later call to that build of the same source."""
+    global _lib, _lib_path
+    path = build(force=True, native=True)
+    _lib, _lib_path = None, path
+    _load()
+    return path
 
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        path = _lib_path or _LIB_PATH
+        if not os.path.exists(path):
             build()
-        lib = ctypes.CDLL(_LIB_PATH)
+        lib = ctypes.CDLL(path)
         u64p = ctypes.POINTER(ctypes.c_uint64)
         lib.oracle_toeplitz_hash.argtypes = [u64p, ctypes.c_uint64, u64p, ctypes.c_uint64, u64p, ctypes.c_int]
         lib.oracle_toeplitz_hash.restype = ctypes.c_int

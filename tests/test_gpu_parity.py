@@ -2,9 +2,8 @@
 
 Every case calls the C ABI (through the ctypes binding) on seeded synthetic
 Bernoulli(0.5) blocks and compares the packed output with the oracle word
-for word.  Full-size blocks beyond what the oracle finishes in seconds are
-checked on sampled output bits (computed one by one by the oracle) plus
-properties that hold at any size (linearity in the key, zero tail).
+for word.  Every block, up to the largest supported transform length, is compared in
+full; the 12.8e6-bit block is also checked for linearity in the key.
 """
 import numpy as np
 import pytest
@@ -89,37 +88,29 @@ def test_paper_finite_size_block():
     check_full(1_000_000, 250_000, cfg=2)
 
 
-def sampled_indices(m, count, gen):
-    fixed = [0, 1, 63, 64, 65, m // 2, m - 65, m - 64, m - 63, m - 2, m - 1]
-    rnd = gen.integers(0, m, size=count)
-    return np.unique(np.clip(np.array(fixed + list(rnd), dtype=np.int64), 0, m - 1))
-
-
-def test_large_block_sampled_and_linear():
+def test_large_block_full_and_linear():
+    # n = 12.8e6, m = 1.28e6: every output word against the oracle, plus
+    # linearity in the key (a property that holds at any size)
     n, m = 12_800_000, 1_280_000
     key, seed = wl.key_and_seed(3, n, m, 0)
     key2 = wl.random_bits(n, wl.rng(3, wl.ROLE_KEY, 1))
     y = gpu_hash(key, n, seed, m)
+    want = oracle.toeplitz_hash(key, n, seed, m)
+    assert np.array_equal(y, want), "%d of %d words differ" % (int(np.sum(y != want)), want.size)
     y2 = gpu_hash(key2, n, seed, m)
     y12 = gpu_hash(key ^ key2, n, seed, m)
     assert np.array_equal(y12, y ^ y2), "linearity in the key"
-    if m % 64:
-        assert int(y[-1]) >> (m % 64) == 0
-    idx = sampled_indices(m, 400, np.random.default_rng(5))
-    want = oracle.toeplitz_bits(key, n, seed, m, idx)
-    got = ((y[idx >> 6] >> (idx & 63).astype(np.uint64)) & np.uint64(1)).astype(np.uint8)
-    assert np.array_equal(got, want)
 
 
-def test_largest_supported_block_sampled():
+def test_largest_supported_block_full():
+    # the largest transform length (27 * 2^20): the row pass cannot hold two
+    # rows in LDS, so the seed spectrum goes through HBM (P2 modes 1 and 0)
     n, m = 24_000_000, 4_300_000
     assert pa.transform_len(n, m) == 27 * 2**20
     key, seed = wl.key_and_seed(15, n, m, 0)
     y = gpu_hash(key, n, seed, m)
-    idx = sampled_indices(m, 150, np.random.default_rng(6))
-    want = oracle.toeplitz_bits(key, n, seed, m, idx)
-    got = ((y[idx >> 6] >> (idx & 63).astype(np.uint64)) & np.uint64(1)).astype(np.uint8)
-    assert np.array_equal(got, want)
+    want = oracle.toeplitz_hash(key, n, seed, m)
+    assert np.array_equal(y, want), "%d of %d words differ" % (int(np.sum(y != want)), want.size)
 
 
 def test_all_ones_extremes():

@@ -65,6 +65,36 @@ pa_status pa_toeplitz_hash(const uint64_t *key_bits, uint64_t n,
                            const uint64_t *seed_bits, uint64_t m,
                            uint64_t *out_bits, void *stream);
 
+/*
+ * pa_toeplitz_hash without any allocation, for callers that cannot
+ * allocate device memory: code recorded under HIP stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, result
+ * and stream semantics as pa_toeplitz_hash; the two residue arrays of the
+ * block (8 L bytes, L = pa_transform_len(n, m)) live in one static device
+ * array of PA_NOALLOC_SCRATCH_BYTES per device, which the library holds
+ * from its first use on a device until the process ends.  No part of that
+ * array needs clearing: every pass writes all it later reads.
+ *
+ * Limits and preconditions:
+ *  - 8 L <= PA_NOALLOC_SCRATCH_BYTES, i.e. L <= 14,155,776 = 27 * 2^19
+ *    (n + m up to about 14.1e6 bits), else PA_ERR_UNSUPPORTED_SIZE before
+ *    any device call;
+ *  - the transform tables of length L must already be resident on the
+ *    current device: any earlier pa_toeplitz_hash call with a block of the
+ *    same transform length builds them (they stay until the process ends);
+ *    otherwise PA_ERR_INVALID_ARG and nothing is enqueued;
+ *  - every call on one device shares that device's array, so calls whose
+ *    work overlaps on one device (several streams, or host threads racing
+ *    on one stream) corrupt each other's results: order them on one stream
+ *    or synchronize.  The array keeps the last call's contents.
+ * It calls no hipMalloc, hipFree or other allocating routine, and records
+ * no profiling events.
+ */
+#define PA_NOALLOC_SCRATCH_BYTES 113246208ull
+pa_status pa_toeplitz_hash_noalloc(const uint64_t *key_bits, uint64_t n,
+                                   const uint64_t *seed_bits, uint64_t m,
+                                   uint64_t *out_bits, void *stream);
+
 /* One block of a batched call. */
 typedef struct pa_block {
     const uint64_t *key_bits; /* device, ceil(n/64) words */

@@ -91,6 +91,8 @@ def lib():
                 st = ctypes.c_int
                 L.pa_toeplitz_hash.argtypes = [vp, u64, vp, u64, vp, vp]
                 L.pa_toeplitz_hash.restype = st
+                L.pa_toeplitz_hash_noalloc.argtypes = [vp, u64, vp, u64, vp, vp]
+                L.pa_toeplitz_hash_noalloc.restype = st
                 L.pa_toeplitz_hash_batched.argtypes = [ctypes.POINTER(_Block), u32, vp]
                 L.pa_toeplitz_hash_batched.restype = st
                 L.pa_plan_create.argtypes = [vp, u64, u64, vp, ctypes.POINTER(vp)]
@@ -325,6 +327,19 @@ def toeplitz_hash(key, n: int, seed, m: int, out=None, stream=None):
     _check(lib().pa_toeplitz_hash(_ptr(key, words(n), "key"), int(n), _ptr(seed, words(n + m - 1), "seed"),
                                   int(m), _ptr(out, words(m), "out"), _stream_handle(stream)))
     return out
+
+
+def toeplitz_hash_noalloc(key, n: int, seed, m: int, out, stream=None):
+    """pa_toeplitz_hash_noalloc: y = T x mod 2 with the library's static
+    device scratch (no allocation; the caller provides out).  The transform
+    tables of the block's length must exist on the device (any earlier
+    toeplitz_hash call of that transform length builds them)."""
+    _check(lib().pa_toeplitz_hash_noalloc(_ptr(key, words(n), "key"), int(n), _ptr(seed, words(n + m - 1), "seed"),
+                                          int(m), _ptr(out, words(m), "out"), _stream_handle(stream)))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 113246208
 
 
 def toeplitz_hash_batched(blocks, stream=None):

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpa.so")
 
-SOURCES = ["pa_kernels.hip", "pa_plan.cpp", "pa_api.cpp", "pa_serve.cpp", "pa_tune.cpp", "pa_graph.cpp", "pa_fft.hip", "pa_fft_host.cpp", "pa_probe.hip"]
+SOURCES = ["pa_kernels.hip", "pa_plan.cpp", "pa_api.cpp", "pa_serve.cpp", "pa_tune.cpp", "pa_graph.cpp", "pa_fft.hip", "pa_fft_host.cpp", "pa_probe.hip", "pa_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -238,7 +238,11 @@ std::mutex g_prof_mu;
 bool g_prof_on = false;
 thread_local bool t_capturing = false;
 
-void set_capturing(bool on) { t_capturing = on; }
+bool set_capturing(bool on) {
+    const bool old = t_capturing;
+    t_capturing = on;
+    return old;
+}
 std::vector<ProfRec> g_prof;
 std::vector<hipEvent_t> g_event_pool;
 
@@ -405,6 +409,16 @@ pa_status plan_for(uint64_t L, int cls, pa::PlanRef *lp) {
     } catch (const std::exception &e) {
         return fail(PA_ERR_DEVICE, std::string("building transform tables: ") + e.what());
     }
+    return PA_OK;
+}
+
+pa_status plan_cached(uint64_t L, int cls, pa::PlanRef *lp) {
+    int a = 0, w = 0;
+    pa::tuned_geometry(L, cls, &a, &w);
+    if (!pa::find_len_plan(L, a, w, lp))
+        return fail(PA_ERR_INVALID_ARG, "the transform tables of length " + std::to_string(L) +
+                                            " are not resident on this device yet: hash one block of this "
+                                            "transform length with pa_toeplitz_hash first");
     return PA_OK;
 }
 

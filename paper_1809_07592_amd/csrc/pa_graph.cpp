@@ -43,8 +43,9 @@ void destroy_graph(pa_graph_s *g) {
 }
 
 struct CaptureFlag {
-    CaptureFlag() { set_capturing(true); }
-    ~CaptureFlag() { set_capturing(false); }
+    CaptureFlag() : old(set_capturing(true)) {}
+    ~CaptureFlag() { set_capturing(old); }
+    bool old;
 };
 
 }  // namespace

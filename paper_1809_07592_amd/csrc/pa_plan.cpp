@@ -391,6 +391,23 @@ std::vector<TunedEntry> tuned_entries() {
     return v;
 }
 
+bool find_len_plan(uint64_t L, int log2R_override, int W_override, PlanRef *out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    LenPlan g;
+    try {
+        plan_geometry(L, log2R_override, W_override, g);
+    } catch (const std::exception &) {
+        return false;
+    }
+    const uint64_t key_len = L | ((uint64_t)g.log2R << 40) | ((uint64_t)g.W << 48);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find({dev, key_len});
+    if (it == g_plans.end()) return false;
+    *out = {&it->second->plan, it->second->dplan};
+    return true;
+}
+
 PlanRef get_len_plan(uint64_t L, int log2R_override, int W_override) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) throw std::runtime_error("hipGetDevice failed");

@@ -39,6 +39,10 @@ struct PlanRef {
 // std::runtime_error on failure.
 PlanRef get_len_plan(uint64_t L, int log2R_override = 0, int W_override = 0);
 
+// The cached plan of length L in the given geometry on the current device,
+// if one was built earlier; never builds one (no device allocation).
+bool find_len_plan(uint64_t L, int log2R_override, int W_override, PlanRef *out);
+
 // Tuning table: the geometry used for length L in batch class cls (0: one
 // block per launch, 1: several).  (0, 0) means the built-in default.
 void tuned_geometry(uint64_t L, int cls, int *log2R, int *W);

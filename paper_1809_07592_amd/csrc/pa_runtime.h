@@ -56,6 +56,9 @@ pa_status get_readback(hipStream_t s, void **out, std::unique_lock<std::mutex> *
 // Cached device plan of length L in the tuned geometry of batch class cls
 // (0: one block per launch, 1: several).
 pa_status plan_for(uint64_t L, int cls, PlanRef *lp);
+// The same plan if it is already built on the current device, else
+// PA_ERR_INVALID_ARG; never allocates device memory.
+pa_status plan_cached(uint64_t L, int cls, PlanRef *lp);
 // Bytes of ceil(bits/64) words.
 double words8(uint64_t bits);
 // Descriptor of a plain-path block with workspace A, S (Shat = S).
@@ -100,8 +103,8 @@ pa_status join_lanes(hipStream_t s, int k);
 // Drops the side streams and events kept for stream s (before s is destroyed).
 void release_stream_state(hipStream_t s);
 // While set on the calling thread, launches record no timing events
-// (stream capture).
-void set_capturing(bool on);
+// (stream capture, calls that must not allocate); returns the previous value.
+bool set_capturing(bool on);
 // Spectrum of the first nbits seed bits into S (L residues), on stream s.
 pa_status run_seed_path(const PlanRef &p, const uint64_t *seed, uint64_t nbits, int32_t *S, hipStream_t s);
 

@@ -58,6 +58,20 @@ FAKE = 0x10000  # non-null, never dereferenced: validation fails first
 def test_rejects_before_device_work(lib, key, n, seed, m, out, status):
     assert lib.pa_toeplitz_hash(key, n, seed, m, out, None) == status
     assert len(pa.last_error()) > 0
+    assert lib.pa_toeplitz_hash_noalloc(key, n, seed, m, out, None) == status
+    assert len(pa.last_error()) > 0
+
+
+def test_noalloc_rejects_blocks_beyond_its_scratch(lib):
+    # 8 L bytes must fit the static scratch: L <= 27 * 2^19; the next
+    # supported length (27 * 2^20) is refused on the host, before any device call
+    assert pa.NOALLOC_SCRATCH_BYTES == 8 * 27 * 2**19
+    assert pa.transform_len(12_800_000, 1_280_000) == 27 * 2**19
+    n, m = 16_000_000, 1_000_000
+    L = pa.transform_len(n, m)
+    assert L == 27 * 2**20
+    assert lib.pa_toeplitz_hash_noalloc(FAKE, n, FAKE, m, FAKE, None) == pa.PA_ERR_UNSUPPORTED_SIZE
+    assert "scratch" in pa.last_error()
 
 
 def test_batched_validation(lib):

@@ -259,7 +259,10 @@ hipEvent_t pool_event() {
 
 // Algorithmic fp64 operations of one length-N transform (either
 // direction): a radix-2 butterfly is one modular product (3 FMAs) and two
-// adds, a radix-3 butterfly three products and seven adds.
+// adds, a radix-3 butterfly three products and seven adds.  One stage of
+// each transform has all factors 1 (the forward's first, the inverse's
+// last) and runs without its twiddle products: a radix-2 butterfly of it
+// costs 2 adds, a radix-3 one 3 FMAs and 7 adds.
 double xform_ops(const pa::XDesc &x) {
     double ops = 0;
     for (int r = 0; r < x.nrounds; ++r) {
@@ -267,8 +270,14 @@ double xform_ops(const pa::XDesc &x) {
         for (int i = 0; i < pa::kKindN3[k]; ++i) ops += (double)x.N / 3.0 * 16.0;
         for (int i = 0; i < pa::kKindN2[k]; ++i) ops += (double)x.N / 2.0 * 5.0;
     }
+    const int k0 = x.round[0].kind;
+    ops -= pa::kKindN3[k0] ? (double)x.N / 3.0 * 6.0 : (double)x.N / 2.0 * 3.0;
     return ops;
 }
+
+// The four-step twist in the column pass: per value one chain product (3
+// FMAs and one multiply for its quotient) and one applied product.
+constexpr double kColTwistOps = 7.0;
 
 // Launch `fn(start, stop)` (returning hipError_t); when profiling is on,
 // start / stop are pool events that the launch records with the kernel's
@@ -299,7 +308,7 @@ double words8(uint64_t bits) { return (double)((bits + 63) / 64) * 8.0; }
 hipError_t p1(const pa::PlanRef &p, int nsrc, const pa::JobArgs &ja, int njobs, double in_bytes, hipStream_t s) {
     const double L = (double)p.host->L;
     const double bytes = in_bytes + 4.0 * L * nsrc * njobs;
-    const double ops = (double)nsrc * njobs * xform_ops(p.host->col) * p.host->C;
+    const double ops = (double)nsrc * njobs * (xform_ops(p.host->col) * p.host->C + kColTwistOps * L);
     return timed("colfwd", bytes, ops,
                  [&](hipEvent_t a, hipEvent_t b) { return pa::launch_colfwd(*p.host, p.dev, nsrc, ja, njobs, s, a, b); });
 }
@@ -311,11 +320,11 @@ hipError_t p2(const pa::PlanRef &p, int mode, const pa::JobArgs &ja, int njobs, 
     double bytes = 0, ops = 0;
     if (mode == 1) {
         bytes = 8.0 * L;               // read residues, write spectrum
-        ops = xf + 6.0 * L + 3.0 * L;  // transform, twist, reduction
+        ops = xf + 3.0 * L;            // transform, reduction
     } else {
         bytes = 12.0 * L;              // read A and the spectrum (or S), write A
-        ops = 2.0 * xf + 12.0 * L + 4.0 * L;  // forward + inverse, two twists, product
-        if (mode == 2) ops += xf + 6.0 * L + 3.0 * L;
+        ops = 2.0 * xf + 6.0 * L + 4.0 * L;  // forward + inverse, inverse twist, product
+        if (mode == 2) ops += xf + 3.0 * L;  // seed transform and its reduction
     }
     return timed(mode == 1 ? "rowspec" : "rowconv", bytes * njobs, ops * njobs,
                  [&](hipEvent_t a, hipEvent_t b) { return pa::launch_rowconv(*p.host, p.dev, mode, ja, njobs, s, a, b); });

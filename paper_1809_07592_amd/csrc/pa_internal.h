@@ -115,8 +115,7 @@ struct LenPlan {
     XDesc row;               // length-C transform (row pass)
     const double2 *twist_lo; // omega_L^i, i < 4096
     const double2 *twist_hi; // omega_L^(4096 i), i < ceil(L / 4096)
-    const double2 *alpha_f;  // [k1][u] = omega_L^(k1 * (C/rho0) * u)
-    const double2 *alpha_i;  // [k1][u] = omega_L^(-k1 * (C/rho0) * u) / L
+    const double2 *alpha_i;  // [k1][u] = omega_L^(-k1 * (C/rho0) * u) / L (inverse twist of the row pass)
 };
 
 // One block of work for the pass kernels (a plain hash, a plan hash, or a

@@ -2,14 +2,15 @@
 // key bits with the seed bits by a number-theoretic transform modulo
 // P = 27*2^20+1, in the four-step layout L = R x C (row-major R x C view):
 //
-//   P1  k_colfwd_bits : unpack bits (key shifted to word-align the output),
+//   P1  k_colfwd      : unpack bits (key shifted to word-align the output),
 //                       length-R forward NTT down each column of a W-wide
-//                       tile in LDS; write residues (int32).
-//   P2  k_rowconv     : per row: twist by omega_L^(j2 k1), length-C forward
-//                       NTT, pointwise product with the seed spectrum,
-//                       inverse NTT, inverse twist; in place.  In seed mode:
-//                       twist, forward NTT, scale by 1/L, store the spectrum.
-//   P3  k_colinv_bits : inverse length-R NTT down each column tile, exact
+//                       tile in LDS, four-step twist omega_L^(k1 j2); write
+//                       residues (int32).
+//   P2  k_rowconv     : per row: length-C forward NTT, pointwise product
+//                       with the seed spectrum, inverse NTT, inverse twist
+//                       (carrying 1/L); in place.  In seed mode: forward
+//                       NTT, store the reduced spectrum.
+//   P3  k_colinv      : inverse length-R NTT down each column tile, exact
 //                       canonical residue, parity, wave64 ballot, packed
 //                       store of the output window [n-1, n+m-1).
 //
@@ -66,6 +67,13 @@ __device__ __forceinline__ int ld32(rsrc_t r, int byte_off) {
 __device__ __forceinline__ void st32(rsrc_t r, int byte_off, int v) {
     __builtin_amdgcn_raw_buffer_store_b32((unsigned)v, r, byte_off, 0, 0);
 }
+// Store with device-scope coherence (cache policy SC1): written through the
+// L2, so the kernel's end has no dirty lines of it to write back.  Measured
+// faster for residue arrays that the next pass reads, except for the
+// column pass of large batches (many MB per launch), which keeps st32.
+__device__ __forceinline__ void st32_wt(rsrc_t r, int byte_off, int v) {
+    __builtin_amdgcn_raw_buffer_store_b32((unsigned)v, r, byte_off, 0, 16);
+}
 __device__ __forceinline__ void st16(rsrc_t r, int byte_off, unsigned v) {
     __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, byte_off, 0, 0);
 }
@@ -81,6 +89,14 @@ __device__ __forceinline__ double2 ld_tw(rsrc_t r, int index) {
     __builtin_memcpy(&d, &v, sizeof(d));
     return d;
 }
+
+// Read-only data addressed uniformly across the wave, through the constant
+// address space so that loads from it are scalar (s_load).
+struct TwPair {
+    double w, wp;
+};
+typedef __attribute__((address_space(4))) const TwPair ctwpair;
+__device__ __forceinline__ double2 ld_const(const ctwpair *t, int i) { return make_double2(t[i].w, t[i].wp); }
 
 // Wave-uniform copies (SGPRs) of values the compiler cannot prove uniform;
 // buffer resources built from them need no waterfall loop.
@@ -99,6 +115,58 @@ __device__ __forceinline__ double2 twist_factor(rsrc_t lo_t, rsrc_t hi_t, uint32
     const double2 hi = ld_tw(hi_t, (int)(e >> 12));
     const double w = mulmod(hi.x, lo.x, lo.y);
     return make_double2(w, w * kPinv);
+}
+
+// The four-step twist of the column pass's output.  The length-R column
+// transform leaves frequency k1 = bitrev(q) at row q.  In a round with unit
+// stride (the transform's last round) a work item holds the RHO rows
+// q0 + l (q0 a multiple of RHO) of column c, so k1(l) = bitrev(q0) +
+// rev(l) * R / RHO, where rev reverses the lg RHO bits of l, and its twist
+// omega_L^(c k1(l)) is base * step^rev(l) with base = omega_L^(c bitrev(q0))
+// and step = omega_L^(c R / RHO).  The factors are formed as that power
+// chain, one product each, and each twisted value (reduced, |v| <= P/2 + 4)
+// goes to emit(l, value) as soon as it is formed.
+template <int LG>
+__device__ __forceinline__ int rev_bits(int l) {
+    int r = 0;
+#pragma unroll
+    for (int i = 0; i < LG; ++i) r |= ((l >> i) & 1) << (LG - 1 - i);
+    return r;
+}
+
+// Table entries (lo, hi halves of the exponent) of base and step, loaded
+// when the round starts so that their latency overlaps its other work.
+struct ColTwist {
+    double2 b_lo, s_lo;  // (w, w/P) of the low parts
+    double b_hi, s_hi;   // w of the high parts
+};
+
+// Exponents: base c * bitrev_log2R(q0), step c * 2^(log2R - LG).
+template <int LG>
+__device__ __forceinline__ ColTwist column_twist_load(rsrc_t lo_t, rsrc_t hi_t, int log2R, uint32_t c, uint32_t q0) {
+    const uint32_t k10 = __builtin_bitreverse32(q0) >> (32 - log2R);
+    const uint32_t eb = c * k10, es = c * ((1u << log2R) >> LG);  // both < L
+    return ColTwist{ld_tw(lo_t, (int)(eb & 4095u)), ld_tw(lo_t, (int)(es & 4095u)), ld_tw(hi_t, (int)(eb >> 12)).x,
+                    ld_tw(hi_t, (int)(es >> 12)).x};
+}
+
+template <int RHO, class Emit>
+__device__ __forceinline__ void column_twist(double (&v)[RHO], const ColTwist &t, Emit &&emit) {
+    constexpr int LG = RHO == 1 ? 0 : RHO == 2 ? 1 : RHO == 4 ? 2 : RHO == 8 ? 3 : 4;
+    static_assert((1 << LG) == RHO, "column rounds hold a power of two of values");
+    const double wb = mulmod(t.b_hi, t.b_lo.x, t.b_lo.y);
+    const double ws = mulmod(t.s_hi, t.s_lo.x, t.s_lo.y);
+    double2 f = make_double2(wb, wb * kPinv);
+    const double2 st = make_double2(ws, ws * kPinv);
+#pragma unroll
+    for (int j = 0; j < RHO; ++j) {
+        const int l = rev_bits<LG>(j);
+        emit(l, mulmod(v[l], f.x, f.y));
+        if (j + 1 < RHO) {
+            const double w = mulmod(f.x, st.x, st.y);
+            f = make_double2(w, w * kPinv);
+        }
+    }
 }
 
 // ------------------------------------------------------------ round shapes
@@ -132,35 +200,38 @@ using RegArrN = double[NA][(N3 == 0 ? 1 : N3 == 1 ? 3 : N3 == 2 ? 9 : 27) << N2]
 // Forward Cooley-Tukey stage K of a round: block index b_full = b*before+sb,
 // input u multiplied by gamma^u (table entry), then r-point DFT.
 // NA arrays (NA = 2: the seed and key rows of the fused row pass) share
-// each stage's twiddles.
-template <int N3, int N2, int K, int NA>
+// each stage's twiddles.  TRIV: the transform's first stage, whose one
+// block has gamma = 1, so its inputs enter the DFT unmultiplied (they are
+// reduced residues or bits, within the bound a product would give).
+template <int N3, int N2, int K, int NA, bool TRIV = false>
 __device__ __forceinline__ void fwd_stage(RegArrN<N3, N2, NA> &v, int b, const double2 *__restrict__ tw, int off) {
     using S = Shape<N3, N2>;
     constexpr int r = S::radix(K), rb = S::before(K), ra = S::after(K);
+    static_assert(!TRIV || rb == 1, "only the first stage has a single block");
 #pragma unroll
     for (int sb = 0; sb < rb; ++sb) {
         const int t = off + (b * rb + sb) * (r - 1);
         if constexpr (r == 2) {
-            const double2 w = tw[t];
+            const double2 w = TRIV ? make_double2(1.0, 0.0) : tw[t];
 #pragma unroll
             for (int a = 0; a < NA; ++a)
 #pragma unroll
                 for (int x = 0; x < ra; ++x) {
                     const int i0 = sb * 2 * ra + x, i1 = i0 + ra;
-                    const double mm = mulmod(v[a][i1], w.x, w.y);
+                    const double mm = TRIV ? v[a][i1] : mulmod(v[a][i1], w.x, w.y);
                     const double y = v[a][i0];
                     v[a][i0] = y + mm;
                     v[a][i1] = y - mm;
                 }
         } else {
-            const double2 w1 = tw[t], w2 = tw[t + 1];
+            const double2 w1 = TRIV ? make_double2(1.0, 0.0) : tw[t], w2 = TRIV ? make_double2(1.0, 0.0) : tw[t + 1];
 #pragma unroll
             for (int a = 0; a < NA; ++a)
 #pragma unroll
                 for (int x = 0; x < ra; ++x) {
                     const int i0 = sb * 3 * ra + x, i1 = i0 + ra, i2 = i1 + ra;
-                    const double b1 = mulmod(v[a][i1], w1.x, w1.y);
-                    const double c1 = mulmod(v[a][i2], w2.x, w2.y);
+                    const double b1 = TRIV ? v[a][i1] : mulmod(v[a][i1], w1.x, w1.y);
+                    const double c1 = TRIV ? v[a][i2] : mulmod(v[a][i2], w2.x, w2.y);
                     const double tt = mulmod(b1 - c1, kW3, kW3p);
                     const double y = v[a][i0];
                     v[a][i0] = y + b1 + c1;
@@ -172,32 +243,35 @@ __device__ __forceinline__ void fwd_stage(RegArrN<N3, N2, NA> &v, int b, const d
 }
 
 // Inverse (decimation in time) stage K of a round: input i of the r-point
-// inverse DFT multiplied by omega_M^(-j' i), j' = x*J_last + jj.
-template <int N3, int N2, int K>
+// inverse DFT multiplied by omega_M^(-j' i), j' = x*J_last + jj.  TRIV: the
+// transform's last stage (inverted first), whose sub-blocks have length 1,
+// so j' = 0 and the factor is 1; its inputs are reduced residues.
+template <int N3, int N2, int K, bool TRIV = false>
 __device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, const double2 *__restrict__ tw,
                                           int off) {
     using S = Shape<N3, N2>;
     constexpr int r = S::radix(K), rb = S::before(K), ra = S::after(K);
+    static_assert(!TRIV || ra == 1, "only the last stage has unit sub-blocks");
 #pragma unroll
     for (int x = 0; x < ra; ++x) {
         const int t = off + (x * jlast + jj) * (r - 1);
         if constexpr (r == 2) {
-            const double2 w = tw[t];
+            const double2 w = TRIV ? make_double2(1.0, 0.0) : tw[t];
 #pragma unroll
             for (int sb = 0; sb < rb; ++sb) {
                 const int i0 = sb * 2 * ra + x, i1 = i0 + ra;
-                const double mm = mulmod(v[i1], w.x, w.y);
+                const double mm = TRIV ? v[i1] : mulmod(v[i1], w.x, w.y);
                 const double a = v[i0];
                 v[i0] = a + mm;
                 v[i1] = a - mm;
             }
         } else {
-            const double2 w1 = tw[t], w2 = tw[t + 1];
+            const double2 w1 = TRIV ? make_double2(1.0, 0.0) : tw[t], w2 = TRIV ? make_double2(1.0, 0.0) : tw[t + 1];
 #pragma unroll
             for (int sb = 0; sb < rb; ++sb) {
                 const int i0 = sb * 3 * ra + x, i1 = i0 + ra, i2 = i1 + ra;
-                const double b1 = mulmod(v[i1], w1.x, w1.y);
-                const double c1 = mulmod(v[i2], w2.x, w2.y);
+                const double b1 = TRIV ? v[i1] : mulmod(v[i1], w1.x, w1.y);
+                const double c1 = TRIV ? v[i2] : mulmod(v[i2], w2.x, w2.y);
                 const double tt = mulmod(b1 - c1, kW3i, kW3ip);
                 const double a = v[i0];
                 v[i0] = a + b1 + c1;
@@ -215,23 +289,25 @@ __device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, 
 template <int N3, int N2>
 constexpr bool kStageFence = Shape<N3, N2>::RHO > 8 && Shape<N3, N2>::RHO != 16;
 
-template <int N3, int N2, int K, int NA>
+// FIRST: the round holds the transform's first stage (K = 0 is trivial).
+template <int N3, int N2, int K, int NA, bool FIRST = false>
 __device__ __forceinline__ void fwd_stages(RegArrN<N3, N2, NA> &v, int b, const XDesc &xd,
                                            const double2 *__restrict__ tw, int s0) {
     if constexpr (K < Shape<N3, N2>::Q) {
-        fwd_stage<N3, N2, K, NA>(v, b, tw, xd.fwd_off[s0 + K]);
+        fwd_stage<N3, N2, K, NA, FIRST && K == 0>(v, b, tw, xd.fwd_off[s0 + K]);
         if constexpr (kStageFence<N3, N2>) __builtin_amdgcn_sched_barrier(0);
-        fwd_stages<N3, N2, K + 1, NA>(v, b, xd, tw, s0);
+        fwd_stages<N3, N2, K + 1, NA, FIRST>(v, b, xd, tw, s0);
     }
 }
 
-template <int N3, int N2, int K>
+// LAST: the round holds the transform's last stage (K = Q-1 is trivial).
+template <int N3, int N2, int K, bool LAST = false>
 __device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast, const XDesc &xd,
                                            const double2 *__restrict__ tw, int s0) {
     if constexpr (K >= 0) {
-        inv_stage<N3, N2, K>(v, jj, jlast, tw, xd.inv_off[s0 + K]);
+        inv_stage<N3, N2, K, LAST && K == Shape<N3, N2>::Q - 1>(v, jj, jlast, tw, xd.inv_off[s0 + K]);
         if constexpr (kStageFence<N3, N2>) __builtin_amdgcn_sched_barrier(0);
-        inv_stages<N3, N2, K - 1>(v, jj, jlast, xd, tw, s0);
+        inv_stages<N3, N2, K - 1, LAST>(v, jj, jlast, xd, tw, s0);
     }
 }
 
@@ -306,7 +382,7 @@ __device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, c
         }
         if constexpr (MODE == MODE_FWD || MODE == MODE_CONV) {
             if (FIRST)
-                fwd_stages<N3, N2, 0, NA>(v, 0, xd, ftw, rd.s0);
+                fwd_stages<N3, N2, 0, NA, FIRST>(v, 0, xd, ftw, rd.s0);
             else if (b_uniform)
                 fwd_stages<N3, N2, 0, NA>(v, __builtin_amdgcn_readfirstlane(b), xd, ftw, rd.s0);
             else
@@ -315,12 +391,12 @@ __device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, c
         if constexpr (NA == 1) {
             if constexpr (MODE == MODE_CONV) mid(ctx, v[0], launder(G));
             if constexpr (MODE == MODE_INV || MODE == MODE_CONV)
-                inv_stages<N3, N2, Shape<N3, N2>::Q - 1>(v[0], jj, J, xd, itw, rd.s0);
+                inv_stages<N3, N2, Shape<N3, N2>::Q - 1, LAST>(v[0], jj, J, xd, itw, rd.s0);
             store(ctx, v[0], launder(G));
         } else {
             if constexpr (MODE == MODE_CONV) {
                 mid(ctx, v, launder(G));
-                inv_stages<N3, N2, Shape<N3, N2>::Q - 1>(v[1], jj, J, xd, itw, rd.s0);
+                inv_stages<N3, N2, Shape<N3, N2>::Q - 1, LAST>(v[1], jj, J, xd, itw, rd.s0);
                 store(ctx, v[1], launder(G));
             } else {
                 store(ctx, v, launder(G));
@@ -419,7 +495,7 @@ __device__ __forceinline__ JobDesc job_of(const JobArgs &ja, unsigned idx) {
 
 // MAXLG: largest radix-2 round of the plan's column transform (3: rounds of
 // at most 8 values, compiled without the 16-value case and its registers).
-template <int MAXLG>
+template <int MAXLG, bool WT>
 __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan, JobArgs ja,
                                                 const double2 *__restrict__ ftw) {
     const double2 *itw = nullptr;
@@ -440,8 +516,8 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
     const int c0 = xcd_tile(blockIdx.x, lp.ntiles) * W;
     int *lds = pa_lds;
     auto pre = [&](int, int, int) PA_INLINE { return NoCtx{}; };
-    auto mid = [&](NoCtx, auto &, Geo) PA_INLINE {};
-    auto load_bits = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double {
+    auto mid = [&](const auto &, auto &, Geo) PA_INLINE {};
+    auto load_bits = [&](const auto &, const Geo &g, int l) PA_INLINE -> double {
         // branch-free: a negative p reads out of range (0); bits >= nbits are masked
         const int p = (g.q0 + (l * g.J)) * C + c0 + g.c - shift;
         const int pr = p + ro;
@@ -449,20 +525,34 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
         const unsigned bit = (w >> (pr & 31)) & ((unsigned)p < (unsigned)nbits ? 1u : 0u);
         return (double)bit;
     };
-    auto load_lds = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double {
+    auto load_lds = [&](const auto &, const Geo &g, int l) PA_INLINE -> double {
         return (double)lds[g.lbase + l * g.lstep];
     };
-    auto store_lds = [&](NoCtx, auto &v, Geo g) PA_INLINE {
+    auto store_lds = [&](const auto &, auto &v, Geo g) PA_INLINE {
 #pragma unroll
         for (int l = 0; l < group_size(v); ++l) lds[g.lbase + l * g.lstep] = (int)v[l];
     };
-    auto store_glb = [&](NoCtx, auto &v, Geo g) PA_INLINE {
-#pragma unroll
-        for (int l = 0; l < group_size(v); ++l) st32(out, ((g.q0 + (l * g.J)) * C + c0 + g.c) * 4, (int)v[l]);
+    const rsrc_t rs_lo = make_rsrc(uni(lp.twist_lo), 4096 * 16);
+    const rsrc_t rs_hi = make_rsrc(uni(lp.twist_hi), (uint32_t)((lp.L + 4095) / 4096) * 16);
+    // last round (unit stride, block b of RHO rows): twist by
+    // omega_L^(k1 c), then store; the twist's table loads start with the round
+    const int lg_last = kKindN2[xd.round[xd.nrounds - 1].kind];
+    auto pre_tw = [&](int c, int b, int) PA_INLINE {
+        return column_twist_load<0>(rs_lo, rs_hi, lp.log2R - lg_last, (uint32_t)(c0 + c), (uint32_t)b);
+    };
+    auto store_glb = [&](const ColTwist &t, auto &v, Geo g) PA_INLINE {
+        constexpr int RHO = (int)(sizeof(v) / sizeof(v[0]));
+        column_twist<RHO>(v, t, [&](int l, double x) PA_INLINE {
+            const int off = ((g.q0 + (l * g.J)) * C + c0 + g.c) * 4;
+            if constexpr (WT)
+                st32_wt(out, off, (int)x);
+            else
+                st32(out, off, (int)x);
+        });
     };
     const int nr = xd.nrounds;
     if (nr == 1) {
-        round_p2<MODE_FWD, true, true, MAXLG>(xd, ftw, itw, 0, wsh, pre, load_bits, mid, store_glb);
+        round_p2<MODE_FWD, true, true, MAXLG>(xd, ftw, itw, 0, wsh, pre_tw, load_bits, mid, store_glb);
         return;
     }
     round_p2<MODE_FWD, true, false, MAXLG>(xd, ftw, itw, 0, wsh, pre, load_bits, mid, store_lds);
@@ -471,18 +561,20 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
         round_p2<MODE_FWD, false, false, MAXLG>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
         __syncthreads();
     }
-    round_p2<MODE_FWD, false, true, MAXLG>(xd, ftw, itw, nr - 1, wsh, pre, load_lds, mid, store_glb);
+    round_p2<MODE_FWD, false, true, MAXLG>(xd, ftw, itw, nr - 1, wsh, pre_tw, load_lds, mid, store_glb);
 }
 
-// P2: one row (index blockIdx.x, column-spectrum index k1 = bitrev(row)).
-// Spectra are stored reduced (|s| <= P/2 + 4) so that a product of an
-// unreduced transform value (<= ~8 P) with them stays exact.
-//   mode 0: A <- twist^-1 . INTT_C( NTT_C(twist . A) * Shat )      (plan path)
-//   mode 1: S <- NTT_C(twist . S)                                   (seed spectrum)
-//   mode 2: as mode 0 with Shat = NTT_C(twist . S) computed here    (plain path)
-// blockIdx.y selects the job.
+// P2: one row of the twisted column spectra (the column pass applied the
+// four-step twist omega_L^(k1 j2)), blockIdx.x = row (k1 = bitrev(row)),
+// blockIdx.y = job.  Spectra are stored reduced (|s| <= P/2 + 4) so that a
+// product of an unreduced transform value (<= ~9 P) with them stays exact.
+//   mode 0: A <- twist^-1 . INTT_C( NTT_C(A) * Shat )         (plan path)
+//   mode 1: S <- NTT_C(S), reduced                            (seed spectrum)
+//   mode 2: as mode 0 with Shat = NTT_C(S) computed here      (plain path)
 // The inverse twist carries the 1/L of the inverse transform.  Round 0's
-// group is q = jj + l*J0 (J0 = C/rho0), twisted by beta(jj) * alpha(l).
+// group is q = jj + l*J0 (J0 = C/rho0): its inverse twist is
+// beta(jj) * alpha(l), beta(jj) = omega_L^(-k1 jj), alpha(l) =
+// omega_L^(-k1 J0 l) / L.
 struct TwCtx {
     double2 beta;
 };
@@ -498,42 +590,38 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
     const JobDesc job = job_of(ja, blockIdx.y);
     const int C = lp.C, nr = xd.nrounds;
     const uint32_t row = blockIdx.x;
-    const uint32_t k1 = __builtin_bitreverse32(row) >> (32 - lp.log2R);
-    const uint32_t L = (uint32_t)lp.L;
     const size_t rbase = (size_t)row * (size_t)C;
     const rsrc_t rowA = make_rsrc(job.A + rbase, (uint32_t)C * 4);
     const rsrc_t rowS = make_rsrc(job.S + rbase, (uint32_t)C * 4);
     const rsrc_t rowH = make_rsrc(job.Shat + rbase, (uint32_t)C * 4);
     int *lds_a = pa_lds;
     int *lds_s = pa_lds + lp.row_lds;
-    const rsrc_t rs_af = make_rsrc(uni(lp.alpha_f) + (size_t)k1 * lp.rho0, (uint32_t)lp.rho0 * 16);
-    const rsrc_t rs_ai = make_rsrc(uni(lp.alpha_i) + (size_t)k1 * lp.rho0, (uint32_t)lp.rho0 * 16);
+    const uint32_t k1 = __builtin_bitreverse32(row) >> (32 - lp.log2R);
+    const uint32_t L = (uint32_t)lp.L;
+    // the row's alpha factors are the same for every item: scalar loads
+    const ctwpair *ai = (const ctwpair *)(uni(lp.alpha_i) + (size_t)k1 * lp.rho0);
     const rsrc_t rs_lo = make_rsrc(uni(lp.twist_lo), 4096 * 16);
     const rsrc_t rs_hi = make_rsrc(uni(lp.twist_hi), (uint32_t)((lp.L + 4095) / 4096) * 16);
 
     auto pre_none = [&](int, int, int) PA_INLINE { return NoCtx{}; };
-    auto pre_fwd = [&](int, int, int jj) PA_INLINE { return TwCtx{twist_factor(rs_lo, rs_hi, k1 * (uint32_t)jj)}; };
     auto pre_inv = [&](int, int, int jj) PA_INLINE {
         const uint32_t e = k1 * (uint32_t)jj;
         return TwCtx{twist_factor(rs_lo, rs_hi, e == 0 ? 0u : L - e)};
     };
-    auto mid_none = [&](auto, auto &, Geo) PA_INLINE {};
+    auto mid_none = [&](const auto &, auto &, Geo) PA_INLINE {};
 
-    // forward transform of one row: round 0 from HBM with the twist, rounds
-    // 1 .. last-1 in LDS; the last round is left to the caller.
+    // forward transform of one row: round 0 from HBM, rounds 1 .. last-1
+    // in LDS; the last round is left to the caller.
     auto forward_head = [&](rsrc_t src, int *lds) PA_INLINE {
-        auto load_tw = [&](TwCtx t, const Geo &g, int l) PA_INLINE -> double {
-            const double x = (double)ld32(src, (g.q0 + (l * g.J)) * 4);
-            const double y = mulmod(x, t.beta.x, t.beta.y);
-            const double2 al = ld_tw(rs_af, l);
-            return mulmod(y, al.x, al.y);
+        auto load_g = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double {
+            return (double)ld32(src, (g.q0 + (l * g.J)) * 4);
         };
         auto store_l = [&](auto, auto &v, Geo g) PA_INLINE {
 #pragma unroll
             for (int l = 0; l < group_size(v); ++l) lds[g.lbase + l * g.lstep] = (int)v[l];
         };
         auto load_l = [&](auto, const Geo &g, int l) PA_INLINE -> double { return (double)lds[g.lbase + l * g.lstep]; };
-        round_fk<MODE_FWD, FK, false>(xd, ftw, itw, 0, pre_fwd, load_tw, mid_none, store_l);
+        round_fk<MODE_FWD, FK, false>(xd, ftw, itw, 0, pre_none, load_g, mid_none, store_l);
         __syncthreads();
         for (int r = 1; r < nr - 1; ++r) {
             round_p2<MODE_FWD, false, false, kRowMaxLg, 1, kMix>(xd, ftw, itw, r, 0, pre_none, load_l, mid_none, store_l);
@@ -550,7 +638,7 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
         forward_head(rowS, lds_a);
         auto store_g = [&](NoCtx, auto &v, Geo g) PA_INLINE {
 #pragma unroll
-            for (int l = 0; l < group_size(v); ++l) st32(rowS, (g.q0 + (l * g.J)) * 4, (int)reduce_sym(v[l]));
+            for (int l = 0; l < group_size(v); ++l) st32_wt(rowS, (g.q0 + (l * g.J)) * 4, (int)reduce_sym(v[l]));
         };
         round_p2<MODE_FWD, false, true, kRowMaxLg, 1, kMix>(xd, ftw, itw, nr - 1, 0, pre_none, load_la, mid_none, store_g);
         return;
@@ -562,12 +650,9 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
     // the first row round at <= 12 values so that two groups fit.)
     static_assert(Shape<kKindN3[FK], kKindN2[FK]>::RHO <= kRowDualFirstMax, "row first round too large");
     if (mode == 2) {
-        auto load_tw2 = [&](TwCtx t, const Geo &g, int l) PA_INLINE -> double2 {
+        auto load_g2 = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double2 {
             const int off = (g.q0 + (l * g.J)) * 4;
-            const double xs = (double)ld32(rowS, off), xa = (double)ld32(rowA, off);
-            const double2 al = ld_tw(rs_af, l);
-            const double ys = mulmod(xs, t.beta.x, t.beta.y), ya = mulmod(xa, t.beta.x, t.beta.y);
-            return make_double2(mulmod(ys, al.x, al.y), mulmod(ya, al.x, al.y));
+            return make_double2((double)ld32(rowS, off), (double)ld32(rowA, off));
         };
         auto load_l2 = [&](auto, const Geo &g, int l) PA_INLINE -> double2 {
             const int i = g.lbase + l * g.lstep;
@@ -588,7 +673,7 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
                 v[1][l] = mulmod(v[1][l], sp, sp * kPinv);
             }
         };
-        round_fk<MODE_FWD, FK, false, 2>(xd, ftw, itw, 0, pre_fwd, load_tw2, mid_none, store_l2);
+        round_fk<MODE_FWD, FK, false, 2>(xd, ftw, itw, 0, pre_none, load_g2, mid_none, store_l2);
         __syncthreads();
         for (int r = 1; r < nr - 1; ++r) {
             round_p2<MODE_FWD, false, false, kRowMaxLg, 2, kMix>(xd, ftw, itw, r, 0, pre_none, load_l2, mid_none, store_l2);
@@ -616,9 +701,9 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
     auto store_tw = [&](TwCtx t, auto &v, Geo g) PA_INLINE {
 #pragma unroll
         for (int l = 0; l < group_size(v); ++l) {
-            const double2 al = ld_tw(rs_ai, l);
+            const double2 al = ld_const(ai, l);
             const double y = mulmod(v[l], al.x, al.y);
-            st32(rowA, (g.q0 + (l * g.J)) * 4, (int)mulmod(y, t.beta.x, t.beta.y));
+            st32_wt(rowA, (g.q0 + (l * g.J)) * 4, (int)mulmod(y, t.beta.x, t.beta.y));
         }
     };
     round_fk<MODE_INV, FK, false>(xd, ftw, itw, 0, pre_inv, load_la, mid_none, store_tw);
@@ -650,6 +735,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     auto load_glb = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double {
         return (double)ld32(ain, ((g.q0 + (l * g.J)) * C + c0 + g.c) * 4);
     };
+
     auto load_lds = [&](NoCtx, const Geo &g, int l) PA_INLINE -> double { return (double)lds[g.lbase + l * g.lstep]; };
     auto store_lds = [&](NoCtx, auto &v, Geo g) PA_INLINE {
 #pragma unroll
@@ -711,6 +797,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
 
 static int g_lds_limit[64];
 
+// Largest column-pass output (bytes per launch) written with write-through
+// stores: short launches end sooner without dirty lines to write back; a
+// large batch's column pass streams faster through the write-back L2.
+constexpr double kColWtBytes = 64.0 * 1024 * 1024;
+
 // Opt the kernels into the device's full per-workgroup LDS (160 KiB on
 // gfx950) once per device; returns the limit in *limit.
 static hipError_t set_lds_limits(int *limit) {
@@ -728,7 +819,8 @@ static hipError_t set_lds_limits(int *limit) {
         const int maxb = optin < 160 * 1024 ? optin : 160 * 1024;
         const void *fns[] = {(const void *)k_rowconv<0>, (const void *)k_rowconv<1>, (const void *)k_rowconv<2>,
                              (const void *)k_rowconv<4>, (const void *)k_rowconv<5>, (const void *)k_rowconv<6>,
-                             (const void *)k_rowconv<7>, (const void *)k_colfwd<3>, (const void *)k_colfwd<4>,
+                             (const void *)k_rowconv<7>, (const void *)k_colfwd<3, false>, (const void *)k_colfwd<4, false>,
+                             (const void *)k_colfwd<3, true>, (const void *)k_colfwd<4, true>,
                              (const void *)k_colinv<3>, (const void *)k_colinv<4>};
         for (const void *f : fns) {
             e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
@@ -770,10 +862,16 @@ hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const J
     const size_t lds = (size_t)hp.col_lds * sizeof(int);
     if (lds > (size_t)limit || nsrc < 1 || nsrc > 2 || njobs < 1 || njobs > 65535) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)hp.ntiles, (unsigned)nsrc, (unsigned)njobs), block((unsigned)hp.col_threads);
-    if (col_max_lg(hp) <= 3)
-        hipExtLaunchKernelGGL(k_colfwd<3>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, hp.col.fwd_tw);
-    else
-        hipExtLaunchKernelGGL(k_colfwd<4>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, hp.col.fwd_tw);
+    // write-through stores unless the launch writes more than kColWtBytes
+    const bool wt = (double)nsrc * (double)njobs * 4.0 * (double)hp.L <= (double)kColWtBytes;
+    const bool lg3 = col_max_lg(hp) <= 3;
+#define PA_CF(LG, WTV) hipExtLaunchKernelGGL((k_colfwd<LG, WTV>), grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, hp.col.fwd_tw)
+    if (lg3) {
+        if (wt) PA_CF(3, true); else PA_CF(3, false);
+    } else {
+        if (wt) PA_CF(4, true); else PA_CF(4, false);
+    }
+#undef PA_CF
     return hipGetLastError();
 }
 

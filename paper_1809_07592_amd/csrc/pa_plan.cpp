@@ -442,19 +442,17 @@ PlanRef get_len_plan(uint64_t L, int log2R_override, int W_override) {
     lp.twist_lo = upload(e->tables, lo);
     lp.twist_hi = upload(e->tables, hi);
 
-    // alpha tables for the row pass twist: element q = jj + l*J0 of round 0
-    // is multiplied by omega_L^(k1 jj) * omega_L^(k1 J0 l) (forward) and by
-    // omega_L^(-k1 jj) * omega_L^(-k1 J0 l) / L (inverse).
+    // inverse twist factors of the row pass: element q = jj + u*J0 of round
+    // 0 is multiplied by omega_L^(-k1 jj) (from the twist tables) and by
+    // omega_L^(-k1 J0 u) / L (this table)
     const uint64_t J0 = (uint64_t)lp.C / (uint64_t)lp.rho0;
     const uint64_t Linv = powmod_u(L % (uint64_t)kP, (uint64_t)kP - 2);
-    std::vector<double2> af((size_t)lp.R * lp.rho0), ai((size_t)lp.R * lp.rho0);
+    std::vector<double2> ai((size_t)lp.R * lp.rho0);
     for (uint64_t k1 = 0; k1 < (uint64_t)lp.R; ++k1)
         for (uint64_t u = 0; u < (uint64_t)lp.rho0; ++u) {
             const uint64_t ex = (k1 * J0 * u) % L;
-            af[(size_t)(k1 * lp.rho0 + u)] = tw_pair(powmod_u(wL, ex));
             ai[(size_t)(k1 * lp.rho0 + u)] = tw_pair(mulmod_u(powmod_u(wL, (L - ex) % L), Linv));
         }
-    lp.alpha_f = upload(e->tables, af);
     lp.alpha_i = upload(e->tables, ai);
 
     void *d = nullptr;

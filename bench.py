@@ -159,13 +159,34 @@ def batched_uneven_run(pa, wl, torch, np, count, stream):
     def step():
         pa.toeplitz_hash_batched(blocks, stream=stream)
 
-    bms, _ = time_steps(step, 5, 2, torch)
     bits = sum(sh.n for sh in shapes)
     lens = sorted({pa.transform_len(sh.n, sh.m) for sh in shapes})
-    with pa.BatchGraph(blocks) as g:          # the same call captured once, replayed
-        gms, _ = time_steps(lambda: g.launch(stream=stream), 5, 2, torch)
+    # both launch forms, as direct calls and as captured graphs (the
+    # library's defaults: flat for calls, lanes for graphs)
+    forms = {}
+    old = os.environ.get("PA_BATCH_FORM")
+    try:
+        for form in ("flat", "lanes"):
+            os.environ["PA_BATCH_FORM"] = form
+            fms, _ = time_steps(step, 5, 2, torch)
+            pa.profile_collect()
+            pa.profile_enable(True)
+            step()
+            torch.cuda.synchronize()
+            launches = sum(st["launches"] for st in pa.profile_collect().values())
+            pa.profile_enable(False)
+            with pa.BatchGraph(blocks) as g:
+                gms_f, _ = time_steps(lambda: g.launch(stream=stream), 5, 2, torch)
+            forms[form] = {"Gbs": bits / (fms * 1e-3) / 1e9, "ms_per_batch": fms, "launches": launches,
+                           "graph_Gbs": bits / (gms_f * 1e-3) / 1e9, "graph_ms_per_batch": gms_f}
+    finally:
+        if old is None:
+            os.environ.pop("PA_BATCH_FORM", None)
+        else:
+            os.environ["PA_BATCH_FORM"] = old
+    bms, gms = forms["flat"]["ms_per_batch"], forms["lanes"]["graph_ms_per_batch"]
     return {"value": bits / (bms * 1e-3) / 1e9, "unit": "Gb/s", "blocks": count, "ms_per_batch": bms,
-            "graph_Gbs": bits / (gms * 1e-3) / 1e9, "graph_ms_per_batch": gms,
+            "graph_Gbs": bits / (gms * 1e-3) / 1e9, "graph_ms_per_batch": gms, "forms": forms,
             "sum_n": bits, "distinct_lengths": len(lens), "min_len": lens[0], "max_len": lens[-1],
             "shapes": "n = round(2^U(18,22)), m = max(1, round(n U(0.05, 0.5))), own seed per block"}
 
@@ -340,6 +361,19 @@ def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30, streams=4
         run_sat_el, _ = run(srv, ids, None)    # saturated (all submitted at once): capacity
         cap_gbs = bits / run_sat_el / 1e9
         unit_arrivals = np.array([r.arrival_s for r in reqs])   # unit-rate Poisson times, rescaled per load
+        # cold start: a fresh server at the headline load, every (seed,
+        # length) spectrum built on first use while requests are served
+        rate0 = load * cap_gbs * 1e9 / (bits / len(reqs))
+        with pa.Server(budget_bytes, max_inflight=max_inflight, streams=streams) as cold_srv:
+            cold_ids = [cold_srv.register_seed(sd, seed_bits) for sd in seeds]
+            cel, clat = run(cold_srv, cold_ids, unit_arrivals / rate0)
+            cst = cold_srv.stats()
+        cla = np.array(clat) / 1e3
+        cold = {"offered_load": load, "Gbs": bits / cel / 1e9, "p50_ms": float(np.percentile(cla, 50)),
+                "p99_ms": float(np.percentile(cla, 99)), "max_ms": float(cla.max()),
+                "spectra_built": cst["spectra_built"], "spectra_evicted": cst["spectra_evicted"]}
+        progress("serving cold start at load %.1f: p50 %.3f ms p99 %.3f ms (%d spectra built on demand)"
+                 % (load, cold["p50_ms"], cold["p99_ms"], cold["spectra_built"]))
         sweep = []
         for rho in [x for x in (0.3, 0.5, 0.9) if x != load] + [load]:   # headline load last
             rate = rho * cap_gbs * 1e9 / (bits / len(reqs))
@@ -375,7 +409,9 @@ def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30, streams=4
             "budget_GiB": budget_bytes / 2**30, "streams": streams, "max_inflight": max_inflight,
             "peak_inflight": st["peak_inflight"], "batches": st["batches"],
             "peak_bytes_in_flight": st["peak_bytes_in_flight"], "mismatches_vs_alone": mism,
-            "load_sweep": sweep, "latency": "completion minus scheduled Poisson arrival (open loop)"}
+            "load_sweep": sweep, "cold_start": cold, "spectrum_bytes": st["spectrum_bytes"],
+            "spectra_resident": st["spectra_resident"],
+            "latency": "completion minus scheduled Poisson arrival (open loop)"}
 
 
 def main():

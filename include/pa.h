@@ -46,7 +46,8 @@ typedef enum pa_status {
     PA_ERR_UNSUPPORTED_SIZE = 2, /* transform length needed exceeds PA_MAX_TRANSFORM_LEN */
     PA_ERR_OUT_OF_MEMORY = 3,    /* device allocation failed */
     PA_ERR_DEVICE = 4,           /* HIP runtime error (see pa_last_error) */
-    PA_ERR_BUSY = 5              /* serving queue full / budget cannot admit */
+    PA_ERR_BUSY = 5,             /* serving queue full / budget cannot admit */
+    PA_ERR_CANCELLED = 6         /* serving: the request was cancelled before it ran */
 } pa_status;
 
 /* Largest cyclic-convolution length the arithmetic supports: the prime
@@ -257,40 +258,68 @@ pa_status pa_plan_describe(uint64_t transform_len, uint32_t log2_rows, uint32_t 
 size_t pa_workspace_bytes(uint64_t n, uint64_t m);
 
 /*
- * Geometry tuning.  The library keeps a per-process table of the (R, W)
- * split used for each transform length L in two batch classes: class 0 is
- * one block per launch (pa_toeplitz_hash, plans), class 1 is several blocks
- * of one length per launch (pa_toeplitz_hash_batched groups of >= 2 blocks,
- * the serving loop).  Any valid split gives the same bits; the choice only
- * changes speed.  Plans and the server's resident seed spectra keep the
- * geometry they were built with.
+ * Geometry tuning.  The library keeps a per-process table of the geometry
+ * used for each transform length L in two batch classes: class 0 is one
+ * block per launch (pa_toeplitz_hash, plans), class 1 is several blocks of
+ * one length per launch (batched calls, the serving loop).  A geometry is
+ * the four-step split (log2_rows: R = 2^log2_rows rows; tile_width: W
+ * columns per column-pass tile), the register-round split of the row
+ * transform (row_first: radix-2 stages in its first round plus one; the
+ * later rounds share the rest evenly) and a fixed row-pass workgroup size
+ * (row_threads: 256, 512, 768 or 1024; otherwise launches choose one by
+ * occupancy).  Zero fields take the built-in defaults.  Any valid geometry
+ * gives the same bits; the choice only changes speed.  Plans and the
+ * server's resident seed spectra keep the geometry they were built with.
  *
- * pa_tune_set: use log2_rows / tile_width for (transform_len, batch_class)
- *   from now on; (0, 0) restores the built-in default.  PA_ERR_INVALID_ARG
- *   for an impossible split or class, PA_ERR_UNSUPPORTED_SIZE for a length
- *   that is not supported.  Host only.
- * pa_tune_get: the geometry now in effect (the default if none is set).
- * pa_autotune: times every valid split of transform_len on `count`
- *   synthetic blocks (n = 4m, the largest that fit L) submitted as one
- *   launch sequence on `stream`, `reps` timed repetitions each after one
- *   warm-up (median of HIP-event time), installs the fastest for the class
- *   of `count` (1: class 0, else class 1) -- the default unless another
- *   split is at least 2% faster -- and fills *result.  Allocates and
- *   frees its own device buffers (count * (8 L + bits) bytes; at most
- *   16 GiB, else PA_ERR_INVALID_ARG) and synchronizes `stream`.
+ * pa_tune_set_geometry: use *g for (transform_len, batch_class) from now
+ *   on; all zero restores the default.  PA_ERR_INVALID_ARG for an
+ *   impossible geometry or class, PA_ERR_UNSUPPORTED_SIZE for a length that
+ *   is not supported.  Host only.  pa_tune_set: the same with only
+ *   log2_rows and tile_width given.
+ * pa_tune_get_geometry / pa_tune_get: the geometry now in effect (the
+ *   default if none is set; row_first and row_threads 0 when default).
+ * pa_autotune: times, on `count` synthetic blocks (n = 4m, the largest
+ *   that fit L) submitted as one launch sequence on `stream`, `reps` timed
+ *   repetitions each after one warm-up (median of HIP-event time): every
+ *   valid (log2_rows, tile_width), then every first-round split of the row
+ *   transform at the fastest of those, then every fixed row workgroup size
+ *   at the fastest so far.  It installs the fastest geometry for the class
+ *   of `count` (1: class 0, else class 1) -- the default unless another is
+ *   at least 2% faster -- and fills *result.  Allocates and frees its own
+ *   device buffers (count * (8 L + bits) bytes; at most 16 GiB, else
+ *   PA_ERR_INVALID_ARG) and synchronizes `stream`.  With PA_TUNE_CACHE set
+ *   to a file name, it then writes the table to that file (keeping other
+ *   architectures' lines).
  * pa_tune_save / pa_tune_load: the table as text, one "L class log2_rows
- *   tile_width" line per entry; load validates every line before
- *   installing any (PA_ERR_INVALID_ARG with the line number otherwise).
+ *   tile_width row_first row_threads arch" line per entry (arch: the
+ *   device architecture, e.g. gfx950).  Load accepts lines of 4 or 6
+ *   integers (any architecture) or 6 integers and an architecture name
+ *   (installed only on a device of that architecture); it validates every
+ *   line before installing any (PA_ERR_INVALID_ARG with the line number
+ *   otherwise).
+ * PA_TUNE_CACHE: read once per process, on the first hash call, with the
+ *   rules of pa_tune_load (a missing or invalid file is ignored).
  */
-typedef struct pa_tune_result {
-    uint32_t log2_rows;     /* chosen split (installed) */
+typedef struct pa_tune_geometry {
+    uint32_t log2_rows;
     uint32_t tile_width;
-    uint32_t candidates;    /* splits timed */
+    uint32_t row_first;
+    uint32_t row_threads;
+} pa_tune_geometry;
+
+typedef struct pa_tune_result {
+    uint32_t log2_rows;     /* chosen geometry (installed) */
+    uint32_t tile_width;
+    uint32_t candidates;    /* geometries timed */
     uint32_t count;         /* blocks per timed launch sequence */
-    double best_us;         /* median time of one launch sequence, chosen split */
-    double default_us;      /* the same for the built-in default split */
+    double best_us;         /* median time of one launch sequence, chosen geometry */
+    double default_us;      /* the same for the built-in default */
+    uint32_t row_first;     /* chosen row split (0: default) */
+    uint32_t row_threads;   /* chosen fixed row workgroup size (0: by occupancy) */
 } pa_tune_result;
 
+pa_status pa_tune_set_geometry(uint64_t transform_len, uint32_t batch_class, const pa_tune_geometry *g);
+pa_status pa_tune_get_geometry(uint64_t transform_len, uint32_t batch_class, pa_tune_geometry *g);
 pa_status pa_tune_set(uint64_t transform_len, uint32_t batch_class, uint32_t log2_rows, uint32_t tile_width);
 pa_status pa_tune_get(uint64_t transform_len, uint32_t batch_class, uint32_t *log2_rows, uint32_t *tile_width);
 pa_status pa_autotune(uint64_t transform_len, uint32_t count, uint32_t reps, void *stream, pa_tune_result *result);
@@ -335,56 +364,78 @@ pa_status pa_profile_collect(pa_kernel_stat *stats, uint32_t capacity, uint32_t 
  * pool (its HBM budget) can hold their workspace (4 bytes per transform
  * point) and fewer than max_inflight are running; every scheduler
  * iteration launches all newly admitted requests as one batched pass
- * sequence on the next of `streams` HIP streams, so requests that arrive
- * while others run are admitted as memory frees up and their work overlaps
- * on the device.  Seeds are registered once; the spectrum of each (seed,
- * transform length) pair is built on first use and stays resident.  Each
- * result is bit-identical to pa_toeplitz_hash on the same block.
+ * sequence on the least-loaded of `streams` HIP streams, so requests that
+ * arrive while others run are admitted as memory frees up and their work
+ * overlaps on the device.  Seeds are registered once (also while requests
+ * run); the spectrum of each (seed, transform length) pair is built on
+ * first use, on a stream of its own that the scheduler does not wait for
+ * (the requests that need it wait on the device), and stays resident in
+ * the same pool (4 bytes per transform point) until the pool needs its
+ * memory for a request and no admitted request uses it (least recently
+ * used first).  Each result is bit-identical to pa_toeplitz_hash on the
+ * same block.
  *
  * Pointers passed to submit are device pointers owned by the caller and
  * must stay valid until the request completes.  executor =
  * PA_EXEC_SIMULATED runs the scheduler without touching the device
  * (requests complete after n / sim_bits_per_us microseconds, outputs are
- * not written): for testing admission and bookkeeping on a host without a
- * GPU.  Submission returns PA_ERR_BUSY if the request can never fit the
- * budget or the queue holds max_queue requests.
+ * not written, spectra take pool memory but are not built): for testing
+ * admission and bookkeeping on a host without a GPU.  Submission returns
+ * PA_ERR_BUSY if the request's workspace and spectrum (8 bytes per
+ * transform point) exceed the whole budget or the queue holds max_queue
+ * requests.
+ *
+ * Failures: a request whose launch fails completes with that status (its
+ * output unspecified); pa_server_wait returns it, and pa_server_drain
+ * returns the first failure since the previous drain.  Later requests are
+ * served as usual.
  */
 typedef struct pa_server_s *pa_server_t;
 
 enum { PA_EXEC_GPU = 0, PA_EXEC_SIMULATED = 1 };
 
 typedef struct pa_server_config {
-    uint64_t hbm_budget_bytes;  /* device workspace pool */
+    uint64_t hbm_budget_bytes;  /* device pool; 0: PA_HBM_BUDGET (bytes, K/M/G suffix allowed), else 16 GiB */
     uint32_t max_inflight;      /* requests running at once */
     uint32_t max_queue;         /* pending requests accepted */
-    uint32_t streams;           /* HIP streams batches rotate over */
+    uint32_t streams;           /* HIP streams batches go to */
     uint32_t executor;          /* PA_EXEC_GPU or PA_EXEC_SIMULATED */
     double sim_bits_per_us;     /* simulated executor speed */
 } pa_server_config;
 
 typedef struct pa_server_stats {
     uint64_t submitted, completed, rejected, batches;
-    uint64_t bytes_in_flight, peak_bytes_in_flight, budget_bytes;
+    uint64_t bytes_in_flight, peak_bytes_in_flight, budget_bytes;  /* pool bytes in use: workspace and spectra */
     uint64_t inflight, peak_inflight, pending;
-    uint64_t input_bits_completed;
+    uint64_t input_bits_completed;  /* of requests completed without failure */
+    uint64_t spectrum_bytes;        /* resident seed spectra (part of bytes_in_flight) */
+    uint64_t spectra_resident, spectra_built, spectra_evicted;
+    uint64_t cancelled, failed;
 } pa_server_stats;
 
 pa_status pa_server_create(const pa_server_config *cfg, pa_server_t *server);
 /* Registers seed bits (device pointer, kept by the caller until the server
- * is destroyed); returns its id. */
+ * is destroyed); returns its id.  May be called while requests run. */
 pa_status pa_server_register_seed(pa_server_t server, const uint64_t *seed_bits, uint64_t seed_len_bits,
                                   uint32_t *seed_id);
 /* Queues y = T x mod 2 with the Toeplitz matrix of seed `seed_id` (its
  * first n+m-1 bits).  *ticket identifies the request. */
 pa_status pa_server_submit(pa_server_t server, uint32_t seed_id, const uint64_t *key_bits, uint64_t n, uint64_t m,
                            uint64_t *out_bits, uint64_t *ticket);
-/* *done = 1 once the request's output is written (and visible to the
- * host-side caller's later stream work). */
+/* Removes a request that is still queued (not yet admitted to the device):
+ * it completes at once with status PA_ERR_CANCELLED and its output is not
+ * written.  PA_ERR_BUSY if it is already admitted (it will complete
+ * normally), PA_ERR_INVALID_ARG if it is unknown or complete. */
+pa_status pa_server_cancel(pa_server_t server, uint64_t ticket);
+/* *done = 1 once the request has completed (output written, failed or
+ * cancelled; for a written output, visible to the caller's later stream
+ * work). */
 pa_status pa_server_poll(pa_server_t server, uint64_t ticket, int *done);
-/* Blocks until the request completes; *latency_us (optional) receives
- * completion time minus submit time. */
+/* Blocks until the request completes and returns its status;
+ * *latency_us (optional) receives completion time minus submit time. */
 pa_status pa_server_wait(pa_server_t server, uint64_t ticket, double *latency_us);
-/* Blocks until every submitted request has completed. */
+/* Blocks until every submitted request has completed; returns the first
+ * failure since the previous drain (PA_OK if none). */
 pa_status pa_server_drain(pa_server_t server);
 pa_status pa_server_stats_get(pa_server_t server, pa_server_stats *stats);
 /* Completion-minus-submit latency of a completed request, microseconds. */

@@ -24,6 +24,7 @@ PA_ERR_UNSUPPORTED_SIZE = 2
 PA_ERR_OUT_OF_MEMORY = 3
 PA_ERR_DEVICE = 4
 PA_ERR_BUSY = 5
+PA_ERR_CANCELLED = 6
 MAX_TRANSFORM_LEN = 28311552
 
 _lib = None
@@ -64,12 +65,19 @@ class ServerConfig(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in (
         "submitted", "completed", "rejected", "batches", "bytes_in_flight", "peak_bytes_in_flight",
-        "budget_bytes", "inflight", "peak_inflight", "pending", "input_bits_completed")]
+        "budget_bytes", "inflight", "peak_inflight", "pending", "input_bits_completed", "spectrum_bytes",
+        "spectra_resident", "spectra_built", "spectra_evicted", "cancelled", "failed")]
 
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("log2_rows", ctypes.c_uint32), ("tile_width", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
-                ("count", ctypes.c_uint32), ("best_us", ctypes.c_double), ("default_us", ctypes.c_double)]
+                ("count", ctypes.c_uint32), ("best_us", ctypes.c_double), ("default_us", ctypes.c_double),
+                ("row_first", ctypes.c_uint32), ("row_threads", ctypes.c_uint32)]
+
+
+class TuneGeometry(ctypes.Structure):
+    _fields_ = [("log2_rows", ctypes.c_uint32), ("tile_width", ctypes.c_uint32), ("row_first", ctypes.c_uint32),
+                ("row_threads", ctypes.c_uint32)]
 
 
 class _Block(ctypes.Structure):
@@ -130,6 +138,10 @@ def lib():
                 L.pa_alu_probe.restype = st
                 L.pa_final_key_length.argtypes = [u64, u64, u64]
                 L.pa_final_key_length.restype = u64
+                L.pa_tune_set_geometry.argtypes = [u64, u32, ctypes.POINTER(TuneGeometry)]
+                L.pa_tune_set_geometry.restype = st
+                L.pa_tune_get_geometry.argtypes = [u64, u32, ctypes.POINTER(TuneGeometry)]
+                L.pa_tune_get_geometry.restype = st
                 L.pa_tune_set.argtypes = [u64, u32, u32, u32]
                 L.pa_tune_set.restype = st
                 L.pa_tune_get.argtypes = [u64, u32, ctypes.POINTER(u32), ctypes.POINTER(u32)]
@@ -153,6 +165,8 @@ def lib():
                 L.pa_server_submit.restype = st
                 L.pa_server_poll.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_int)]
                 L.pa_server_poll.restype = st
+                L.pa_server_cancel.argtypes = [vp, u64]
+                L.pa_server_cancel.restype = st
                 L.pa_server_wait.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_double)]
                 L.pa_server_wait.restype = st
                 L.pa_server_drain.argtypes = [vp]
@@ -207,10 +221,14 @@ def plan_info(transform_len: int, log2_rows: int = 0, tile_width: int = 0) -> di
     return info.as_dict()
 
 
-def tune_set(transform_len: int, batch_class: int, log2_rows: int, tile_width: int):
-    """Use this (R, W) split for the length in batch class 0 (one block per
-    launch) or 1 (several); (0, 0) restores the default."""
-    _check(lib().pa_tune_set(int(transform_len), int(batch_class), int(log2_rows), int(tile_width)))
+def tune_set(transform_len: int, batch_class: int, log2_rows: int, tile_width: int, row_first: int = 0,
+             row_threads: int = 0):
+    """Use this geometry for the length in batch class 0 (one block per
+    launch) or 1 (several): the (R, W) split, the row transform's first
+    round split and a fixed row workgroup size; all zero restores the
+    default."""
+    g = TuneGeometry(int(log2_rows), int(tile_width), int(row_first), int(row_threads))
+    _check(lib().pa_tune_set_geometry(int(transform_len), int(batch_class), ctypes.byref(g)))
 
 
 def tune_get(transform_len: int, batch_class: int) -> tuple:
@@ -220,13 +238,22 @@ def tune_get(transform_len: int, batch_class: int) -> tuple:
     return int(a.value), int(w.value)
 
 
+def tune_get_geometry(transform_len: int, batch_class: int) -> dict:
+    """The full geometry in effect for the length and class."""
+    g = TuneGeometry()
+    _check(lib().pa_tune_get_geometry(int(transform_len), int(batch_class), ctypes.byref(g)))
+    return {f: int(getattr(g, f)) for f, _ in g._fields_}
+
+
 def autotune(transform_len: int, count: int = 1, reps: int = 5, stream=None) -> dict:
-    """Time every valid split of the length on `count` synthetic blocks and
-    install the fastest for that batch class."""
+    """Time the valid geometries of the length on `count` synthetic blocks
+    (every (R, W) split, then the row round splits and row workgroup sizes
+    at the best) and install the fastest for that batch class."""
     r = TuneResult()
     _check(lib().pa_autotune(int(transform_len), int(count), int(reps), _stream_handle(stream), ctypes.byref(r)))
-    return {"log2_rows": int(r.log2_rows), "tile_width": int(r.tile_width), "candidates": int(r.candidates),
-            "count": int(r.count), "best_us": r.best_us, "default_us": r.default_us}
+    return {"log2_rows": int(r.log2_rows), "tile_width": int(r.tile_width), "row_first": int(r.row_first),
+            "row_threads": int(r.row_threads), "candidates": int(r.candidates), "count": int(r.count),
+            "best_us": r.best_us, "default_us": r.default_us}
 
 
 def tune_save(path: str):
@@ -518,6 +545,11 @@ class Server:
         _check(lib().pa_server_submit(self._h, int(seed_id), self._addr(key, words(n), "key"), int(n), int(m),
                                       self._addr(out, words(m), "out"), ctypes.byref(t)))
         return t.value
+
+    def cancel(self, ticket: int):
+        """Cancels a request that is still queued (raises PAError with
+        PA_ERR_BUSY if it has already been admitted)."""
+        _check(lib().pa_server_cancel(self._h, int(ticket)))
 
     def poll(self, ticket: int) -> bool:
         d = ctypes.c_int()

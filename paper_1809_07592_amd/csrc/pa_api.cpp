@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -397,6 +398,7 @@ pa_status plan_for(uint64_t L, int cls, pa::PlanRef *lp) {
     thread_local unsigned memo_next = 0;
     int dev = 0;
     PA_HIP(hipGetDevice(&dev), "hipGetDevice");
+    load_tune_cache_once();
     const uint64_t ver = pa::tune_version();
     for (const Memo &mm : memo)
         if (mm.L == L && mm.cls == cls && mm.dev == dev && mm.version == ver) {
@@ -404,9 +406,7 @@ pa_status plan_for(uint64_t L, int cls, pa::PlanRef *lp) {
             return PA_OK;
         }
     try {
-        int a = 0, w = 0;
-        pa::tuned_geometry(L, cls, &a, &w);
-        *lp = pa::get_len_plan(L, a, w);
+        *lp = pa::get_len_plan(L, pa::tuned_geometry(L, cls));
         Memo &mm = memo[memo_next++ % 4];
         mm.L = L;
         mm.cls = cls;
@@ -422,9 +422,7 @@ pa_status plan_for(uint64_t L, int cls, pa::PlanRef *lp) {
 }
 
 pa_status plan_cached(uint64_t L, int cls, pa::PlanRef *lp) {
-    int a = 0, w = 0;
-    pa::tuned_geometry(L, cls, &a, &w);
-    if (!pa::find_len_plan(L, a, w, lp))
+    if (!pa::find_len_plan(L, pa::tuned_geometry(L, cls), lp))
         return fail(PA_ERR_INVALID_ARG, "the transform tables of length " + std::to_string(L) +
                                             " are not resident on this device yet: hash one block of this "
                                             "transform length with pa_toeplitz_hash first");
@@ -490,6 +488,7 @@ const char *pa_status_string(pa_status s) {
         case PA_ERR_OUT_OF_MEMORY: return "PA_ERR_OUT_OF_MEMORY";
         case PA_ERR_DEVICE: return "PA_ERR_DEVICE";
         case PA_ERR_BUSY: return "PA_ERR_BUSY";
+        case PA_ERR_CANCELLED: return "PA_ERR_CANCELLED";
     }
     return "PA_ERR_UNKNOWN";
 }
@@ -622,21 +621,69 @@ uint64_t pa_final_key_length(uint64_t n, uint64_t t, uint64_t s) {
 namespace pa {
 namespace rt {
 
-// Validation, length groups and plans of a block array (host only).
-pa_status prepare_batch(const pa_block *blocks, uint32_t count, bool modified, BatchPrep *bp) {
+BatchForm batch_form(BatchForm dflt) {
+    const char *v = std::getenv("PA_BATCH_FORM");
+    if (v && std::strcmp(v, "lanes") == 0) return kFormLanes;
+    if (v && std::strcmp(v, "flat") == 0) return kFormFlat;
+    return dflt;
+}
+
+namespace {
+
+constexpr uint64_t kMaxFlatWgs = 1u << 21;
+
+// Launch classes of one pass (flat form).  Groups are keyed by what a
+// launch must share (kernel variant, workgroup size); inside a key, groups
+// sorted by LDS join a class while the class's largest LDS keeps every
+// member's workgroups per CU.
+struct PassGroup {
+    size_t g;       // group index
+    int variant, threads, mode;
+    size_t lds;
+};
+
+template <class Wgs>
+std::vector<std::vector<PassGroup>> form_classes(std::vector<PassGroup> v, Wgs wgs) {
+    std::sort(v.begin(), v.end(), [](const PassGroup &a, const PassGroup &b) {
+        if (a.variant != b.variant) return a.variant < b.variant;
+        if (a.mode != b.mode) return a.mode < b.mode;
+        if (a.threads != b.threads) return a.threads < b.threads;
+        return a.lds < b.lds;
+    });
+    std::vector<std::vector<PassGroup>> out;
+    for (const PassGroup &pg : v) {
+        if (!out.empty()) {
+            const PassGroup &f = out.back().front();
+            if (f.variant == pg.variant && f.mode == pg.mode && f.threads == pg.threads &&
+                wgs(f.variant, f.threads, pg.lds) == wgs(f.variant, f.threads, f.lds)) {
+                out.back().push_back(pg);
+                continue;
+            }
+        }
+        out.push_back({pg});
+    }
+    return out;
+}
+
+}  // namespace
+
+// Validation, length groups and plans of a block array (host only), and
+// the flat form's launch classes.
+pa_status prepare_batch(const pa_block *blocks, uint32_t count, bool modified, BatchPrep *bp, BatchForm form) {
     if (!blocks) return fail(PA_ERR_INVALID_ARG, "null block array");
     bp->modified = modified;
+    bp->form = form;
     bp->blocks.assign(blocks, blocks + count);
-    std::vector<uint64_t> lens(count);
+    bp->block_len.assign(count, 0);
     for (uint32_t i = 0; i < count; ++i) {
         const pa_block &b = blocks[i];
-        pa_status st = modified ? check_modified(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, &lens[i])
-                                : check_block(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, &lens[i]);
+        pa_status st = modified ? check_modified(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, &bp->block_len[i])
+                                : check_block(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, &bp->block_len[i]);
         if (st != PA_OK) return fail(st, "block " + std::to_string(i) + ": " + g_last_error);
     }
-    // one pass sequence per length class
+    // one plan per length class
     std::map<uint64_t, std::vector<uint32_t>> groups;
-    for (uint32_t i = 0; i < count; ++i) groups[lens[i]].push_back(i);
+    for (uint32_t i = 0; i < count; ++i) groups[bp->block_len[i]].push_back(i);
     bp->groups.clear();
     for (auto &g : groups) {
         BatchPrep::Group gr;
@@ -645,39 +692,199 @@ pa_status prepare_batch(const pa_block *blocks, uint32_t count, bool modified, B
         PA_TRY(plan_for(g.first, g.second.size() > 1 ? 1 : 0, &gr.plan));
         bp->groups.push_back(std::move(gr));
     }
-    // workspace: the job table, then 8L bytes (A and S) per block
-    bp->table_bytes = ((size_t)count * sizeof(pa::JobDesc) + 255) / 256 * 256;
+    bp->launches.clear();
+    size_t region = 0;
+    if (form == kFormLanes) {
+        region = (size_t)count * sizeof(pa::JobDesc);
+    } else {
+        // the plans first, then per launch its job table and segment array
+        bp->plans_off = 0;
+        region = (bp->groups.size() * sizeof(pa::LenPlan) + 255) / 256 * 256;
+        std::vector<PassGroup> p1, p2, p3;
+        for (size_t gi = 0; gi < bp->groups.size(); ++gi) {
+            const pa::LenPlan &h = *bp->groups[gi].plan.host;
+            const size_t col_lds = (size_t)h.col_lds * 4;
+            const int lg = pa::col_max_lg(h) <= 3 ? 3 : 4;
+            p1.push_back({gi, lg, h.col_threads, 0, col_lds});
+            p3.push_back({gi, lg, h.col_threads, 0, col_lds});
+            // a fixed (tuned) row workgroup size is a class of its own
+            const int rt = h.row_threads_fixed ? -h.row_threads : h.row_threads;
+            if (h.fused_ok) {
+                p2.push_back({gi, h.row.round[0].kind, rt, 2, (size_t)h.row_lds * 8});
+            } else {
+                p2.push_back({gi, h.row.round[0].kind, rt, 1, (size_t)h.row_lds * 4});
+            }
+        }
+        auto colw = [](bool inv) {
+            return [inv](int v, int t, size_t lds) { return pa::col_wgs_per_cu(inv, v, t, lds); };
+        };
+        auto roww = [](int v, int t, size_t lds) { return pa::rowconv_wgs_per_cu(v, t < 0 ? -t : t, lds); };
+        auto add = [&](int pass, const std::vector<std::vector<PassGroup>> &classes) {
+            for (const auto &cl : classes) {
+                // an unfused row class runs the seed pass (mode 1) then the key pass (mode 0)
+                const std::vector<int> modes = pass == 2 && cl.front().mode == 1 ? std::vector<int>{1, 0}
+                                                                                  : std::vector<int>{cl.front().mode};
+                for (int mode : modes) {
+                    size_t lds = 0;
+                    for (const PassGroup &pg : cl) lds = std::max(lds, pg.lds);
+                    BatchPrep::PassLaunch pl;
+                    uint64_t wg = 0;
+                    // a launch holds at most kMaxFlatWgs workgroups (grid x
+                    // times 1024 threads stays below 2^32); larger classes
+                    // are cut into several launches
+                    auto flush = [&]() {
+                        if (pl.blocks.empty()) return;
+                        pl.pass = pass;
+                        pl.mode = mode;
+                        pl.fl.variant = cl.front().variant;
+                        pl.fl.threads = cl.front().threads;
+                        pl.fl.lds = lds;
+                        pl.fl.nwg = (uint32_t)wg;
+                        region = (region + 255) / 256 * 256;
+                        pl.tab_off = region;
+                        region += pl.blocks.size() * sizeof(pa::JobDesc);
+                        region = (region + 255) / 256 * 256;
+                        pl.seg_off = region;
+                        region += (pl.blocks.size() + 1) * sizeof(uint32_t);
+                        bp->launches.push_back(std::move(pl));
+                        pl = BatchPrep::PassLaunch{};
+                        wg = 0;
+                    };
+                    for (const PassGroup &pg : cl) {
+                        const BatchPrep::Group &g = bp->groups[pg.g];
+                        const pa::LenPlan &h = *g.plan.host;
+                        const uint64_t per = pass == 1 ? 2u * (uint64_t)h.ntiles : pass == 2 ? (uint64_t)h.R : (uint64_t)h.ntiles;
+                        for (uint32_t b : g.members) {
+                            if (wg + per > kMaxFlatWgs) flush();
+                            pl.blocks.push_back(b);
+                            pl.plan_idx.push_back((uint32_t)pg.g);
+                            wg += per;
+                        }
+                    }
+                    flush();
+                }
+            }
+            return PA_OK;
+        };
+        PA_TRY(add(1, form_classes(p1, colw(false))));
+        PA_TRY(add(2, form_classes(p2, roww)));
+        PA_TRY(add(3, form_classes(p3, colw(true))));
+    }
+    // workspace: the table region, then 8L bytes (A and S) per block
+    bp->table_bytes = (region + 255) / 256 * 256;
     bp->total_bytes = bp->table_bytes;
-    for (uint32_t i = 0; i < count; ++i) bp->total_bytes += (size_t)(8 * lens[i]);
+    for (uint32_t i = 0; i < count; ++i) bp->total_bytes += (size_t)(8 * bp->block_len[i]);
     return PA_OK;
 }
 
-// Job descriptors for workspace `ws` (table order: groups in length order).
+// Job descriptors for workspace `ws` (which must hold bp.total_bytes).
 void build_table(BatchPrep &bp, void *ws) {
+    // A and S of every block, in group order
+    std::vector<pa::JobDesc> desc(bp.blocks.size());
     int32_t *next = (int32_t *)((char *)ws + bp.table_bytes);
     bp.table.clear();
-    bp.table.reserve(bp.blocks.size());
     size_t first = 0;
     for (auto &g : bp.groups) {
         g.first = first;
         for (uint32_t i : g.members) {
             const pa_block &b = bp.blocks[i];
-            bp.table.push_back(bp.modified
-                                   ? modified_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, next, next + g.L)
-                                   : plain_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, next, next + g.L));
+            desc[i] = bp.modified ? modified_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, next, next + g.L)
+                                  : plain_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, next, next + g.L);
             next += 2 * g.L;
+            bp.table.push_back(desc[i]);
         }
         first += g.members.size();
     }
+    bp.blob.assign(bp.table_bytes, 0);
+    if (bp.form == kFormLanes) {
+        memcpy(bp.blob.data(), bp.table.data(), bp.table.size() * sizeof(pa::JobDesc));
+        return;
+    }
+    for (size_t gi = 0; gi < bp.groups.size(); ++gi)
+        memcpy(bp.blob.data() + bp.plans_off + gi * sizeof(pa::LenPlan), bp.groups[gi].plan.host, sizeof(pa::LenPlan));
+    for (auto &pl : bp.launches) {
+        pa::JobDesc *tab = (pa::JobDesc *)(bp.blob.data() + pl.tab_off);
+        uint32_t *seg = (uint32_t *)(bp.blob.data() + pl.seg_off);
+        uint32_t wg = 0;
+        pl.bytes = pl.ops = 0;
+        for (size_t k = 0; k < pl.blocks.size(); ++k) {
+            tab[k] = desc[pl.blocks[k]];
+            tab[k].plan_idx = pl.plan_idx[k];
+            seg[k] = wg;
+            const pa::LenPlan &h = *bp.groups[pl.plan_idx[k]].plan.host;
+            wg += pl.pass == 1 ? 2u * (uint32_t)h.ntiles : pl.pass == 2 ? (uint32_t)h.R : (uint32_t)h.ntiles;
+        }
+        seg[pl.blocks.size()] = wg;
+    }
 }
 
-// Launches every group's passes against the device job table `dtable`,
-// spread over up to 1 + kSideStreams lanes forked from s (largest work
-// first, each to the least-loaded lane, so one group's tail overlaps the
-// next group's passes) and joined back into s.
-pa_status launch_batch(const BatchPrep &bp, const pa::JobDesc *dtable, hipStream_t s) {
+namespace {
+
+// Algorithmic bytes / operations of one flat launch (the sums of what the
+// per-length launches would record).
+void flat_costs(const BatchPrep &bp, const BatchPrep::PassLaunch &pl, double *bytes, double *ops, double *written) {
+    *bytes = *ops = *written = 0;
+    for (size_t k = 0; k < pl.blocks.size(); ++k) {
+        const pa::LenPlan &h = *bp.groups[pl.plan_idx[k]].plan.host;
+        const pa_block &b = bp.blocks[pl.blocks[k]];
+        const double L = (double)h.L;
+        const uint64_t n = bp.modified ? b.n - b.m : b.n, sb = bp.modified ? b.n - 1 : b.n + b.m - 1;
+        if (pl.pass == 1) {
+            *bytes += words8(n) + words8(sb) + 8.0 * L;
+            *ops += 2.0 * (xform_ops(h.col) * h.C + kColTwistOps * L);
+            *written += 8.0 * L;
+        } else if (pl.pass == 2) {
+            const double xf = xform_ops(h.row) * h.R;
+            if (pl.mode == 1) {
+                *bytes += 8.0 * L;
+                *ops += xf + 3.0 * L;
+            } else {
+                *bytes += 12.0 * L;
+                *ops += 2.0 * xf + 10.0 * L + (pl.mode == 2 ? xf + 3.0 * L : 0.0);
+            }
+        } else {
+            *bytes += 4.0 * L + words8(b.m) + (bp.modified ? words8(b.m) : 0.0);
+            *ops += xform_ops(h.col) * h.C + 4.0 * L;
+        }
+    }
+}
+
+const char *flat_name(int pass, int mode) {
+    return pass == 1 ? "colfwd" : pass == 3 ? "colinv" : mode == 1 ? "rowspec" : "rowconv";
+}
+
+}  // namespace
+
+// Launches every pass against the device copy of the table region at ws.
+pa_status launch_batch(const BatchPrep &bp, void *ws, hipStream_t s) {
     const int ng = (int)bp.groups.size();
     if (ng == 0) return PA_OK;
+    if (bp.form == kFormFlat) {
+        const pa::LenPlan *dplans = (const pa::LenPlan *)((char *)ws + bp.plans_off);
+        auto launch_one = [&](const BatchPrep::PassLaunch &pl, hipStream_t ls) {
+            pa::JobArgs ja{};
+            ja.table = (const pa::JobDesc *)((char *)ws + pl.tab_off);
+            ja.seg = (const uint32_t *)((char *)ws + pl.seg_off);
+            ja.njobs = (uint32_t)pl.blocks.size();
+            double bytes = 0, ops = 0, written = 0;
+            flat_costs(bp, pl, &bytes, &ops, &written);
+            pa::FlatLaunch fl = pl.fl;
+            fl.bytes_written = written;
+            return timed(flat_name(pl.pass, pl.mode), bytes, ops, [&](hipEvent_t a, hipEvent_t b) {
+                if (pl.pass == 1) return pa::launch_colfwd_flat(fl, dplans, ja, ls, a, b);
+                if (pl.pass == 2) return pa::launch_rowconv_flat(fl, dplans, pl.mode, ja, ls, a, b);
+                return pa::launch_colinv_flat(fl, dplans, ja, ls, a, b);
+            });
+        };
+        // the passes follow each other on s (running a pass's launches on
+        // concurrent lanes measured no faster)
+        for (const auto &pl : bp.launches) {
+            const hipError_t e = launch_one(pl, s);
+            if (e != hipSuccess) return from_hip(e, "flat batch launch");
+        }
+        return PA_OK;
+    }
+    const pa::JobDesc *dtable = (const pa::JobDesc *)ws;
     const int lanes = std::min(ng, 1 + kSideStreams);
     std::vector<int> order(ng), lane_of(ng, 0);
     std::vector<double> work(ng), load(lanes, 0.0);
@@ -720,13 +927,12 @@ pa_status launch_batch(const BatchPrep &bp, const pa::JobDesc *dtable, hipStream
 pa_status hash_batched(const pa_block *blocks, uint32_t count, hipStream_t s, bool modified) {
     if (count == 0) return PA_OK;
     BatchPrep bp;
-    PA_TRY(prepare_batch(blocks, count, modified, &bp));
+    PA_TRY(prepare_batch(blocks, count, modified, &bp, batch_form(kFormFlat)));
     void *ws = nullptr;
     PA_TRY(get_workspace(s, bp.total_bytes, &ws));
     build_table(bp, ws);
-    pa::JobDesc *dtable = (pa::JobDesc *)ws;
-    PA_TRY(stage_upload(s, dtable, bp.table.data(), bp.table.size() * sizeof(pa::JobDesc)));
-    return launch_batch(bp, dtable, s);
+    PA_TRY(stage_upload(s, ws, bp.blob.data(), bp.blob.size()));
+    return launch_batch(bp, ws, s);
 }
 
 }  // namespace rt

@@ -24,6 +24,7 @@ struct pa_graph_s {
     hipGraphExec_t exec = nullptr;
     uint32_t count = 0;
     bool modified = false;
+    BatchForm form = kFormLanes;  // launch form captured
     // length-group signature the launches were captured for: (L, blocks)
     std::vector<std::pair<uint64_t, size_t>> groups;
 };
@@ -57,11 +58,12 @@ pa_status pa_graph_create(const pa_block *blocks, uint32_t count, int modified, 
     *graph = nullptr;
     if (count == 0) return fail(PA_ERR_INVALID_ARG, "empty block array");
     BatchPrep bp;
-    PA_TRY(prepare_batch(blocks, count, modified != 0, &bp));
+    PA_TRY(prepare_batch(blocks, count, modified != 0, &bp, batch_form(kFormLanes)));
     pa_graph_s *g = new (std::nothrow) pa_graph_s();
     if (!g) return fail(PA_ERR_OUT_OF_MEMORY, "host allocation");
     g->count = count;
     g->modified = modified != 0;
+    g->form = bp.form;
     for (const auto &gr : bp.groups) g->groups.push_back({gr.L, gr.members.size()});
     auto bail = [&](pa_status st) {
         destroy_graph(g);
@@ -71,7 +73,7 @@ pa_status pa_graph_create(const pa_block *blocks, uint32_t count, int modified, 
     if (e == hipSuccess) e = hipMalloc(&g->buf, bp.total_bytes);
     if (e != hipSuccess) return bail(from_hip(e, "graph workspace"));
     build_table(bp, g->buf);
-    e = hipMemcpy(g->buf, bp.table.data(), bp.table.size() * sizeof(pa::JobDesc), hipMemcpyHostToDevice);
+    e = hipMemcpy(g->buf, bp.blob.data(), bp.blob.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking);
     if (e != hipSuccess) return bail(from_hip(e, "graph setup"));
     // everything created lazily on the launch path exists before capture:
@@ -94,7 +96,7 @@ pa_status pa_graph_create(const pa_block *blocks, uint32_t count, int modified, 
     pa_status st;
     {
         CaptureFlag cf;
-        st = launch_batch(bp, (const pa::JobDesc *)g->buf, g->capture);
+        st = launch_batch(bp, g->buf, g->capture);
     }
     hipGraph_t captured = nullptr;
     e = hipStreamEndCapture(g->capture, &captured);
@@ -123,7 +125,7 @@ pa_status pa_graph_update(pa_graph_t graph, const pa_block *blocks, uint32_t cou
     if (dev != graph->device) return fail(PA_ERR_INVALID_ARG, "graph belongs to another device");
     if (count != graph->count) return fail(PA_ERR_INVALID_ARG, "block count differs from the graph's");
     BatchPrep bp;
-    PA_TRY(prepare_batch(blocks, count, graph->modified, &bp));
+    PA_TRY(prepare_batch(blocks, count, graph->modified, &bp, graph->form));
     bool same = bp.groups.size() == graph->groups.size();
     for (size_t i = 0; same && i < bp.groups.size(); ++i)
         same = bp.groups[i].L == graph->groups[i].first && bp.groups[i].members.size() == graph->groups[i].second;
@@ -131,7 +133,7 @@ pa_status pa_graph_update(pa_graph_t graph, const pa_block *blocks, uint32_t cou
     // Same groups give the same table layout (descriptors and 2L residues
     // per block, in group order); the captured launches keep their plans.
     build_table(bp, graph->buf);
-    return stage_upload((hipStream_t)stream, graph->buf, bp.table.data(), bp.table.size() * sizeof(pa::JobDesc));
+    return stage_upload((hipStream_t)stream, graph->buf, bp.blob.data(), bp.blob.size());
 }
 
 uint32_t pa_graph_block_count(pa_graph_t graph) { return graph ? graph->count : 0; }

@@ -107,6 +107,8 @@ struct LenPlan {
     int ntiles;              // C / W
     int col_threads;         // workgroup size of the column passes
     int row_threads;         // largest row-pass workgroup (launches over many rows may use fewer)
+    int row_threads_fixed;   // 1: launches use exactly row_threads (a tuned choice)
+    int row_first;           // row_first of the geometry (0: default)
     int col_lds;             // LDS ints of one column tile (padded)
     int row_lds;             // LDS ints of one row (padded)
     int fused_ok;            // two rows fit in LDS: the plain path runs seed and key in one row pass
@@ -134,13 +136,19 @@ struct JobDesc {
     uint32_t shift;        // shift of source 0 (off0 - (n - 1)); source 1 is unshifted
     uint32_t key_off;      // source 0 starts at this bit of `key` (modified Toeplitz: m)
     const uint64_t *xor_src;  // non-null: P3 XORs output bit i with bit i of this array
+    uint32_t plan_idx;     // flat launches: index of the job's plan in the launch's plan array
 };
 
 // Jobs of a launch: either one descriptor passed inline in the kernel
-// arguments, or a device table indexed by a grid dimension.
+// arguments, or a device table indexed by a grid dimension, or (a flat
+// launch over jobs of several lengths, whose plans are an array passed as
+// the kernels' plan argument) a device table with seg[j] the first
+// workgroup of job j and seg[njobs] the grid size.
 struct JobArgs {
     const JobDesc *table;
     JobDesc one;
+    const uint32_t *seg;
+    uint32_t njobs;
 };
 
 }  // namespace pa

@@ -31,6 +31,33 @@ hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int mode, const 
 hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const JobArgs &ja, int njobs, hipStream_t s,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
+// A flat launch over the jobs of several lengths (JobArgs with seg set):
+// the kernel variant (column passes: the largest round's lg, 3 or 4; row
+// pass: the first-round kind), workgroup size (row pass: the plans' size,
+// which the launch may lower for occupancy, or minus a fixed one) and LDS
+// bytes shared by its jobs (the largest any of them needs), the workgroup
+// count, and (column pass) the bytes it writes, which decides its store
+// policy.
+struct FlatLaunch {
+    int variant;
+    int threads;
+    size_t lds;
+    uint32_t nwg;
+    double bytes_written;
+};
+// `plans`: device array of the plans the jobs' plan_idx refer to.
+hipError_t launch_colfwd_flat(const FlatLaunch &fl, const LenPlan *plans, const JobArgs &ja, hipStream_t s,
+                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_rowconv_flat(const FlatLaunch &fl, const LenPlan *plans, int mode, const JobArgs &ja,
+                               hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_colinv_flat(const FlatLaunch &fl, const LenPlan *plans, const JobArgs &ja, hipStream_t s,
+                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// Largest radix-2 round (lg) of a plan's column transform.
+int col_max_lg(const LenPlan &hp);
+// Resident workgroups per CU (0 if unknown) for the given launch shape.
+int rowconv_wgs_per_cu(int fk, int threads, size_t lds);
+int col_wgs_per_cu(bool inverse, int lg, int threads, size_t lds);
+
 // One-time per-device launch setup for a plan's kernels (LDS opt-in,
 // register counts), so that later launches make no attribute calls (for
 // example inside a stream capture).

@@ -98,6 +98,14 @@ struct TwPair {
 typedef __attribute__((address_space(4))) const TwPair ctwpair;
 __device__ __forceinline__ double2 ld_const(const ctwpair *t, int i) { return make_double2(t[i].w, t[i].wp); }
 
+// Plans in device memory are read through the constant address space: the
+// kernels never write them, and uniform loads from that space are scalar
+// (s_load) whatever the pointer's origin (a kernel argument, or a plan
+// array indexed per job in flat launches).
+typedef __attribute__((address_space(4))) const LenPlan CPlan;
+typedef __attribute__((address_space(4))) const XDesc CXDesc;
+typedef __attribute__((address_space(4))) const RoundDesc CRoundDesc;
+
 // Wave-uniform copies (SGPRs) of values the compiler cannot prove uniform;
 // buffer resources built from them need no waterfall loop.
 template <class T>
@@ -204,7 +212,7 @@ using RegArrN = double[NA][(N3 == 0 ? 1 : N3 == 1 ? 3 : N3 == 2 ? 9 : 27) << N2]
 // block has gamma = 1, so its inputs enter the DFT unmultiplied (they are
 // reduced residues or bits, within the bound a product would give).
 template <int N3, int N2, int K, int NA, bool TRIV = false>
-__device__ __forceinline__ void fwd_stage(RegArrN<N3, N2, NA> &v, int b, const double2 *__restrict__ tw, int off) {
+__device__ __forceinline__ void fwd_stage(RegArrN<N3, N2, NA> &v, int b, const ctwpair *tw, int off) {
     using S = Shape<N3, N2>;
     constexpr int r = S::radix(K), rb = S::before(K), ra = S::after(K);
     static_assert(!TRIV || rb == 1, "only the first stage has a single block");
@@ -212,7 +220,7 @@ __device__ __forceinline__ void fwd_stage(RegArrN<N3, N2, NA> &v, int b, const d
     for (int sb = 0; sb < rb; ++sb) {
         const int t = off + (b * rb + sb) * (r - 1);
         if constexpr (r == 2) {
-            const double2 w = TRIV ? make_double2(1.0, 0.0) : tw[t];
+            const double2 w = TRIV ? make_double2(1.0, 0.0) : ld_const(tw, t);
 #pragma unroll
             for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -224,7 +232,7 @@ __device__ __forceinline__ void fwd_stage(RegArrN<N3, N2, NA> &v, int b, const d
                     v[a][i1] = y - mm;
                 }
         } else {
-            const double2 w1 = TRIV ? make_double2(1.0, 0.0) : tw[t], w2 = TRIV ? make_double2(1.0, 0.0) : tw[t + 1];
+            const double2 w1 = TRIV ? make_double2(1.0, 0.0) : ld_const(tw, t), w2 = TRIV ? make_double2(1.0, 0.0) : ld_const(tw, t + 1);
 #pragma unroll
             for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -247,7 +255,7 @@ __device__ __forceinline__ void fwd_stage(RegArrN<N3, N2, NA> &v, int b, const d
 // transform's last stage (inverted first), whose sub-blocks have length 1,
 // so j' = 0 and the factor is 1; its inputs are reduced residues.
 template <int N3, int N2, int K, bool TRIV = false>
-__device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, const double2 *__restrict__ tw,
+__device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, const ctwpair *tw,
                                           int off) {
     using S = Shape<N3, N2>;
     constexpr int r = S::radix(K), rb = S::before(K), ra = S::after(K);
@@ -256,7 +264,7 @@ __device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, 
     for (int x = 0; x < ra; ++x) {
         const int t = off + (x * jlast + jj) * (r - 1);
         if constexpr (r == 2) {
-            const double2 w = TRIV ? make_double2(1.0, 0.0) : tw[t];
+            const double2 w = TRIV ? make_double2(1.0, 0.0) : ld_const(tw, t);
 #pragma unroll
             for (int sb = 0; sb < rb; ++sb) {
                 const int i0 = sb * 2 * ra + x, i1 = i0 + ra;
@@ -266,7 +274,7 @@ __device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, 
                 v[i1] = a - mm;
             }
         } else {
-            const double2 w1 = TRIV ? make_double2(1.0, 0.0) : tw[t], w2 = TRIV ? make_double2(1.0, 0.0) : tw[t + 1];
+            const double2 w1 = TRIV ? make_double2(1.0, 0.0) : ld_const(tw, t), w2 = TRIV ? make_double2(1.0, 0.0) : ld_const(tw, t + 1);
 #pragma unroll
             for (int sb = 0; sb < rb; ++sb) {
                 const int i0 = sb * 3 * ra + x, i1 = i0 + ra, i2 = i1 + ra;
@@ -291,8 +299,8 @@ constexpr bool kStageFence = Shape<N3, N2>::RHO > 8 && Shape<N3, N2>::RHO != 16;
 
 // FIRST: the round holds the transform's first stage (K = 0 is trivial).
 template <int N3, int N2, int K, int NA, bool FIRST = false>
-__device__ __forceinline__ void fwd_stages(RegArrN<N3, N2, NA> &v, int b, const XDesc &xd,
-                                           const double2 *__restrict__ tw, int s0) {
+__device__ __forceinline__ void fwd_stages(RegArrN<N3, N2, NA> &v, int b, const CXDesc &xd,
+                                           const ctwpair *tw, int s0) {
     if constexpr (K < Shape<N3, N2>::Q) {
         fwd_stage<N3, N2, K, NA, FIRST && K == 0>(v, b, tw, xd.fwd_off[s0 + K]);
         if constexpr (kStageFence<N3, N2>) __builtin_amdgcn_sched_barrier(0);
@@ -302,8 +310,8 @@ __device__ __forceinline__ void fwd_stages(RegArrN<N3, N2, NA> &v, int b, const 
 
 // LAST: the round holds the transform's last stage (K = Q-1 is trivial).
 template <int N3, int N2, int K, bool LAST = false>
-__device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast, const XDesc &xd,
-                                           const double2 *__restrict__ tw, int s0) {
+__device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast, const CXDesc &xd,
+                                           const ctwpair *tw, int s0) {
     if constexpr (K >= 0) {
         inv_stage<N3, N2, K, LAST && K == Shape<N3, N2>::Q - 1>(v, jj, jlast, tw, xd.inv_off[s0 + K]);
         if constexpr (kStageFence<N3, N2>) __builtin_amdgcn_sched_barrier(0);
@@ -346,8 +354,8 @@ __device__ __forceinline__ Geo launder(Geo g) {
 // key array (index 1) is inverse-transformed.
 template <int MODE, int N3, int N2, bool FIRST, bool LAST, int NA = 1, bool GENJ = false, class Pre, class Load, class Mid,
           class Store>
-__device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, const double2 *__restrict__ ftw,
-                                         const double2 *__restrict__ itw, int wsh, Pre &pre, Load &load, Mid &mid,
+__device__ __forceinline__ void round_io(const CRoundDesc &rd, const CXDesc &xd, const ctwpair *ftw,
+                                         const ctwpair *itw, int wsh, Pre &pre, Load &load, Mid &mid,
                                          Store &store) {
     constexpr int RHO = Shape<N3, N2>::RHO;
     const int W = 1 << wsh;
@@ -411,10 +419,10 @@ __device__ __forceinline__ void round_io(const RoundDesc &rd, const XDesc &xd, c
 // stage (kinds 3 and 6, after a 9-value first round).
 template <int MODE, bool FIRST, bool LAST, int MAXLG, int NA = 1, bool MIX = false, class Pre, class Load, class Mid,
           class Store>
-__device__ __forceinline__ void round_p2(const XDesc &xd, const double2 *__restrict__ ftw,
-                                         const double2 *__restrict__ itw, int r, int wsh, Pre &pre, Load &load,
+__device__ __forceinline__ void round_p2(const CXDesc &xd, const ctwpair *ftw,
+                                         const ctwpair *itw, int r, int wsh, Pre &pre, Load &load,
                                          Mid &mid, Store &store) {
-    const RoundDesc &rd = xd.round[r];
+    const CRoundDesc &rd = xd.round[r];
     switch (rd.kind) {
         case 4:
             if constexpr (MIX) round_io<MODE, 1, 0, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store);
@@ -436,8 +444,8 @@ __device__ __forceinline__ void round_p2(const XDesc &xd, const double2 *__restr
 
 // Round 0 of a transform whose first round has the compile-time kind FK.
 template <int MODE, int FK, bool LAST, int NA = 1, class Pre, class Load, class Mid, class Store>
-__device__ __forceinline__ void round_fk(const XDesc &xd, const double2 *__restrict__ ftw,
-                                         const double2 *__restrict__ itw, int wsh, Pre &pre, Load &load, Mid &mid,
+__device__ __forceinline__ void round_fk(const CXDesc &xd, const ctwpair *ftw,
+                                         const ctwpair *itw, int wsh, Pre &pre, Load &load, Mid &mid,
                                          Store &store) {
     // a 9-value first row round leaves a stride of 3 * 2^k
     constexpr bool kGenJ = kKindN3[FK] == 2;
@@ -459,9 +467,8 @@ extern __shared__ int pa_lds[];
 
 // P1: forward column NTT of one W-column tile of a bit string.  Transform
 // input position p = q*C + c0 + c holds bit p - shift of the source when
-// that index lies in [0, nbits), else 0.  blockIdx.y selects the source
-// (0: job.key shifted by job.shift into job.A; 1: job.seed into job.S) and
-// blockIdx.z the job.
+// that index lies in [0, nbits), else 0.  Source 0 is job.key shifted by
+// job.shift (into job.A), source 1 job.seed (into job.S).
 #define PA_INLINE __attribute__((always_inline))
 
 // Column tile of this workgroup.  Workgroups are dispatched round-robin
@@ -474,9 +481,28 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
     return (bid & 7) * per + (bid >> 3);
 }
 
+// Flat launches (ja.seg set): workgroup wg belongs to the job j with
+// seg[j] <= wg < seg[j + 1] (a binary search over scalar loads); the
+// workgroup's index inside its job is wg - seg[j].
+__device__ __forceinline__ uint32_t flat_job(const JobArgs &ja, uint32_t wg, uint32_t *local) {
+    typedef __attribute__((address_space(4))) const uint32_t cu32;
+    const cu32 *seg = (const cu32 *)uni(ja.seg);
+    uint32_t lo = 0, hi = uni(ja.njobs);  // seg[lo] <= wg < seg[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (seg[mid] <= wg)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    *local = wg - seg[lo];
+    return lo;
+}
+
 // The job's descriptor (every field wave-uniform).
 __device__ __forceinline__ JobDesc job_of(const JobArgs &ja, unsigned idx) {
     JobDesc j = ja.table ? ja.table[idx] : ja.one;
+    j.plan_idx = uni(j.plan_idx);
     j.key = uni(j.key);
     j.seed = uni(j.seed);
     j.out = uni(j.out);
@@ -495,14 +521,33 @@ __device__ __forceinline__ JobDesc job_of(const JobArgs &ja, unsigned idx) {
 
 // MAXLG: largest radix-2 round of the plan's column transform (3: rounds of
 // at most 8 values, compiled without the 16-value case and its registers).
+// Grid: (tiles, sources, jobs) with plan[0] the launch's plan, or, in a
+// flat launch, one dimension covering every job's tiles of source 0 then
+// source 1, each job with its own plan, plan[job.plan_idx].
 template <int MAXLG, bool WT>
-__global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan, JobArgs ja,
-                                                const double2 *__restrict__ ftw) {
-    const double2 *itw = nullptr;
-    const LenPlan &lp = *plan;
-    const XDesc &xd = lp.col;
-    const JobDesc job = job_of(ja, blockIdx.z);
-    const bool src = blockIdx.y != 0;
+__global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan, JobArgs ja) {
+    uint32_t jidx, tile;
+    bool src;
+    const LenPlan *pp = plan;
+    if (ja.seg) {
+        uint32_t local = 0;
+        jidx = flat_job(ja, blockIdx.x, &local);
+        pp = plan + uni(ja.table[jidx].plan_idx);
+        const uint32_t nt = (uint32_t)pp->ntiles;
+        src = local >= nt;
+        tile = src ? local - nt : local;
+    } else {
+        jidx = blockIdx.z;
+        src = blockIdx.y != 0;
+        tile = blockIdx.x;
+    }
+    // every value above is the same on all lanes: keep it in SGPRs
+    jidx = uni(jidx);
+    tile = uni(tile);
+    const CPlan &lp = *(const CPlan *)pp;
+    const CXDesc &xd = lp.col;
+    const ctwpair *ftw = (const ctwpair *)uni(xd.fwd_tw), *itw = nullptr;
+    const JobDesc job = job_of(ja, jidx);
     const int nbits = (int)(src ? job.seed_bits : job.n);
     const int shift = src ? 0 : (int)job.shift;
     // source 0 may start at bit key_off: address its 32-bit word, keep the
@@ -513,7 +558,7 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
     const rsrc_t bits = make_rsrc(base, (uint32_t)(((uint32_t)nbits + (uint32_t)ro + 31) / 32 * 4));
     const rsrc_t out = make_rsrc(src ? job.S : job.A, (uint32_t)(lp.L * 4));
     const int W = lp.W, wsh = __builtin_ctz((unsigned)W), C = lp.C;
-    const int c0 = xcd_tile(blockIdx.x, lp.ntiles) * W;
+    const int c0 = xcd_tile((int)tile, lp.ntiles) * W;
     int *lds = pa_lds;
     auto pre = [&](int, int, int) PA_INLINE { return NoCtx{}; };
     auto mid = [&](const auto &, auto &, Geo) PA_INLINE {};
@@ -579,17 +624,30 @@ struct TwCtx {
     double2 beta;
 };
 
+// Grid: (rows, jobs) with plan[0] the launch's plan, or, in a flat launch,
+// one dimension covering every job's rows, each job with its own plan,
+// plan[job.plan_idx].
 template <int FK>
-__global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ plan, JobArgs ja, int mode,
-                                                 const double2 *__restrict__ ftw, const double2 *__restrict__ itw) {
-    const LenPlan &lp = *plan;
-    const XDesc &xd = lp.row;
+__global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ plan, JobArgs ja, int mode) {
+    uint32_t jidx, row;
+    const LenPlan *pp = plan;
+    if (ja.seg) {
+        jidx = flat_job(ja, blockIdx.x, &row);
+        pp = plan + uni(ja.table[jidx].plan_idx);
+    } else {
+        jidx = blockIdx.y;
+        row = blockIdx.x;
+    }
+    jidx = uni(jidx);
+    row = uni(row);
+    const CPlan &lp = *(const CPlan *)pp;
+    const CXDesc &xd = lp.row;
+    const ctwpair *ftw = (const ctwpair *)uni(xd.fwd_tw), *itw = (const ctwpair *)uni(xd.inv_tw);
     // a 9-value first round may be followed by a round with the last
     // radix-3 stage (lengths with 27 | C)
     constexpr bool kMix = kKindN3[FK] == 2;
-    const JobDesc job = job_of(ja, blockIdx.y);
+    const JobDesc job = job_of(ja, jidx);
     const int C = lp.C, nr = xd.nrounds;
-    const uint32_t row = blockIdx.x;
     const size_t rbase = (size_t)row * (size_t)C;
     const rsrc_t rowA = make_rsrc(job.A + rbase, (uint32_t)C * 4);
     const rsrc_t rowS = make_rsrc(job.S + rbase, (uint32_t)C * 4);
@@ -714,19 +772,32 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
 // multiple of 64, matching the key shift of P1).  Chunks of W bits are
 // written whole for i < 64*ceil(m/64); bits >= m are zero.  blockIdx.y
 // selects the job.
+// Grid: (tiles, jobs) with plan[0] the launch's plan, or, in a flat
+// launch, one dimension covering every job's tiles, each with its own plan,
+// plan[job.plan_idx].
 template <int MAXLG>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_colinv(const LenPlan *__restrict__ plan,
-                                                                                       JobArgs ja,
-                                                                                       const double2 *__restrict__ itw) {
-    const double2 *ftw = nullptr;
-    const LenPlan &lp = *plan;
-    const XDesc &xd = lp.col;
-    const JobDesc job = job_of(ja, blockIdx.y);
+__global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan,
+                                                                                       JobArgs ja) {
+    uint32_t jidx, tile;
+    const LenPlan *pp = plan;
+    if (ja.seg) {
+        jidx = flat_job(ja, blockIdx.x, &tile);
+        pp = plan + uni(ja.table[jidx].plan_idx);
+    } else {
+        jidx = blockIdx.y;
+        tile = blockIdx.x;
+    }
+    jidx = uni(jidx);
+    tile = uni(tile);
+    const CPlan &lp = *(const CPlan *)pp;
+    const CXDesc &xd = lp.col;
+    const ctwpair *ftw = nullptr, *itw = (const ctwpair *)uni(xd.inv_tw);
+    const JobDesc job = job_of(ja, jidx);
     const int32_t *A = job.A;
     uint64_t *out = job.out;
     const uint32_t off0 = job.off0, m = job.m;
     const int W = lp.W, wsh = __builtin_ctz((unsigned)W), C = lp.C, nr = xd.nrounds;
-    const int c0 = xcd_tile(blockIdx.x, lp.ntiles) * W;
+    const int c0 = xcd_tile((int)tile, lp.ntiles) * W;
     int *lds = pa_lds;
     const rsrc_t ain = make_rsrc(A, (uint32_t)(lp.L * 4));
     const rsrc_t obuf = make_rsrc(out, (uint32_t)((m + 63) / 64 * 8));
@@ -845,7 +916,7 @@ hipError_t warm_launch_state(const LenPlan &hp) {
 }
 
 // Largest radix-2 round (log2 of its size) of the column transform.
-static int col_max_lg(const LenPlan &hp) {
+int col_max_lg(const LenPlan &hp) {
     int mx = 0;
     for (int r = 0; r < hp.col.nrounds; ++r) {
         const int k = hp.col.round[r].kind;
@@ -854,18 +925,10 @@ static int col_max_lg(const LenPlan &hp) {
     return mx;
 }
 
-hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const JobArgs &ja, int njobs,
-                         hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    int limit = 0;
-    hipError_t e = set_lds_limits(&limit);
-    if (e != hipSuccess) return e;
-    const size_t lds = (size_t)hp.col_lds * sizeof(int);
-    if (lds > (size_t)limit || nsrc < 1 || nsrc > 2 || njobs < 1 || njobs > 65535) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)hp.ntiles, (unsigned)nsrc, (unsigned)njobs), block((unsigned)hp.col_threads);
-    // write-through stores unless the launch writes more than kColWtBytes
-    const bool wt = (double)nsrc * (double)njobs * 4.0 * (double)hp.L <= (double)kColWtBytes;
-    const bool lg3 = col_max_lg(hp) <= 3;
-#define PA_CF(LG, WTV) hipExtLaunchKernelGGL((k_colfwd<LG, WTV>), grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, hp.col.fwd_tw)
+static hipError_t colfwd_launch(bool lg3, bool wt, dim3 grid, int threads, size_t lds, const LenPlan *dp,
+                                const JobArgs &ja, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const dim3 block((unsigned)threads);
+#define PA_CF(LG, WTV) hipExtLaunchKernelGGL((k_colfwd<LG, WTV>), grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja)
     if (lg3) {
         if (wt) PA_CF(3, true); else PA_CF(3, false);
     } else {
@@ -873,6 +936,31 @@ hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const J
     }
 #undef PA_CF
     return hipGetLastError();
+}
+
+hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const JobArgs &ja, int njobs,
+                         hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    int limit = 0;
+    hipError_t e = set_lds_limits(&limit);
+    if (e != hipSuccess) return e;
+    const size_t lds = (size_t)hp.col_lds * sizeof(int);
+    if (lds > (size_t)limit || nsrc < 1 || nsrc > 2 || njobs < 1 || njobs > 65535 || ja.seg)
+        return hipErrorInvalidConfiguration;
+    // write-through stores unless the launch writes more than kColWtBytes
+    const bool wt = (double)nsrc * (double)njobs * 4.0 * (double)hp.L <= (double)kColWtBytes;
+    return colfwd_launch(col_max_lg(hp) <= 3, wt, dim3((unsigned)hp.ntiles, (unsigned)nsrc, (unsigned)njobs),
+                         hp.col_threads, lds, dp, ja, s, e0, e1);
+}
+
+hipError_t launch_colfwd_flat(const FlatLaunch &fl, const LenPlan *plans, const JobArgs &ja, hipStream_t s, hipEvent_t e0,
+                              hipEvent_t e1) {
+    int limit = 0;
+    hipError_t e = set_lds_limits(&limit);
+    if (e != hipSuccess) return e;
+    if (fl.lds > (size_t)limit || !ja.seg || !ja.table || fl.nwg == 0 || (fl.variant != 3 && fl.variant != 4))
+        return hipErrorInvalidConfiguration;
+    const bool wt = fl.bytes_written <= kColWtBytes;
+    return colfwd_launch(fl.variant == 3, wt, dim3(fl.nwg), fl.threads, fl.lds, plans, ja, s, e0, e1);
 }
 
 // VGPRs per thread of k_rowconv<fk> (cached; from the code object).
@@ -908,7 +996,7 @@ static hipError_t rowconv_regs(int fk, int *regs) {
 // thread and `lds` bytes each: 4 SIMDs of 512 VGPRs (granule 8) and at most
 // 8 waves each; a workgroup's waves are spread evenly over the SIMDs.
 static int resident_waves(int t, int regs, size_t lds, int lds_limit) {
-    const int per_simd = t / 256;  // t is a multiple of 256
+    const int per_simd = (t + 255) / 256;
     const int vg = (regs + 7) / 8 * 8;
     int simd_waves = 512 / vg;
     if (simd_waves > 8) simd_waves = 8;
@@ -918,46 +1006,91 @@ static int resident_waves(int t, int regs, size_t lds, int lds_limit) {
     return wgs * t / 64;
 }
 
+// Row workgroup size for `rows` rows of plans whose largest row pass needs
+// `plan_threads` threads: with rows for two or more workgroups per CU, the
+// size that keeps the most waves resident per CU (ties: the smaller, whose
+// workgroups do not wait on each other's barriers); a single block's few
+// rows leave one workgroup per CU: the plan's full size.
+static hipError_t row_threads_for(int fk, int plan_threads, size_t rows, size_t lds, int limit, int *threads) {
+    *threads = plan_threads;
+    if (rows < 512) return hipSuccess;
+    int regs = 0;
+    hipError_t e = rowconv_regs(fk, &regs);
+    if (e != hipSuccess) return e;
+    int best = 0;
+    for (int t : {512, 768, 1024}) {
+        if (t > plan_threads) continue;
+        const int w = resident_waves(t, regs, lds, limit);
+        if (w > best) {
+            best = w;
+            *threads = t;
+        }
+    }
+    return hipSuccess;
+}
+
+int rowconv_wgs_per_cu(int fk, int threads, size_t lds) {
+    int limit = 0, regs = 0;
+    if (set_lds_limits(&limit) != hipSuccess || rowconv_regs(fk, &regs) != hipSuccess) return 0;
+    return resident_waves(threads, regs, lds, limit) * 64 / threads;
+}
+
+static hipError_t rowconv_launch(int fk, dim3 grid, int threads, size_t lds, const LenPlan *dp, int mode,
+                                 const JobArgs &ja, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const dim3 block((unsigned)threads);
+    switch (fk) {
+#define PA_FK(K)                                                                                         \
+    case K:                                                                                              \
+        hipExtLaunchKernelGGL(k_rowconv<K>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, mode);     \
+        break;
+        PA_FK(0) PA_FK(1) PA_FK(2) PA_FK(4) PA_FK(5) PA_FK(6) PA_FK(7)
+#undef PA_FK
+        default: return hipErrorInvalidConfiguration;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int mode, const JobArgs &ja, int njobs,
                           hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     int limit = 0;
     hipError_t e = set_lds_limits(&limit);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)hp.row_lds * sizeof(int) * (mode == 2 ? 2 : 1);
-    if (lds > (size_t)limit || njobs < 1 || njobs > 65535 || (mode == 2 && !hp.fused_ok))
+    if (lds > (size_t)limit || njobs < 1 || njobs > 65535 || (mode == 2 && !hp.fused_ok) || ja.seg)
         return hipErrorInvalidConfiguration;
     const int fk = hp.row.round[0].kind;
     if (fk < 0 || fk >= kNumKinds) return hipErrorInvalidConfiguration;
     int threads = hp.row_threads;
-    // With rows for two or more workgroups per CU, take the size that keeps
-    // the most waves resident per CU (ties: the smaller, whose workgroups
-    // do not wait on each other's barriers).  A single block's few rows
-    // leave one workgroup per CU: the plan's full size.
-    if ((size_t)hp.R * (size_t)njobs >= 512) {
-        int regs = 0;
-        e = rowconv_regs(fk, &regs);
+    if (!hp.row_threads_fixed) {
+        e = row_threads_for(fk, hp.row_threads, (size_t)hp.R * (size_t)njobs, lds, limit, &threads);
         if (e != hipSuccess) return e;
-        int best = 0;
-        for (int t : {512, 768, 1024}) {
-            if (t > hp.row_threads) continue;
-            const int w = resident_waves(t, regs, lds, limit);
-            if (w > best) {
-                best = w;
-                threads = t;
-            }
-        }
     }
-    const dim3 grid((unsigned)hp.R, (unsigned)njobs), block((unsigned)threads);
-    switch (hp.row.round[0].kind) {
-#define PA_FK(K) \
-    case K:                                                                                              \
-        hipExtLaunchKernelGGL(k_rowconv<K>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, mode, hp.row.fwd_tw, \
-                              hp.row.inv_tw);                                                            \
-        break;
-        PA_FK(0) PA_FK(1) PA_FK(2) PA_FK(4) PA_FK(5) PA_FK(6) PA_FK(7)
-#undef PA_FK
-        default: return hipErrorInvalidConfiguration;
+    return rowconv_launch(fk, dim3((unsigned)hp.R, (unsigned)njobs), threads, lds, dp, mode, ja, s, e0, e1);
+}
+
+hipError_t launch_rowconv_flat(const FlatLaunch &fl, const LenPlan *plans, int mode, const JobArgs &ja,
+                               hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    int limit = 0;
+    hipError_t e = set_lds_limits(&limit);
+    if (e != hipSuccess) return e;
+    if (fl.lds > (size_t)limit || !ja.seg || !ja.table || fl.nwg == 0 || !rowconv_fn(fl.variant))
+        return hipErrorInvalidConfiguration;
+    // a negative size is a fixed (tuned) one
+    int threads = -fl.threads;
+    if (fl.threads > 0) {
+        e = row_threads_for(fl.variant, fl.threads, fl.nwg, fl.lds, limit, &threads);
+        if (e != hipSuccess) return e;
     }
+    return rowconv_launch(fl.variant, dim3(fl.nwg), threads, fl.lds, plans, mode, ja, s, e0, e1);
+}
+
+static hipError_t colinv_launch(bool lg3, dim3 grid, int threads, size_t lds, const LenPlan *dp, const JobArgs &ja,
+                                hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const dim3 block((unsigned)threads);
+    if (lg3)
+        hipExtLaunchKernelGGL(k_colinv<3>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja);
+    else
+        hipExtLaunchKernelGGL(k_colinv<4>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja);
     return hipGetLastError();
 }
 
@@ -967,13 +1100,36 @@ hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const JobArgs &ja
     hipError_t e = set_lds_limits(&limit);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)hp.col_lds * sizeof(int);
-    if (lds > (size_t)limit || njobs < 1 || njobs > 65535) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)hp.ntiles, (unsigned)njobs), block((unsigned)hp.col_threads);
-    if (col_max_lg(hp) <= 3)
-        hipExtLaunchKernelGGL(k_colinv<3>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, hp.col.inv_tw);
-    else
-        hipExtLaunchKernelGGL(k_colinv<4>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, hp.col.inv_tw);
-    return hipGetLastError();
+    if (lds > (size_t)limit || njobs < 1 || njobs > 65535 || ja.seg) return hipErrorInvalidConfiguration;
+    return colinv_launch(col_max_lg(hp) <= 3, dim3((unsigned)hp.ntiles, (unsigned)njobs), hp.col_threads, lds, dp,
+                         ja, s, e0, e1);
+}
+
+hipError_t launch_colinv_flat(const FlatLaunch &fl, const LenPlan *plans, const JobArgs &ja, hipStream_t s, hipEvent_t e0,
+                              hipEvent_t e1) {
+    int limit = 0;
+    hipError_t e = set_lds_limits(&limit);
+    if (e != hipSuccess) return e;
+    if (fl.lds > (size_t)limit || !ja.seg || !ja.table || fl.nwg == 0 || (fl.variant != 3 && fl.variant != 4))
+        return hipErrorInvalidConfiguration;
+    return colinv_launch(fl.variant == 3, dim3(fl.nwg), fl.threads, fl.lds, plans, ja, s, e0, e1);
+}
+
+// Workgroups per CU of a column-pass launch (the kernels' VGPR counts and
+// the LDS of one tile).
+int col_wgs_per_cu(bool inverse, int lg, int threads, size_t lds) {
+    int limit = 0;
+    if (set_lds_limits(&limit) != hipSuccess) return 0;
+    static int regs_cache[2][5];
+    int &rc = regs_cache[inverse ? 1 : 0][lg];
+    if (rc == 0) {
+        hipFuncAttributes a{};
+        const void *fn = inverse ? (lg == 3 ? (const void *)k_colinv<3> : (const void *)k_colinv<4>)
+                                 : (lg == 3 ? (const void *)k_colfwd<3, false> : (const void *)k_colfwd<4, false>);
+        if (hipFuncGetAttributes(&a, fn) != hipSuccess) return 0;
+        rc = a.numRegs > 0 ? a.numRegs : 128;
+    }
+    return resident_waves(threads, rc, lds, limit) * 64 / threads;
 }
 
 }  // namespace pa

@@ -23,6 +23,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "pa_internal.h"
@@ -106,12 +107,24 @@ static int kind_of(int n3, int n2) {
 // first_max > 0: prefer splits whose first round holds at most first_max
 // values, even at the cost of one more round (the row pass carries the
 // seed and key rows together only for such first rounds).
-static std::vector<std::pair<int, int>> split_rounds(int n3, int n2, int maxlg, int first_max = 0) {
+// first_lg >= 0: the first round takes exactly that many radix-2 stages
+// (within the same limits), the later rounds share the rest evenly.
+static std::vector<std::pair<int, int>> split_rounds(int n3, int n2, int maxlg, int first_max = 0, int first_lg = -1) {
     const int cap1[4] = {maxlg, maxlg - 1, 1, 0};
     int c1 = cap1[n3];
     const int p3 = n3 == 0 ? 1 : n3 == 1 ? 3 : n3 == 2 ? 9 : 27;
     if (first_max > 0 && p3 <= first_max) {
         while (c1 > 0 && (p3 << c1) > first_max) --c1;
+    }
+    if (first_lg >= 0) {
+        if (n3 == 3) throw std::runtime_error("lengths with 27 | C keep their built-in first round");
+        if (first_lg > c1 || first_lg > n2 || (n3 == 0 && first_lg == 0))
+            throw std::runtime_error("first round split out of range for this length");
+        const int rem = n2 - first_lg;
+        std::vector<std::pair<int, int>> cand{{n3, first_lg}};
+        const int rest = (rem + maxlg - 1) / maxlg;
+        for (int r = 0; r < rest; ++r) cand.push_back({0, rem / rest + (r < rem % rest ? 1 : 0)});
+        return cand;
     }
     if (first_max > 0 && n3 == 3 && n2 >= 1) {
         // 27 = 9 * 3: a 9-value first round, then the last radix-3 stage
@@ -179,7 +192,7 @@ struct XTables {
 
 // Descriptor and (optionally) twiddle tables of a length-N transform; pure
 // host code.
-static XDesc describe_xdesc(int N, int maxlg, XTables *tabs, int first_max = 0) {
+static XDesc describe_xdesc(int N, int maxlg, XTables *tabs, int first_max = 0, int first_lg = -1) {
     XDesc x{};
     x.N = N;
     uint64_t tmp = (uint64_t)N;
@@ -191,7 +204,7 @@ static XDesc describe_xdesc(int N, int maxlg, XTables *tabs, int first_max = 0) 
     x.nstages = (int)radix.size();
     if (x.nstages > kMaxStages) throw std::runtime_error("too many stages");
 
-    auto rounds = split_rounds(k3, k2, maxlg, first_max);
+    auto rounds = split_rounds(k3, k2, maxlg, first_max, first_lg);
     if ((int)rounds.size() > kMaxRounds) throw std::runtime_error("too many rounds");
     x.nrounds = (int)rounds.size();
     int s = 0;
@@ -304,11 +317,12 @@ static int threads_for(const XDesc &x, int W, int cap) {
 }
 
 static std::mutex g_mu;
-static std::map<std::pair<int, uint64_t>, std::unique_ptr<PlanEntry>> g_plans;
+static std::map<std::tuple<int, uint64_t, Geometry>, std::unique_ptr<PlanEntry>> g_plans;
 
 // Launch geometry of length L (pure host code; throws on invalid choices).
-// log2R = 0 / W = 0 pick the defaults.
-void plan_geometry(uint64_t L, int log2R, int Wreq, LenPlan &lp, XTables *ct, XTables *rt) {
+// Zero fields of g pick the defaults.
+void plan_geometry(uint64_t L, const Geometry &g, LenPlan &lp, XTables *ct, XTables *rt) {
+    const int log2R = g.log2R, Wreq = g.W;
     int k, j;
     factor_len(L, k, j);
     if (L < kMinLen || L > kMaxLen || k < 7 || k > kMaxPow2 || j > kMaxPow3)
@@ -322,7 +336,8 @@ void plan_geometry(uint64_t L, int log2R, int Wreq, LenPlan &lp, XTables *ct, XT
     lp.C = (int)(L >> a);
     if ((uint64_t)lp.R * (uint64_t)lp.C != L || lp.C % 64) throw std::runtime_error("bad four-step split");
     lp.col = describe_xdesc(lp.R, kColMaxLg, ct);
-    lp.row = describe_xdesc(lp.C, kRowMaxLg, rt, kRowDualFirstMax);
+    lp.row = describe_xdesc(lp.C, kRowMaxLg, rt, kRowDualFirstMax, g.row_first - 1);
+    lp.row_first = g.row_first;
     if (lp.row.nrounds < 2) throw std::runtime_error("row transform needs at least two rounds");
     const int rho_c0 = lp.col.round[0].M / lp.col.round[0].J;
     // Column tile width: the extraction ballots need whole waves per item
@@ -347,86 +362,96 @@ void plan_geometry(uint64_t L, int log2R, int Wreq, LenPlan &lp, XTables *ct, XT
     // rows: up to one item per thread in every round, in whole groups of 4
     // waves (one per SIMD: a barrier waits for the SIMD with the most waves)
     lp.row_threads = std::min(1024, (threads_for(lp.row, 1, 1024) + 255) / 256 * 256);
+    if (g.row_threads) {
+        if (g.row_threads != 256 && g.row_threads != 512 && g.row_threads != 768 && g.row_threads != 1024)
+            throw std::runtime_error("row workgroup size must be 256, 512, 768 or 1024");
+        lp.row_threads = g.row_threads;
+        lp.row_threads_fixed = 1;
+    }
     if (round_items(lp.col.round[0], W) % 64) throw std::runtime_error("column round not a multiple of 64 items");
     lp.col_lds = (lp.R + (lp.R >> lp.col.lgpad)) * W;
     lp.row_lds = lp.C + (lp.C >> lp.row.lgpad);
     if (lp.col_lds * 4 > 160 * 1024 || lp.row_lds * 4 > 160 * 1024) throw std::runtime_error("tile does not fit in LDS");
     lp.fused_ok = 2 * lp.row_lds * 4 <= 160 * 1024;
     lp.rho0 = lp.row.round[0].M / lp.row.round[0].J;
+    // the row kernels exist for first rounds of 2, 4, 8, 3, 6, 12 and 9 values
+    if (lp.row.round[0].kind >= 8 || lp.row.round[0].kind == 3) throw std::runtime_error("no row kernel for this first round");
+}
+
+Geometry geometry_of(const LenPlan &lp) {
+    return Geometry{lp.log2R, lp.W, lp.row_first, lp.row_threads_fixed ? lp.row_threads : 0};
 }
 
 // ---------------------------------------------------------------- tuning
 
 static std::mutex g_tune_mu;
-static std::map<std::pair<uint64_t, int>, std::pair<int, int>> g_tuned;  // (L, class) -> (log2R, W)
-static std::atomic<uint64_t> g_tune_version{1};                       // bumped on every table change
+static std::map<std::pair<uint64_t, int>, Geometry> g_tuned;  // (L, class) -> geometry
+static std::atomic<uint64_t> g_tune_version{1};             // bumped on every table change
 
 uint64_t tune_version() { return g_tune_version.load(std::memory_order_acquire); }
 
-void tuned_geometry(uint64_t L, int cls, int *log2R, int *W) {
+Geometry tuned_geometry(uint64_t L, int cls) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find({L, cls});
-    *log2R = it == g_tuned.end() ? 0 : it->second.first;
-    *W = it == g_tuned.end() ? 0 : it->second.second;
+    return it == g_tuned.end() ? Geometry{} : it->second;
 }
 
-void set_tuned_geometry(uint64_t L, int cls, int log2R, int W) {
+void set_tuned_geometry(uint64_t L, int cls, const Geometry &g) {
     if (cls != 0 && cls != 1) throw std::runtime_error("batch class must be 0 or 1");
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    if (log2R == 0 && W == 0) {
+    if (g == Geometry{}) {
         g_tuned.erase({L, cls});
         g_tune_version.fetch_add(1, std::memory_order_acq_rel);
         return;
     }
     LenPlan lp;
-    plan_geometry(L, log2R, W, lp);  // throws for an invalid geometry
-    g_tuned[{L, cls}] = {lp.log2R, lp.W};
+    plan_geometry(L, g, lp);  // throws for an invalid geometry
+    g_tuned[{L, cls}] = geometry_of(lp);
     g_tune_version.fetch_add(1, std::memory_order_acq_rel);
 }
 
 std::vector<TunedEntry> tuned_entries() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     std::vector<TunedEntry> v;
-    for (auto &e : g_tuned) v.push_back({e.first.first, e.first.second, e.second.first, e.second.second});
+    for (auto &e : g_tuned) v.push_back({e.first.first, e.first.second, e.second});
     return v;
 }
 
-bool find_len_plan(uint64_t L, int log2R_override, int W_override, PlanRef *out) {
+bool find_len_plan(uint64_t L, const Geometry &g, PlanRef *out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return false;
-    LenPlan g;
+    LenPlan lp;
     try {
-        plan_geometry(L, log2R_override, W_override, g);
+        plan_geometry(L, g, lp);
     } catch (const std::exception &) {
         return false;
     }
-    const uint64_t key_len = L | ((uint64_t)g.log2R << 40) | ((uint64_t)g.W << 48);
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_plans.find({dev, key_len});
+    auto it = g_plans.find({dev, L, geometry_of(lp)});
     if (it == g_plans.end()) return false;
     *out = {&it->second->plan, it->second->dplan};
     return true;
 }
 
-PlanRef get_len_plan(uint64_t L, int log2R_override, int W_override) {
+PlanRef get_len_plan(uint64_t L, const Geometry &geo) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) throw std::runtime_error("hipGetDevice failed");
+    Geometry eff;
     {
         // cache on the effective geometry, so an explicit default shares the entry
         LenPlan g;
-        plan_geometry(L, log2R_override, W_override, g);
-        log2R_override = g.log2R;
-        W_override = g.W;
+        plan_geometry(L, geo, g);
+        eff = geometry_of(g);
     }
-    const uint64_t key_len = L | ((uint64_t)log2R_override << 40) | ((uint64_t)W_override << 48);
+    const auto key = std::make_tuple(dev, L, eff);
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_plans.find({dev, key_len});
+    auto it = g_plans.find(key);
     if (it != g_plans.end()) return {&it->second->plan, it->second->dplan};
 
     auto e = std::make_unique<PlanEntry>();
     LenPlan &lp = e->plan;
     XTables ct, rt;
-    plan_geometry(L, log2R_override, W_override, lp, &ct, &rt);
+    plan_geometry(L, eff, lp, &ct, &rt);
     lp.col.fwd_tw = upload(e->tables, ct.fwd);
     lp.col.inv_tw = upload(e->tables, ct.inv);
     lp.row.fwd_tw = upload(e->tables, rt.fwd);
@@ -463,7 +488,7 @@ PlanRef get_len_plan(uint64_t L, int log2R_override, int W_override) {
     e->dplan = (LenPlan *)d;
 
     PlanRef out{&e->plan, e->dplan};
-    g_plans[{dev, key_len}] = std::move(e);
+    g_plans[key] = std::move(e);
     return out;
 }
 

@@ -24,9 +24,30 @@ uint64_t choose_len(uint64_t req);
 
 struct XTables;
 
+// The free choices of a plan (0 = the built-in default): log2 of the row
+// count R, the column tile width W, the radix-2 stages of the row
+// transform's first register round plus one (row_first; the later rounds
+// share the rest evenly), and a fixed row-pass workgroup size (row_threads;
+// 0 lets launches choose by occupancy).  Any choice gives the same bits.
+struct Geometry {
+    int log2R = 0, W = 0, row_first = 0, row_threads = 0;
+    bool operator<(const Geometry &o) const {
+        if (log2R != o.log2R) return log2R < o.log2R;
+        if (W != o.W) return W < o.W;
+        if (row_first != o.row_first) return row_first < o.row_first;
+        return row_threads < o.row_threads;
+    }
+    bool operator==(const Geometry &o) const {
+        return log2R == o.log2R && W == o.W && row_first == o.row_first && row_threads == o.row_threads;
+    }
+};
+
 // Launch geometry of length L without touching the device (throws
 // std::runtime_error for invalid choices); table pointers are left null.
-void plan_geometry(uint64_t L, int log2R, int W, LenPlan &lp, XTables *ct = nullptr, XTables *rt = nullptr);
+void plan_geometry(uint64_t L, const Geometry &g, LenPlan &lp, XTables *ct = nullptr, XTables *rt = nullptr);
+inline void plan_geometry(uint64_t L, int log2R, int W, LenPlan &lp) { plan_geometry(L, Geometry{log2R, W, 0, 0}, lp); }
+// The effective geometry of a plan (defaults resolved).
+Geometry geometry_of(const LenPlan &lp);
 
 // A plan: host copy (for launch geometry) and the device copy the kernels read.
 struct PlanRef {
@@ -34,24 +55,24 @@ struct PlanRef {
     const LenPlan *dev;
 };
 
-// Cached per-device plan for length L; log2R_override > 0 forces R = 2^a,
-// W_override > 0 forces the column tile width.  Throws std::bad_alloc /
-// std::runtime_error on failure.
-PlanRef get_len_plan(uint64_t L, int log2R_override = 0, int W_override = 0);
+// Cached per-device plan for length L in geometry g.  Throws
+// std::bad_alloc / std::runtime_error on failure.
+PlanRef get_len_plan(uint64_t L, const Geometry &g = Geometry{});
 
 // The cached plan of length L in the given geometry on the current device,
 // if one was built earlier; never builds one (no device allocation).
-bool find_len_plan(uint64_t L, int log2R_override, int W_override, PlanRef *out);
+bool find_len_plan(uint64_t L, const Geometry &g, PlanRef *out);
 
 // Tuning table: the geometry used for length L in batch class cls (0: one
-// block per launch, 1: several).  (0, 0) means the built-in default.
-void tuned_geometry(uint64_t L, int cls, int *log2R, int *W);
-// Validates with plan_geometry (throws std::runtime_error if invalid);
-// (0, 0) removes the entry.
-void set_tuned_geometry(uint64_t L, int cls, int log2R, int W);
+// block per launch, 1: several); all zero means the built-in default.
+Geometry tuned_geometry(uint64_t L, int cls);
+// Validates with plan_geometry (throws std::runtime_error if invalid); an
+// all-zero geometry removes the entry.
+void set_tuned_geometry(uint64_t L, int cls, const Geometry &g);
 struct TunedEntry {
     uint64_t L;
-    int cls, log2R, W;
+    int cls;
+    Geometry g;
 };
 std::vector<TunedEntry> tuned_entries();
 // Changes whenever the tuning table does (for caches of plan lookups).

@@ -12,6 +12,7 @@
 
 #include "../../include/pa.h"
 #include "pa_internal.h"
+#include "pa_kernels.h"
 #include "pa_plan.h"
 
 // Early return of a failed status / HIP error (inside pa::rt or with its
@@ -59,6 +60,8 @@ pa_status plan_for(uint64_t L, int cls, PlanRef *lp);
 // The same plan if it is already built on the current device, else
 // PA_ERR_INVALID_ARG; never allocates device memory.
 pa_status plan_cached(uint64_t L, int cls, PlanRef *lp);
+// Reads PA_TUNE_CACHE (once per process) into the tuning table.
+void load_tune_cache_once();
 // Bytes of ceil(bits/64) words.
 double words8(uint64_t bits);
 // Descriptor of a plain-path block with workspace A, S (Shat = S).
@@ -73,7 +76,18 @@ hipError_t p3(const PlanRef &p, const JobArgs &ja, int njobs, double out_bytes, 
 pa_status run_plain(const PlanRef &p, const JobArgs &ja, int njobs, double in_bytes, double out_bytes,
                     hipStream_t s);
 // A validated block array grouped by transform length, with the plans of
-// the groups and the workspace layout (job table, then A and S per block).
+// the groups and the workspace layout: a table region (job descriptors,
+// plans, segment arrays), then A and S per block.
+//
+// Two launch forms:
+//  * lanes: per length group, its own three pass launches (grid.y/z over
+//    the group's blocks), groups spread over concurrent stream lanes;
+//  * flat: per pass, one launch per class of lengths that share a kernel
+//    variant, workgroup size and (without losing occupancy) LDS size; each
+//    launch's grid covers every block of the class (a flat tile list: the
+//    kernels find their block by a search over the launch's segment
+//    array), and the passes follow each other on the caller's stream.
+enum BatchForm { kFormFlat = 0, kFormLanes = 1 };
 struct BatchPrep {
     struct Group {
         uint64_t L = 0;
@@ -81,18 +95,38 @@ struct BatchPrep {
         std::vector<uint32_t> members;  // block indices
         size_t first = 0;               // first table entry (after build_table)
     };
+    struct PassLaunch {
+        int pass = 0;                   // 1, 2, 3
+        int mode = 0;                   // row pass mode
+        pa::FlatLaunch fl{};
+        std::vector<uint32_t> blocks;   // block indices in launch order
+        std::vector<uint32_t> plan_idx; // per block: its plan in the plan array
+        size_t tab_off = 0, seg_off = 0;  // byte offsets in the table region
+        double bytes = 0, ops = 0;      // algorithmic, for the profiler
+    };
     bool modified = false;
+    BatchForm form = kFormFlat;
     std::vector<pa_block> blocks;
+    std::vector<uint64_t> block_len;
     std::vector<Group> groups;
-    std::vector<JobDesc> table;
+    std::vector<PassLaunch> launches;   // flat form, in launch order
+    size_t plans_off = 0;               // flat form: plan array offset
+    std::vector<JobDesc> table;         // lanes form: descriptors in group order
+    std::vector<unsigned char> blob;    // table region contents (after build_table)
     size_t table_bytes = 0, total_bytes = 0;
 };
-pa_status prepare_batch(const pa_block *blocks, uint32_t count, bool modified, BatchPrep *bp);
-// Fills bp.table for workspace `ws` (which must hold bp.total_bytes).
+// Form set by PA_BATCH_FORM ("flat" or "lanes"), else dflt.  Direct calls
+// default to the flat form (fewer launches, measured as fast or faster);
+// captured graphs to the lanes form, whose replay overlaps the passes of
+// different lengths (measured faster on an uneven batch).
+BatchForm batch_form(BatchForm dflt);
+pa_status prepare_batch(const pa_block *blocks, uint32_t count, bool modified, BatchPrep *bp,
+                        BatchForm form);
+// Fills bp.blob (the table region) for workspace `ws` (which must hold
+// bp.total_bytes).
 void build_table(BatchPrep &bp, void *ws);
-// Launches all groups against the device copy of bp.table (lanes forked
-// from and joined back into s).
-pa_status launch_batch(const BatchPrep &bp, const JobDesc *dtable, hipStream_t s);
+// Launches every pass, reading the device copy of bp.blob at ws.
+pa_status launch_batch(const BatchPrep &bp, void *ws, hipStream_t s);
 // Plain (modified = false) or modified Toeplitz over a host array of
 // blocks: validation, grouping by transform length, concurrent lanes.
 pa_status hash_batched(const pa_block *blocks, uint32_t count, hipStream_t s, bool modified);

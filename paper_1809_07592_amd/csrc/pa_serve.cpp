@@ -4,19 +4,30 @@
 // One scheduler thread per server.  Each iteration it (1) retires batches
 // whose completion event has fired, returning their workspace to the pool
 // and waking waiters; (2) admits queued requests in arrival order while the
-// pool can hold their workspace and fewer than max_inflight are running;
-// (3) launches all newly admitted requests as one batched plan-path pass
-// sequence (key column pass, row convolution against the resident seed
-// spectrum, extraction; one launch per pass and transform length, smallest
-// length first) on the next stream.  Each length group completes on its own
-// event, so small requests do not wait for a large one admitted with them.
-// Batches of successive iterations run on different streams, so work
-// admitted while earlier work is on the device overlaps with it.
+// pool can hold their workspace (and, the first time a (seed, length) pair
+// is needed, its spectrum) and fewer than max_inflight are running; (3)
+// starts the spectrum builds the admitted requests need on the server's
+// build stream, without waiting for them; (4) launches all newly admitted
+// requests as one batched plan-path pass sequence (key column pass, row
+// convolution against the resident seed spectrum, extraction; one launch
+// per pass and transform length, smallest length first) on the stream with
+// the least input queued.  A group whose spectrum is still being built
+// waits for its build event on the device, before its row pass only.  Each
+// length group completes on its own event, so small requests do not wait
+// for a large one admitted with them.  Batches of successive iterations run
+// on different streams, so work admitted while earlier work is on the
+// device overlaps with it.
+//
+// Device memory: one pool of the HBM budget holds every request's
+// workspace and every resident spectrum.  Spectra no running request uses
+// are evicted, least recently used first, when the pool cannot admit the
+// next request.
 #include <hip/hip_runtime.h>
 #include <sys/prctl.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -82,6 +93,8 @@ class Pool {
     std::map<uint64_t, uint64_t> free_;
 };
 
+struct Spectrum;
+
 struct Req {
     uint64_t ticket;
     uint32_t seed;
@@ -90,6 +103,8 @@ struct Req {
     uint64_t *out;
     Clock::time_point t_submit, t_done;
     bool done = false;
+    pa_status status = PA_OK;  // of a completed request
+    Spectrum *spec = nullptr;  // admitted: the resident spectrum it uses
 };
 
 // One length group of a batch.  Groups run in order on the batch's stream,
@@ -117,11 +132,21 @@ struct StreamCtx {
     hipEvent_t staged = nullptr;   // after the last copy out of `pinned`
 };
 
-// A resident seed spectrum and the plan (geometry) it was built with; the
-// key passes of a request must use the same geometry.
+// A resident seed spectrum (in the pool) and the plan (geometry) it was
+// built with; the key passes of a request must use the same geometry.
 struct Spectrum {
+    uint32_t seed = 0;
+    const uint64_t *bits = nullptr;  // the seed's bits and their count (copied at admission)
+    uint64_t bits_len = 0;
+    uint64_t L = 0;
     int32_t *S = nullptr;
+    uint64_t off = 0, bytes = 0;   // pool allocation
     pa::PlanRef plan{};
+    hipEvent_t ready = nullptr;    // recorded on the build stream after the build
+    bool built = false;            // the build is known complete
+    bool launched = false;         // the build has been enqueued
+    uint32_t users = 0;            // admitted requests not yet complete
+    uint64_t last_use = 0;         // for least-recently-used eviction
 };
 
 struct Seed {
@@ -141,7 +166,8 @@ struct pa_server_s {
     std::vector<StreamCtx> streams;
     hipStream_t plan_stream = nullptr;
     std::vector<uint64_t> stream_bits;  // input bits queued or running per stream
-    std::vector<Seed> seeds;
+    std::deque<Seed> seeds;             // stable addresses: registered while the scheduler runs
+    uint64_t use_clock = 0;
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -152,41 +178,106 @@ struct pa_server_s {
     bool stop = false;
     std::thread th;
     pa_server_stats st{};
-    std::string error;  // first scheduler failure
+    pa_status drain_status = PA_OK;  // first failure since the last drain
+    std::string drain_error;
 
     std::vector<hipEvent_t> spare_events;  // completion events for reuse
 
     void loop();
     bool retire_locked();
     hipError_t take_event(hipEvent_t *ev);
-    void complete_locked(Req *r, Clock::time_point t, size_t stream);
+    void complete_locked(Req *r, Clock::time_point t, size_t stream, pa_status status);
     pa_status launch(std::vector<Req *> &batch_reqs, Batch *b);
-    pa_status spectrum_for(uint32_t seed, uint64_t L, const Spectrum **out);
+    bool admit_locked(Req *r, std::vector<Spectrum *> *builds);
+    bool evict_one_locked();
+    pa_status build_spectrum(Spectrum *sp);
 };
 
-pa_status pa_server_s::spectrum_for(uint32_t seed, uint64_t L, const Spectrum **out) {
-    Seed &sd = seeds[seed];
-    auto it = sd.spectra.find(L);
-    if (it != sd.spectra.end()) {
-        *out = &it->second;
+// Frees the least recently used spectrum that no admitted request uses and
+// whose build has finished (lock held).  False if there is none.
+bool pa_server_s::evict_one_locked() {
+    Spectrum *best = nullptr;
+    Seed *best_seed = nullptr;
+    for (Seed &sd : seeds)
+        for (auto &kv : sd.spectra) {
+            Spectrum &sp = kv.second;
+            if (sp.users || !sp.launched) continue;
+            if (!sp.built && !sim) {
+                const hipError_t q = hipEventQuery(sp.ready);
+                if (q == hipErrorNotReady) continue;
+                sp.built = true;
+            }
+            if (!best || sp.last_use < best->last_use) {
+                best = &sp;
+                best_seed = &sd;
+            }
+        }
+    if (!best) return false;
+    pool->release(best->off, best->bytes);
+    st.spectrum_bytes -= best->bytes;
+    st.spectra_resident--;
+    st.spectra_evicted++;
+    if (best->ready) spare_events.push_back(best->ready);
+    best_seed->spectra.erase(best->L);
+    return true;
+}
+
+// Admission of the request at the head of the queue (lock held): its
+// workspace and, if the (seed, length) spectrum is not resident, room for
+// the spectrum, evicting unused spectra while that helps.  New spectra are
+// appended to *builds.  False if the pool cannot hold them yet.
+bool pa_server_s::admit_locked(Req *r, std::vector<Spectrum *> *builds) {
+    Seed &sd = seeds[r->seed];
+    auto it = sd.spectra.find(r->L);
+    const bool have = it != sd.spectra.end();
+    const uint64_t sbytes = 4 * r->L;
+    for (;;) {
+        uint64_t off = 0, soff = 0;
+        if (pool->alloc(r->need, &off)) {
+            if (have || pool->alloc(sbytes, &soff)) {
+                r->ws_off = off;
+                Spectrum *sp = nullptr;
+                if (have) {
+                    sp = &it->second;
+                } else {
+                    sp = &sd.spectra[r->L];
+                    sp->seed = r->seed;
+                    sp->bits = sd.bits;
+                    sp->bits_len = sd.len;
+                    sp->L = r->L;
+                    sp->off = soff;
+                    sp->bytes = sbytes;
+                    sp->S = sim ? nullptr : (int32_t *)((char *)pool_base + soff);
+                    st.spectrum_bytes += sbytes;
+                    st.spectra_resident++;
+                    builds->push_back(sp);
+                }
+                sp->users++;
+                sp->last_use = ++use_clock;
+                r->spec = sp;
+                return true;
+            }
+            pool->release(off, r->need);
+        }
+        if (!evict_one_locked()) return false;
+    }
+}
+
+// Enqueues the spectrum build on the build stream and records its event;
+// nothing waits for it here.
+pa_status pa_server_s::build_spectrum(Spectrum *sp) {
+    if (sim) {
+        sp->built = sp->launched = true;
         return PA_OK;
     }
     pa::PlanRef p{};
-    pa_status stt = plan_for(L, 1, &p);
-    if (stt != PA_OK) return stt;
-    int32_t *S = nullptr;
-    hipError_t e = hipMalloc((void **)&S, (size_t)(4 * L));
-    if (e != hipSuccess) return from_hip(e, "spectrum allocation");
-    stt = run_seed_path(p, sd.bits, std::min(sd.len, L), S, plan_stream);
-    if (stt == PA_OK) stt = from_hip(hipStreamSynchronize(plan_stream), "spectrum build");
-    if (stt != PA_OK) {
-        (void)hipFree(S);
-        return stt;
-    }
-    Spectrum &sp = sd.spectra[L];
-    sp.S = S;
-    sp.plan = p;
-    *out = &sp;
+    PA_TRY(plan_for(sp->L, 1, &p));
+    sp->plan = p;
+    PA_TRY(run_seed_path(p, sp->bits, std::min(sp->bits_len, sp->L), sp->S, plan_stream));
+    hipError_t e = take_event(&sp->ready);
+    if (e == hipSuccess) e = hipEventRecord(sp->ready, plan_stream);
+    if (e != hipSuccess) return from_hip(e, "spectrum build event");
+    sp->launched = true;
     return PA_OK;
 }
 
@@ -215,13 +306,8 @@ pa_status pa_server_s::launch(std::vector<Req *> &rs, Batch *b) {
         std::vector<Req *> reqs;
     };
     std::vector<Group> groups;
-    std::vector<std::pair<Req *, const Spectrum *>> order;
-    for (Req *r : rs) {
-        const Spectrum *sp = nullptr;
-        pa_status stt = spectrum_for(r->seed, r->L, &sp);
-        if (stt != PA_OK) return stt;
-        order.push_back({r, sp});
-    }
+    std::vector<std::pair<Req *, Spectrum *>> order;
+    for (Req *r : rs) order.push_back({r, r->spec});
     std::sort(order.begin(), order.end(), [](const auto &a, const auto &c) {
         if (a.first->L != c.first->L) return a.first->L < c.first->L;
         return a.second->plan.host < c.second->plan.host;
@@ -268,6 +354,17 @@ pa_status pa_server_s::launch(std::vector<Req *> &rs, Batch *b) {
             out_b += words8(table[k].m);
         }
         e = p1(p, 1, ja, nj, in_b, sc.s);
+        // a spectrum still being built: the row pass waits for its event
+        for (size_t k = first; k < first + g.count && e == hipSuccess; ++k) {
+            Spectrum *sp = order[k].second;
+            if (sp->built) continue;
+            const hipError_t q = hipEventQuery(sp->ready);
+            if (q == hipSuccess) {
+                sp->built = true;
+                continue;
+            }
+            e = hipStreamWaitEvent(sc.s, sp->ready, 0);
+        }
         if (e == hipSuccess) e = p2(p, 0, ja, nj, sc.s);
         if (e == hipSuccess) e = p3(p, ja, nj, out_b, sc.s);
         Part part;
@@ -288,14 +385,25 @@ pa_status pa_server_s::launch(std::vector<Req *> &rs, Batch *b) {
     return PA_OK;
 }
 
-void pa_server_s::complete_locked(Req *r, Clock::time_point t, size_t stream) {
+void pa_server_s::complete_locked(Req *r, Clock::time_point t, size_t stream, pa_status status) {
     stream_bits[stream] -= r->n;
     r->t_done = t;
     r->done = true;
+    r->status = status;
     pool->release(r->ws_off, r->need);
+    if (r->spec) {
+        r->spec->users--;
+        r->spec->last_use = ++use_clock;
+        r->spec = nullptr;
+    }
     st.completed++;
     st.inflight--;
-    st.input_bits_completed += r->n;
+    if (status == PA_OK) {
+        st.input_bits_completed += r->n;
+    } else {
+        st.failed++;
+        if (drain_status == PA_OK) drain_status = status;
+    }
 }
 
 // Retires finished batches (lock held).  Returns true if any finished.
@@ -306,7 +414,7 @@ bool pa_server_s::retire_locked() {
         Batch &b = running[i];
         if (sim) {
             if (now >= b.sim_done) {
-                for (Req *r : b.reqs) complete_locked(r, now, b.stream);
+                for (Req *r : b.reqs) complete_locked(r, now, b.stream, PA_OK);
                 b.parts_done = b.parts.size();
                 any = true;
             }
@@ -316,12 +424,13 @@ bool pa_server_s::retire_locked() {
                 Part &pt = b.parts[b.parts_done];
                 const hipError_t q = hipEventQuery(pt.ev);
                 if (q == hipErrorNotReady) break;
-                if (q != hipSuccess && error.empty())
-                    // a failed device: complete the part anyway (outputs
-                    // unspecified) so that no waiter blocks for good
-                    error = std::string("completion event: ") + hipGetErrorString(q);
+                // a failed device: complete the part anyway (outputs
+                // unspecified, status PA_ERR_DEVICE) so that no waiter
+                // blocks for good
+                if (q != hipSuccess && drain_error.empty())
+                    drain_error = std::string("completion event: ") + hipGetErrorString(q);
                 const auto t = Clock::now();
-                for (Req *r : pt.reqs) complete_locked(r, t, b.stream);
+                for (Req *r : pt.reqs) complete_locked(r, t, b.stream, q == hipSuccess ? PA_OK : PA_ERR_DEVICE);
                 spare_events.push_back(pt.ev);
                 pt.ev = nullptr;
                 pt.done = true;
@@ -346,15 +455,14 @@ void pa_server_s::loop() {
     (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     for (;;) {
         std::vector<Req *> admitted;
+        std::vector<Spectrum *> builds;
         {
             std::unique_lock<std::mutex> lk(mu);
             if (retire_locked()) cv_done.notify_all();
             if (stop && pending.empty() && running.empty()) break;
             while (!pending.empty() && st.inflight < cfg.max_inflight) {
                 Req *r = pending.front();
-                uint64_t off = 0;
-                if (!pool->alloc(r->need, &off)) break;  // arrival order: wait for memory
-                r->ws_off = off;
+                if (!admit_locked(r, &builds)) break;  // arrival order: wait for memory
                 admitted.push_back(r);
                 pending.pop_front();
                 st.inflight++;
@@ -369,6 +477,11 @@ void pa_server_s::loop() {
                 continue;
             }
         }
+        // start the spectrum builds; the batch's row passes wait for them on
+        // the device, so the scheduler never blocks on a build
+        pa_status bst = PA_OK;
+        for (Spectrum *sp : builds)
+            if (bst == PA_OK) bst = build_spectrum(sp);
         Batch b;
         b.reqs = admitted;
         {
@@ -384,18 +497,25 @@ void pa_server_s::loop() {
             b.sim_done = Clock::now() + std::chrono::microseconds((int64_t)us);
             b.parts.resize(1);
         } else {
-            pa_status stt = launch(b.reqs, &b);
+            pa_status stt = bst != PA_OK ? bst : launch(b.reqs, &b);
             if (stt != PA_OK) {
+                const std::string msg = pa_last_error();
+                // a failed build leaves its spectrum unusable: forget it
+                // once nothing can still be writing it
+                if (bst != PA_OK) (void)hipStreamSynchronize(plan_stream);
                 std::lock_guard<std::mutex> lk(mu);
-                if (error.empty()) error = pa_last_error();
-                // fail the batch: complete its requests (outputs unspecified)
-                for (Req *r : admitted) {
-                    r->done = true;
-                    r->t_done = Clock::now();
-                    pool->release(r->ws_off, r->need);
-                    st.inflight--;
-                    stream_bits[b.stream] -= r->n;
-                }
+                if (drain_error.empty()) drain_error = msg;
+                // fail the batch's requests only (outputs unspecified); the
+                // server keeps serving later requests
+                const auto t = Clock::now();
+                for (Req *r : admitted) complete_locked(r, t, b.stream, stt);
+                for (Spectrum *sp : builds)
+                    if (!sp->launched && sp->users == 0) {
+                        pool->release(sp->off, sp->bytes);
+                        st.spectrum_bytes -= sp->bytes;
+                        st.spectra_resident--;
+                        seeds[sp->seed].spectra.erase(sp->L);
+                    }
                 for (Part &pt : b.parts)
                     if (pt.ev) spare_events.push_back(pt.ev);
                 cv_done.notify_all();
@@ -405,14 +525,31 @@ void pa_server_s::loop() {
         std::lock_guard<std::mutex> lk(mu);
         running.push_back(b);
         st.batches++;
+        st.spectra_built += builds.size();
     }
 }
 
 extern "C" {
 
-pa_status pa_server_create(const pa_server_config *cfg, pa_server_t *server) {
-    if (!cfg || !server) return fail(PA_ERR_INVALID_ARG, "null argument");
+pa_status pa_server_create(const pa_server_config *cfg_in, pa_server_t *server) {
+    if (!cfg_in || !server) return fail(PA_ERR_INVALID_ARG, "null argument");
     *server = nullptr;
+    pa_server_config cfgv = *cfg_in;
+    const pa_server_config *cfg = &cfgv;
+    if (cfgv.hbm_budget_bytes == 0) {
+        // PA_HBM_BUDGET (bytes, or with a K/M/G suffix), else 16 GiB
+        cfgv.hbm_budget_bytes = 16ull << 30;
+        if (const char *v = std::getenv("PA_HBM_BUDGET")) {
+            char *end = nullptr;
+            const double x = std::strtod(v, &end);
+            double mul = 1;
+            if (end && (*end == 'K' || *end == 'k')) mul = 1024.0;
+            if (end && (*end == 'M' || *end == 'm')) mul = 1024.0 * 1024;
+            if (end && (*end == 'G' || *end == 'g')) mul = 1024.0 * 1024 * 1024;
+            if (!(x > 0) || end == v) return fail(PA_ERR_INVALID_ARG, std::string("PA_HBM_BUDGET not a size: ") + v);
+            cfgv.hbm_budget_bytes = (uint64_t)(x * mul);
+        }
+    }
     if (cfg->hbm_budget_bytes < (1u << 20) || cfg->max_inflight == 0 || cfg->max_queue == 0 || cfg->streams == 0 ||
         cfg->streams > 16)
         return fail(PA_ERR_INVALID_ARG, "budget >= 1 MiB, max_inflight, max_queue >= 1, 1 <= streams <= 16");
@@ -466,9 +603,10 @@ pa_status pa_server_submit(pa_server_t s, uint32_t seed_id, const uint64_t *key_
     if (seed_id >= s->seeds.size()) return fail(PA_ERR_INVALID_ARG, "unknown seed id");
     if (n + m - 1 > s->seeds[seed_id].len) return fail(PA_ERR_INVALID_ARG, "seed shorter than n + m - 1");
     const uint64_t need = 4 * L;
-    if ((need + kAlign - 1) / kAlign * kAlign > s->pool->size()) {
+    // its workspace and, when not resident, its seed spectrum (4 L each)
+    if (2 * ((need + kAlign - 1) / kAlign * kAlign) > s->pool->size()) {
         s->st.rejected++;
-        return fail(PA_ERR_BUSY, "request workspace exceeds the whole budget");
+        return fail(PA_ERR_BUSY, "request workspace and seed spectrum exceed the whole budget");
     }
     if (s->pending.size() >= s->cfg.max_queue) {
         s->st.rejected++;
@@ -524,7 +662,9 @@ pa_status pa_server_wait(pa_server_t s, uint64_t ticket, double *latency_us) {
     if (!r) return fail(PA_ERR_INVALID_ARG, "unknown ticket");
     s->cv_done.wait(lk, [&] { return r->done; });
     if (latency_us) *latency_us = std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count();
-    if (!s->error.empty()) return fail(PA_ERR_DEVICE, s->error);
+    if (r->status == PA_ERR_CANCELLED) return fail(PA_ERR_CANCELLED, "request cancelled");
+    if (r->status != PA_OK)
+        return fail(r->status, s->drain_error.empty() ? std::string("request failed") : s->drain_error);
     return PA_OK;
 }
 
@@ -532,7 +672,30 @@ pa_status pa_server_drain(pa_server_t s) {
     if (!s) return fail(PA_ERR_INVALID_ARG, "null server");
     std::unique_lock<std::mutex> lk(s->mu);
     s->cv_done.wait(lk, [&] { return s->pending.empty() && s->running.empty() && s->st.inflight == 0; });
-    if (!s->error.empty()) return fail(PA_ERR_DEVICE, s->error);
+    const pa_status st = s->drain_status;
+    const std::string msg = s->drain_error;
+    s->drain_status = PA_OK;
+    s->drain_error.clear();
+    if (st != PA_OK) return fail(st, msg.empty() ? std::string("a request failed") : msg);
+    return PA_OK;
+}
+
+pa_status pa_server_cancel(pa_server_t s, uint64_t ticket) {
+    if (!s) return fail(PA_ERR_INVALID_ARG, "null server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    Req *r = find_req(s, ticket);
+    if (!r) return fail(PA_ERR_INVALID_ARG, "unknown ticket");
+    if (r->done) return fail(PA_ERR_INVALID_ARG, "request already complete");
+    auto it = std::find(s->pending.begin(), s->pending.end(), r);
+    if (it == s->pending.end()) return fail(PA_ERR_BUSY, "request already admitted to the device; it will complete");
+    s->pending.erase(it);
+    r->done = true;
+    r->status = PA_ERR_CANCELLED;
+    r->t_done = Clock::now();
+    s->st.cancelled++;
+    s->st.pending = s->pending.size();
+    s->cv_done.notify_all();
+    s->cv_work.notify_one();
     return PA_OK;
 }
 
@@ -560,9 +723,11 @@ pa_status pa_server_destroy(pa_server_t s) {
             if (sc.pinned) (void)hipHostFree(sc.pinned);
             if (sc.s) (void)hipStreamDestroy(sc.s);
         }
+        if (s->plan_stream) (void)hipStreamSynchronize(s->plan_stream);
         for (hipEvent_t ev : s->spare_events) (void)hipEventDestroy(ev);
         for (auto &sd : s->seeds)
-            for (auto &kv : sd.spectra) (void)hipFree(kv.second.S);
+            for (auto &kv : sd.spectra)
+                if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
         if (s->plan_stream) (void)hipStreamDestroy(s->plan_stream);
         if (s->pool_base) err = hipFree(s->pool_base);
     }

@@ -7,6 +7,8 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
+#include <mutex>
 #include <fstream>
 #include <sstream>
 #include <string>
@@ -20,21 +22,27 @@ using namespace pa::rt;
 
 namespace {
 
-// A split replaces the default only if it is at least 2% faster.
+// A geometry replaces the default only if it is at least 2% faster.
 constexpr double kKeepDefault = 0.98;
 
+pa::Geometry geo_of(const pa_tune_geometry &g) {
+    return pa::Geometry{(int)g.log2_rows, (int)g.tile_width, (int)g.row_first, (int)g.row_threads};
+}
+
 // Maps host-side geometry errors to statuses.
-pa_status check_geometry(uint64_t L, uint32_t cls, uint32_t a, uint32_t w) {
+pa_status check_geometry(uint64_t L, uint32_t cls, const pa::Geometry &g) {
     if (cls > 1) return fail(PA_ERR_INVALID_ARG, "batch_class must be 0 or 1");
     const auto &lens = pa::supported_lengths();
     if (std::find(lens.begin(), lens.end(), L) == lens.end())
         return fail(PA_ERR_UNSUPPORTED_SIZE, "transform_len " + std::to_string(L) + " is not a supported length");
-    if (a == 0 && w == 0) return PA_OK;
+    if (g == pa::Geometry{}) return PA_OK;
+    if (g.log2R < 0 || g.W < 0 || g.row_first < 0 || g.row_threads < 0)
+        return fail(PA_ERR_INVALID_ARG, "invalid geometry: negative field");
     try {
         pa::LenPlan lp;
-        pa::plan_geometry(L, (int)a, (int)w, lp);
+        pa::plan_geometry(L, g, lp);
     } catch (const std::exception &e) {
-        return fail(PA_ERR_INVALID_ARG, std::string("invalid split: ") + e.what());
+        return fail(PA_ERR_INVALID_ARG, std::string("invalid geometry: ") + e.what());
     }
     return PA_OK;
 }
@@ -54,56 +62,31 @@ struct Events {
     }
 };
 
-}  // namespace
-
-extern "C" {
-
-pa_status pa_tune_set(uint64_t transform_len, uint32_t batch_class, uint32_t log2_rows, uint32_t tile_width) {
-    PA_TRY(check_geometry(transform_len, batch_class, log2_rows, tile_width));
-    try {
-        pa::set_tuned_geometry(transform_len, (int)batch_class, (int)log2_rows, (int)tile_width);
-    } catch (const std::exception &e) {
-        return fail(PA_ERR_INVALID_ARG, e.what());
-    }
-    return PA_OK;
+// Architecture name of the current device (the tuning file's key beside
+// the length), e.g. "gfx950"; "unknown" without a device.
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    if (c != std::string::npos) a.resize(c);
+    return a.empty() ? "unknown" : a;
 }
 
-pa_status pa_tune_get(uint64_t transform_len, uint32_t batch_class, uint32_t *log2_rows, uint32_t *tile_width) {
-    if (!log2_rows || !tile_width) return fail(PA_ERR_INVALID_ARG, "null out-pointer");
-    PA_TRY(check_geometry(transform_len, batch_class, 0, 0));
-    int a = 0, w = 0;
-    pa::tuned_geometry(transform_len, (int)batch_class, &a, &w);
-    pa::LenPlan lp;
-    try {
-        pa::plan_geometry(transform_len, a, w, lp);
-    } catch (const std::exception &e) {
-        return fail(PA_ERR_INVALID_ARG, e.what());
-    }
-    *log2_rows = (uint32_t)lp.log2R;
-    *tile_width = (uint32_t)lp.W;
-    return PA_OK;
-}
+struct Row {
+    uint64_t L;
+    uint32_t cls;
+    pa::Geometry g;
+    std::string arch;  // empty: any
+};
 
-pa_status pa_tune_save(const char *path) {
-    if (!path) return fail(PA_ERR_INVALID_ARG, "null path");
-    std::ofstream f(path);
-    if (!f) return fail(PA_ERR_INVALID_ARG, std::string("cannot write ") + path);
-    f << "# transform_len batch_class log2_rows tile_width\n";
-    for (const auto &e : pa::tuned_entries()) f << e.L << ' ' << e.cls << ' ' << e.log2R << ' ' << e.W << '\n';
-    f.flush();
-    if (!f) return fail(PA_ERR_INVALID_ARG, std::string("write failed: ") + path);
-    return PA_OK;
-}
-
-pa_status pa_tune_load(const char *path) {
-    if (!path) return fail(PA_ERR_INVALID_ARG, "null path");
+// Parses a tuning file: "L class log2_rows tile_width [row_first
+// row_threads [arch]]" per line, '#' comments.  Every line is validated
+// (geometry errors only for rows of this arch) before anything is used.
+pa_status parse_file(const char *path, std::vector<Row> *rows, const std::string &arch) {
     std::ifstream f(path);
     if (!f) return fail(PA_ERR_INVALID_ARG, std::string("cannot read ") + path);
-    struct Row {
-        uint64_t L;
-        uint32_t cls, a, w;
-    };
-    std::vector<Row> rows;
     std::string line;
     int ln = 0;
     while (std::getline(f, line)) {
@@ -112,15 +95,140 @@ pa_status pa_tune_load(const char *path) {
         if (h != std::string::npos) line.resize(h);
         if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
         std::istringstream is(line);
-        long long L, cls, a, w;
-        std::string extra;
-        if (!(is >> L >> cls >> a >> w) || (is >> extra) || L <= 0 || cls < 0 || a < 0 || w < 0)
-            return fail(PA_ERR_INVALID_ARG, std::string(path) + ":" + std::to_string(ln) + ": expected 4 integers");
-        pa_status st = check_geometry((uint64_t)L, (uint32_t)cls, (uint32_t)a, (uint32_t)w);
-        if (st != PA_OK) return fail(st, std::string(path) + ":" + std::to_string(ln) + ": " + pa_last_error());
-        rows.push_back({(uint64_t)L, (uint32_t)cls, (uint32_t)a, (uint32_t)w});
+        std::vector<std::string> tok;
+        for (std::string t; is >> t;) tok.push_back(t);
+        if (tok.size() != 4 && tok.size() != 6 && tok.size() != 7)
+            return fail(PA_ERR_INVALID_ARG, std::string(path) + ":" + std::to_string(ln) +
+                                                ": expected 4 or 6 integers and an optional arch name");
+        long long v[6] = {0, 0, 0, 0, 0, 0};
+        const size_t nint = tok.size() == 7 ? 6 : tok.size();
+        for (size_t i = 0; i < nint; ++i) {
+            char *end = nullptr;
+            v[i] = std::strtoll(tok[i].c_str(), &end, 10);
+            if (!end || *end || v[i] < 0)
+                return fail(PA_ERR_INVALID_ARG, std::string(path) + ":" + std::to_string(ln) + ": bad integer '" +
+                                                    tok[i] + "'");
+        }
+        Row r{(uint64_t)v[0], (uint32_t)v[1], pa::Geometry{(int)v[2], (int)v[3], (int)v[4], (int)v[5]},
+              tok.size() == 7 ? tok[6] : std::string()};
+        if (r.arch.empty() || r.arch == arch) {
+            pa_status st = check_geometry(r.L, r.cls, r.g);
+            if (st != PA_OK) return fail(st, std::string(path) + ":" + std::to_string(ln) + ": " + pa_last_error());
+        }
+        rows->push_back(r);
     }
-    for (const Row &r : rows) pa::set_tuned_geometry(r.L, (int)r.cls, (int)r.a, (int)r.w);
+    return PA_OK;
+}
+
+// Writes the current table for `arch` (one line per entry) and keeps the
+// other architectures' lines of an existing file; replaces the file whole.
+pa_status write_file(const char *path, const std::string &arch, bool keep_others) {
+    std::vector<Row> others;
+    if (keep_others) {
+        std::vector<Row> old;
+        std::ifstream probe(path);
+        if (probe && parse_file(path, &old, arch) == PA_OK)
+            for (const Row &r : old)
+                if (!r.arch.empty() && r.arch != arch) others.push_back(r);
+    }
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp);
+        if (!f) return fail(PA_ERR_INVALID_ARG, std::string("cannot write ") + tmp);
+        f << "# transform_len batch_class log2_rows tile_width row_first row_threads arch\n";
+        for (const auto &e : pa::tuned_entries())
+            f << e.L << ' ' << e.cls << ' ' << e.g.log2R << ' ' << e.g.W << ' ' << e.g.row_first << ' '
+              << e.g.row_threads << ' ' << arch << '\n';
+        for (const Row &r : others)
+            f << r.L << ' ' << r.cls << ' ' << r.g.log2R << ' ' << r.g.W << ' ' << r.g.row_first << ' '
+              << r.g.row_threads << ' ' << r.arch << '\n';
+        f.flush();
+        if (!f) return fail(PA_ERR_INVALID_ARG, std::string("write failed: ") + tmp);
+    }
+    if (std::rename(tmp.c_str(), path) != 0) return fail(PA_ERR_INVALID_ARG, std::string("cannot replace ") + path);
+    return PA_OK;
+}
+
+}  // namespace
+
+namespace pa {
+namespace rt {
+
+// PA_TUNE_CACHE: read once per process, on the first plan lookup, the rows
+// of the current device's architecture (a missing file is not an error).
+void load_tune_cache_once() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const char *path = std::getenv("PA_TUNE_CACHE");
+        if (!path || !*path) return;
+        std::ifstream probe(path);
+        if (!probe) return;
+        const std::string arch = device_arch();
+        std::vector<Row> rows;
+        if (parse_file(path, &rows, arch) != PA_OK) return;
+        for (const Row &r : rows)
+            if (r.arch.empty() || r.arch == arch) pa::set_tuned_geometry(r.L, (int)r.cls, r.g);
+    });
+}
+
+}  // namespace rt
+}  // namespace pa
+
+extern "C" {
+
+pa_status pa_tune_set(uint64_t transform_len, uint32_t batch_class, uint32_t log2_rows, uint32_t tile_width) {
+    const pa_tune_geometry g{log2_rows, tile_width, 0, 0};
+    return pa_tune_set_geometry(transform_len, batch_class, &g);
+}
+
+pa_status pa_tune_set_geometry(uint64_t transform_len, uint32_t batch_class, const pa_tune_geometry *g) {
+    if (!g) return fail(PA_ERR_INVALID_ARG, "null geometry");
+    PA_TRY(check_geometry(transform_len, batch_class, geo_of(*g)));
+    try {
+        pa::set_tuned_geometry(transform_len, (int)batch_class, geo_of(*g));
+    } catch (const std::exception &e) {
+        return fail(PA_ERR_INVALID_ARG, e.what());
+    }
+    return PA_OK;
+}
+
+pa_status pa_tune_get_geometry(uint64_t transform_len, uint32_t batch_class, pa_tune_geometry *g) {
+    if (!g) return fail(PA_ERR_INVALID_ARG, "null out-pointer");
+    PA_TRY(check_geometry(transform_len, batch_class, pa::Geometry{}));
+    pa::LenPlan lp;
+    try {
+        pa::plan_geometry(transform_len, pa::tuned_geometry(transform_len, (int)batch_class), lp);
+    } catch (const std::exception &e) {
+        return fail(PA_ERR_INVALID_ARG, e.what());
+    }
+    g->log2_rows = (uint32_t)lp.log2R;
+    g->tile_width = (uint32_t)lp.W;
+    g->row_first = (uint32_t)lp.row_first;
+    g->row_threads = lp.row_threads_fixed ? (uint32_t)lp.row_threads : 0u;
+    return PA_OK;
+}
+
+pa_status pa_tune_get(uint64_t transform_len, uint32_t batch_class, uint32_t *log2_rows, uint32_t *tile_width) {
+    if (!log2_rows || !tile_width) return fail(PA_ERR_INVALID_ARG, "null out-pointer");
+    pa_tune_geometry g{};
+    PA_TRY(pa_tune_get_geometry(transform_len, batch_class, &g));
+    *log2_rows = g.log2_rows;
+    *tile_width = g.tile_width;
+    return PA_OK;
+}
+
+pa_status pa_tune_save(const char *path) {
+    if (!path) return fail(PA_ERR_INVALID_ARG, "null path");
+    return write_file(path, device_arch(), false);
+}
+
+pa_status pa_tune_load(const char *path) {
+    if (!path) return fail(PA_ERR_INVALID_ARG, "null path");
+    const std::string arch = device_arch();
+    std::vector<Row> rows;
+    PA_TRY(parse_file(path, &rows, arch));
+    for (const Row &r : rows)
+        if (r.arch.empty() || r.arch == arch) pa::set_tuned_geometry(r.L, (int)r.cls, r.g);
     return PA_OK;
 }
 
@@ -129,7 +237,7 @@ pa_status pa_autotune(uint64_t transform_len, uint32_t count, uint32_t reps, voi
     if (count == 0 || count > 65535 || reps == 0 || reps > 1000)
         return fail(PA_ERR_INVALID_ARG, "count in [1, 65535] and reps in [1, 1000] required");
     const uint64_t L = transform_len;
-    PA_TRY(check_geometry(L, 0, 0, 0));
+    PA_TRY(check_geometry(L, 0, pa::Geometry{}));
     hipStream_t s = (hipStream_t)stream;
     // Largest block with n = 4m whose required length fits L (m a multiple of 64).
     const uint64_t m = std::max<uint64_t>(64, L / 320 * 64), n = 4 * m;
@@ -163,10 +271,10 @@ pa_status pa_autotune(uint64_t transform_len, uint32_t count, uint32_t reps, voi
     Events ev;
     PA_HIP(hipEventCreate(&ev.a), "event");
     PA_HIP(hipEventCreate(&ev.b), "event");
-    auto time_split = [&](int a, int w, double *us) -> pa_status {
+    auto time_geo = [&](const pa::Geometry &g, double *us) -> pa_status {
         pa::PlanRef p{};
         try {
-            p = pa::get_len_plan(L, a, w);
+            p = pa::get_len_plan(L, g);
         } catch (const std::bad_alloc &) {
             return fail(PA_ERR_OUT_OF_MEMORY, "allocating transform tables");
         } catch (const std::exception &e) {
@@ -187,40 +295,69 @@ pa_status pa_autotune(uint64_t transform_len, uint32_t count, uint32_t reps, voi
         *us = t[t.size() / 2];
         return PA_OK;
     };
+    auto valid = [&](const pa::Geometry &g, pa::LenPlan *lp) {
+        try {
+            pa::plan_geometry(L, g, *lp);
+            return true;
+        } catch (const std::exception &) {
+            return false;
+        }
+    };
 
     pa::LenPlan def;
-    pa::plan_geometry(L, 0, 0, def);
+    pa::plan_geometry(L, pa::Geometry{}, def);
+    const pa::Geometry defg = pa::geometry_of(def);
     pa_tune_result r{};
     r.count = count;
     r.best_us = 1e300;
-    for (int a = 1; a <= 10; ++a)
-        for (int w : {16, 32, 64}) {
-            pa::LenPlan lp;
-            try {
-                pa::plan_geometry(L, a, w, lp);
-            } catch (const std::exception &) {
-                continue;
-            }
-            double us = 0;
-            PA_TRY(time_split(a, w, &us));
-            ++r.candidates;
-            if (a == def.log2R && w == def.W) r.default_us = us;
-            if (us < r.best_us) {
-                r.best_us = us;
-                r.log2_rows = (uint32_t)a;
-                r.tile_width = (uint32_t)w;
-            }
+    pa::Geometry best{};
+    auto consider = [&](const pa::Geometry &g) -> pa_status {
+        pa::LenPlan lp;
+        if (!valid(g, &lp)) return PA_OK;
+        double us = 0;
+        PA_TRY(time_geo(g, &us));
+        ++r.candidates;
+        if (pa::geometry_of(lp) == defg) r.default_us = us;
+        if (us < r.best_us) {
+            r.best_us = us;
+            best = pa::geometry_of(lp);
         }
+        return PA_OK;
+    };
+    // 1. every four-step split (R, W) with the default rounds
+    for (int a = 1; a <= 10; ++a)
+        for (int w : {16, 32, 64}) PA_TRY(consider(pa::Geometry{a, w, 0, 0}));
     if (r.candidates == 0) return fail(PA_ERR_UNSUPPORTED_SIZE, "no valid split");
-    // keep the default unless a split beats it clearly (timing noise would
-    // otherwise flip between near-equal splits from run to run)
+    // 2. the row transform's first-round split at the best (R, W)
+    const pa::Geometry split = best;
+    for (int f = 1; f <= 4; ++f) {
+        pa::Geometry g = split;
+        g.row_first = f;
+        pa::LenPlan lp;
+        if (valid(g, &lp) && !(pa::geometry_of(lp).row_first == split.row_first)) PA_TRY(consider(g));
+    }
+    // 3. fixed row workgroup sizes at the best so far
+    const pa::Geometry rounds = best;
+    for (int t : {256, 512, 768, 1024}) {
+        pa::Geometry g = rounds;
+        g.row_threads = t;
+        PA_TRY(consider(g));
+    }
+    // keep the default unless another geometry beats it clearly (timing
+    // noise would otherwise flip between near-equal ones from run to run)
     if (r.default_us > 0 && r.best_us > kKeepDefault * r.default_us) {
         r.best_us = r.default_us;
-        r.log2_rows = (uint32_t)def.log2R;
-        r.tile_width = (uint32_t)def.W;
+        best = defg;
     }
-    pa::set_tuned_geometry(L, count > 1 ? 1 : 0, (int)r.log2_rows, (int)r.tile_width);
+    r.log2_rows = (uint32_t)best.log2R;
+    r.tile_width = (uint32_t)best.W;
+    r.row_first = (uint32_t)best.row_first;
+    r.row_threads = (uint32_t)best.row_threads;
+    pa::set_tuned_geometry(L, count > 1 ? 1 : 0, best == defg ? pa::Geometry{} : best);
     *result = r;
+    // PA_TUNE_CACHE: keep the table for later processes on this architecture
+    if (const char *path = std::getenv("PA_TUNE_CACHE"))
+        if (*path) PA_TRY(write_file(path, device_arch(), true));
     return PA_OK;
 }
 

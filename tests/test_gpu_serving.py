@@ -86,3 +86,41 @@ def test_small_request_does_not_wait_for_a_large_one():
     for _, _, kb, ks, ob, os_ in pairs:
         assert torch.equal(ob, pa.toeplitz_hash(kb, n_big, dseed, m_big))
         assert torch.equal(os_, pa.toeplitz_hash(ks, n_small, dseed, m_small))
+
+
+def test_spectra_built_on_demand_evicted_and_rebuilt_under_a_small_budget():
+    """A budget that holds few spectra: every (seed, length) pair is built
+    on first use on the server's build stream (requests wait on the device,
+    not the scheduler), unused spectra are evicted and rebuilt when needed
+    again, and seeds registered while requests run are served too.  Every
+    result equals the same request run alone."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    n_seeds = 6
+    seeds = [wl.random_bits(1_500_000, wl.rng(33, wl.ROLE_SEED, i)) for i in range(n_seeds)]
+    dseeds = [dev(sd) for sd in seeds]
+    g = np.random.default_rng(34)
+    with pa.Server(48 << 20, max_inflight=32, streams=3) as srv:
+        ids = [srv.register_seed(dseeds[k], 1_500_000) for k in range(3)]
+        reqs, outs, keys = [], [], []
+        for i in range(90):
+            if i == 30:   # registered while earlier requests are on the device
+                ids += [srv.register_seed(dseeds[k], 1_500_000) for k in range(3, n_seeds)]
+            sid = int(g.integers(0, len(ids)))
+            n = int(round(10 ** g.uniform(4.5, 6.0)))
+            m = max(1, min(n, int(round(n * g.uniform(0.1, 0.5)))))
+            key = dev(wl.random_bits(n, wl.rng(33, wl.ROLE_KEY, i)))
+            out = torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")
+            keys.append(key)
+            outs.append(out)
+            reqs.append((sid, n, m, srv.submit(ids[sid], key, n, m, out)))
+        srv.drain()
+        st = srv.stats()
+        assert st["completed"] == 90 and st["failed"] == 0
+        assert st["spectra_evicted"] > 0 and st["spectra_built"] > st["spectra_resident"]
+        assert st["peak_bytes_in_flight"] <= 48 << 20
+    torch.cuda.synchronize()
+    for (sid, n, m, _), key, out in zip(reqs, keys, outs):
+        alone = pa.toeplitz_hash(key, n, dseeds[sid], m)
+        torch.cuda.synchronize()
+        assert torch.equal(out[: wl.words(m)], alone[: wl.words(m)]), (sid, n, m)

@@ -75,8 +75,11 @@ def test_autotune_installs_a_valid_split(count):
     L = pa.transform_len(N, M)
     r = pa.autotune(L, count=count, reps=2)
     cls = 0 if count == 1 else 1
-    assert r["candidates"] == len(valid_splits(L))
-    assert pa.tune_get(L, cls) == (r["log2_rows"], r["tile_width"])
+    # every split, then row round splits and row workgroup sizes
+    assert r["candidates"] >= len(valid_splits(L)) + 4
+    g = pa.tune_get_geometry(L, cls)
+    assert (g["log2_rows"], g["tile_width"], g["row_first"], g["row_threads"]) == (
+        r["log2_rows"], r["tile_width"], r["row_first"], r["row_threads"])
     assert 0 < r["best_us"] <= r["default_us"]
     key, seed = wl.key_and_seed(42, N, M, count)
     got = host(pa.toeplitz_hash(dev(key), N, dev(seed), M), M)
@@ -119,3 +122,58 @@ def test_plan_and_server_keep_their_geometry_across_a_table_change():
         srv.drain()
     for i in range(6):
         assert np.array_equal(host(outs[i], M), want[i]), i
+
+
+@pytest.mark.parametrize("n,m", [(100_003, 25_001), (600_001, 150_001)])
+def test_every_row_split_and_row_workgroup_size_gives_the_same_bits(n, m):
+    # 100,003 bits: rows of 2^k columns (first round 2, 4 or 8 values);
+    # 600,001 bits: rows with a radix-3 stage (first round 3, 6 or 12 values)
+    key, seed = wl.key_and_seed(44, n, m, 0)
+    want = oracle.toeplitz_hash(key, n, seed, m)
+    L = pa.transform_len(n, m)
+    a, w = pa.tune_get(L, 0)
+    dk, ds = dev(key), dev(seed)
+    tried = 0
+    for rf in range(0, 5):
+        for rt in (0, 256, 512, 768, 1024):
+            try:
+                pa.tune_set(L, 0, a, w, row_first=rf, row_threads=rt)
+            except pa.PAError:
+                continue
+            tried += 1
+            got = host(pa.toeplitz_hash(dk, n, ds, m), m)
+            assert np.array_equal(got, want), (rf, rt)
+    assert tried >= 12
+    pa.tune_set(L, 0, 0, 0)
+
+
+def test_tune_cache_file_is_written_and_read(tmp_path):
+    import subprocess
+    import sys
+    L = pa.transform_len(N, M)
+    path = str(tmp_path / "cache.txt")
+    pa.tune_set(L, 1, 0, 0)
+    import os
+    old = os.environ.get("PA_TUNE_CACHE")
+    os.environ["PA_TUNE_CACHE"] = path
+    try:
+        pa.autotune(L, count=2, reps=1)
+    finally:
+        if old is None:
+            os.environ.pop("PA_TUNE_CACHE", None)
+        else:
+            os.environ["PA_TUNE_CACHE"] = old
+    rows = [ln.split() for ln in open(path) if not ln.startswith("#")]
+    assert rows and all(len(r) == 7 and r[6].startswith("gfx") for r in rows)
+    # write a distinctive geometry for class 1 into the cache and read it
+    # back in a fresh process, whose first hash loads the file
+    with open(path, "w") as f:
+        f.write("%d 1 7 32 0 512 %s\n" % (L, rows[0][6]))
+    code = ("import numpy as np, torch, paper_1809_07592_amd as pa\n"
+            "k = torch.zeros(%d, dtype=torch.int64, device='cuda'); s = torch.zeros(%d, dtype=torch.int64, device='cuda')\n"
+            "pa.toeplitz_hash(k, %d, s, %d); torch.cuda.synchronize()\n"
+            "print(pa.tune_get_geometry(%d, 1))\n" % ((N + 63) // 64, (N + M + 62) // 64, N, M, L))
+    env = dict(os.environ, PA_TUNE_CACHE=path)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert "'log2_rows': 7, 'tile_width': 32, 'row_first': 0, 'row_threads': 512" in out.stdout

@@ -2,9 +2,13 @@
 
 The native scheduler runs unchanged; only the executor is replaced by one
 that completes a batch after n / rate microseconds without touching the
-device.  Checks: every request completes, the HBM budget and the in-flight
-limit are never exceeded, oversize and overflow submissions are refused,
-admission continues while earlier work is running (continuous batching).
+device (seed spectra take pool memory but are not built).  Checks: every
+request completes, the HBM budget (workspace and resident spectra) and
+the in-flight limit are never exceeded, unused spectra are evicted when
+the pool needs room, oversize and overflow submissions are refused,
+admission continues while earlier work is running (continuous batching),
+queued requests can be cancelled, seeds can be registered while requests
+run, and the budget can come from PA_HBM_BUDGET.
 """
 import pytest
 
@@ -27,7 +31,7 @@ def ws(n, m):
 
 
 def test_all_complete_within_budget_and_inflight_limit():
-    budget = 64 << 20
+    budget = 160 << 20
     with pa.Server(budget, max_inflight=6, executor=pa.EXEC_SIMULATED, sim_bits_per_us=2e5) as s:
         sid = s.register_seed(FAKE_SEED, 20_000_000)
         shapes = [(int(1e5 * 1.37 ** (i % 15)), 0) for i in range(200)]
@@ -40,17 +44,20 @@ def test_all_complete_within_budget_and_inflight_limit():
         assert st["submitted"] == st["completed"] == 200 and st["rejected"] == 0
         assert st["peak_bytes_in_flight"] <= st["budget_bytes"] <= budget
         assert 1 <= st["peak_inflight"] <= 6
-        assert st["inflight"] == 0 and st["bytes_in_flight"] == 0 and st["pending"] == 0
+        # after the drain only resident seed spectra hold pool memory
+        assert st["inflight"] == 0 and st["pending"] == 0
+        assert st["bytes_in_flight"] == st["spectrum_bytes"] > 0
         assert st["batches"] >= 200 / 6
         for t in tickets:
             assert s.poll(t) and s.latency_us(t) >= 0
 
 
 def test_memory_bound_admission_overlaps_work():
-    # budget fits three of these blocks: later arrivals are admitted as
-    # earlier ones finish, while others are still running
+    # budget fits the seed spectrum and three of these blocks: later
+    # arrivals are admitted as earlier ones finish, while others are still
+    # running
     n, m = 1_000_000, 250_000
-    budget = 3 * ws(n, m) + 4096
+    budget = 4 * ws(n, m) + 4096
     with pa.Server(budget, max_inflight=64, executor=pa.EXEC_SIMULATED, sim_bits_per_us=1e4) as s:
         sid = s.register_seed(FAKE_SEED, n + m)
         ts = [s.submit(sid, FAKE_KEY, n, m, FAKE_OUT) for _ in range(12)]
@@ -59,6 +66,7 @@ def test_memory_bound_admission_overlaps_work():
         assert st["completed"] == 12
         assert st["peak_inflight"] == 3
         assert st["peak_bytes_in_flight"] <= budget
+        assert st["spectra_resident"] == 1 and st["spectrum_bytes"] == ws(n, m) and st["spectra_built"] == 1
         assert st["batches"] >= 4
         lat = sorted(s.latency_us(t) for t in ts)
         assert lat[-1] > lat[0]
@@ -96,3 +104,85 @@ def test_bad_configs():
         args.update(kw)
         with pytest.raises(pa.PAError):
             pa.Server(**args)
+
+
+def test_unused_spectra_are_evicted_when_the_pool_needs_room():
+    # room for one spectrum and one workspace: each request on another seed
+    # evicts the previous seed's spectrum, which no request uses any more
+    n, m = 500_000, 100_000
+    budget = 2 * ws(n, m) + 4096
+    with pa.Server(budget, max_inflight=8, executor=pa.EXEC_SIMULATED, sim_bits_per_us=1e5) as s:
+        sids = [s.register_seed(FAKE_SEED + 0x1000 * i, n + m) for i in range(4)]
+        for i in range(12):
+            s.submit(sids[i % 4], FAKE_KEY, n, m, FAKE_OUT)
+        s.drain()
+        st = s.stats()
+        assert st["completed"] == 12 and st["failed"] == 0
+        assert st["spectra_built"] == 12 and st["spectra_evicted"] == 11 and st["spectra_resident"] == 1
+        assert st["peak_bytes_in_flight"] <= budget and st["peak_inflight"] == 1
+        assert st["bytes_in_flight"] == st["spectrum_bytes"] == ws(n, m)
+
+
+def test_cancel_a_queued_request():
+    with pa.Server(8 << 20, max_inflight=1, executor=pa.EXEC_SIMULATED, sim_bits_per_us=1.0) as s:
+        sid = s.register_seed(FAKE_SEED, 5_000_000)
+        first = s.submit(sid, FAKE_KEY, 100_000, 10, FAKE_OUT)     # runs for about 0.1 s
+        queued = [s.submit(sid, FAKE_KEY, 100_000, 10, FAKE_OUT) for _ in range(3)]
+        import time
+        time.sleep(0.02)
+        with pytest.raises(pa.PAError) as e:
+            s.cancel(first)                                         # already on the device
+        assert e.value.status == pa.PA_ERR_BUSY
+        s.cancel(queued[1])
+        assert s.poll(queued[1])
+        with pytest.raises(pa.PAError) as e:
+            s.wait(queued[1])
+        assert e.value.status == pa.PA_ERR_CANCELLED
+        with pytest.raises(pa.PAError) as e:
+            s.cancel(queued[1])                                     # already complete
+        assert e.value.status == pa.PA_ERR_INVALID_ARG
+        s.drain()
+        st = s.stats()
+        assert st["cancelled"] == 1 and st["completed"] == 3 and st["submitted"] == 4
+        for t in (first, queued[0], queued[2]):
+            s.wait(t)
+
+
+def test_seeds_registered_while_requests_run():
+    import threading
+    with pa.Server(256 << 20, max_inflight=16, executor=pa.EXEC_SIMULATED, sim_bits_per_us=5e4) as s:
+        sids = [s.register_seed(FAKE_SEED, 3_000_000)]
+        errors = []
+
+        def register_more():
+            try:
+                for i in range(200):
+                    sids.append(s.register_seed(FAKE_SEED + 0x100 * (i + 1), 3_000_000))
+            except Exception as exc:  # surfaced below
+                errors.append(exc)
+
+        th = threading.Thread(target=register_more)
+        th.start()
+        tickets = []
+        for i in range(400):
+            sid = sids[i % len(sids)]
+            n = 100_000 + 7_919 * (i % 50)
+            tickets.append(s.submit(sid, FAKE_KEY, n, n // 4, FAKE_OUT))
+        th.join()
+        s.drain()
+        assert not errors
+        st = s.stats()
+        assert st["completed"] == 400 and st["failed"] == 0 and len(sids) == 201
+        assert st["peak_bytes_in_flight"] <= st["budget_bytes"]
+
+
+def test_budget_from_environment(monkeypatch):
+    monkeypatch.setenv("PA_HBM_BUDGET", "48M")
+    with pa.Server(0, executor=pa.EXEC_SIMULATED) as s:
+        assert s.stats()["budget_bytes"] == 48 << 20
+    monkeypatch.setenv("PA_HBM_BUDGET", "lots")
+    with pytest.raises(pa.PAError):
+        pa.Server(0, executor=pa.EXEC_SIMULATED)
+    monkeypatch.delenv("PA_HBM_BUDGET")
+    with pa.Server(0, executor=pa.EXEC_SIMULATED) as s:
+        assert s.stats()["budget_bytes"] == 16 << 30

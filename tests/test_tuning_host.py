@@ -84,3 +84,43 @@ def test_load_rejects_bad_file_atomically(tmp_path):
         pa.tune_load(path)
     with pytest.raises(pa.PAError):
         pa.tune_load(os.path.join(str(tmp_path), "missing.txt"))
+
+
+def test_full_geometry_set_get_and_validation():
+    # 6144-column rows (L = 3 * 2^19, R = 256): the first round can take 0, 1
+    # or 2 radix-2 stages after its radix-3 stage (3, 6 or 12 values)
+    pa.tune_set(L, 0, 8, 16, row_first=2, row_threads=1024)
+    g = pa.tune_get_geometry(L, 0)
+    assert g == {"log2_rows": 8, "tile_width": 16, "row_first": 2, "row_threads": 1024}
+    info = pa.plan_info(L, 8, 16)
+    assert info["row_round_size"][0] == 12       # the default first round
+    for bad in (dict(row_first=4), dict(row_threads=300), dict(row_threads=2048)):
+        with pytest.raises(pa.PAError) as ei:
+            pa.tune_set(L, 0, 8, 16, **bad)
+        assert ei.value.status == pa.PA_ERR_INVALID_ARG
+    assert pa.tune_get_geometry(L, 0)["row_threads"] == 1024    # unchanged by the failures
+    pa.tune_set(L, 0, 0, 0)
+    assert pa.tune_get_geometry(L, 0)["row_first"] == 0
+
+
+def test_save_load_keeps_full_geometry_and_filters_by_architecture(tmp_path):
+    pa.tune_set(L, 1, 9, 32, row_first=1, row_threads=512)
+    path = str(tmp_path / "tune.txt")
+    pa.tune_save(path)
+    lines = [ln.split() for ln in open(path) if not ln.startswith("#")]
+    assert any(ln[:6] == [str(L), "1", "9", "32", "1", "512"] and len(ln) == 7 for ln in lines)
+    arch = [ln for ln in lines if ln[0] == str(L)][0][6]
+    pa.tune_set(L, 1, 0, 0)
+    # a line for another architecture is kept in the file but not installed
+    with open(path, "a") as f:
+        f.write("%d 0 10 16 0 0 gfx000\n" % L)
+    pa.tune_load(path)
+    assert pa.tune_get_geometry(L, 1) == {"log2_rows": 9, "tile_width": 32, "row_first": 1, "row_threads": 512}
+    assert pa.tune_get(L, 0) != (10, 16)
+    # a bad line of this architecture fails the whole load
+    with open(path, "a") as f:
+        f.write("%d 0 8 16 9 0 %s\n" % (L, arch))
+    pa.tune_set(L, 1, 0, 0)
+    with pytest.raises(pa.PAError):
+        pa.tune_load(path)
+    assert pa.tune_get_geometry(L, 1)["row_first"] == 0

@@ -153,18 +153,21 @@ def test_tune_cache_file_is_written_and_read(tmp_path):
     L = pa.transform_len(N, M)
     path = str(tmp_path / "cache.txt")
     pa.tune_set(L, 1, 0, 0)
+    pa.tune_set(2**20, 0, 9, 32)   # an entry the file must carry (autotune may keep the default)
     import os
     old = os.environ.get("PA_TUNE_CACHE")
     os.environ["PA_TUNE_CACHE"] = path
     try:
         pa.autotune(L, count=2, reps=1)
     finally:
+        pa.tune_set(2**20, 0, 0, 0)
         if old is None:
             os.environ.pop("PA_TUNE_CACHE", None)
         else:
             os.environ["PA_TUNE_CACHE"] = old
     rows = [ln.split() for ln in open(path) if not ln.startswith("#")]
-    assert rows and all(len(r) == 7 and r[6].startswith("gfx") for r in rows)
+    assert any(r[:6] == [str(2**20), "0", "9", "32", "0", "0"] for r in rows)
+    assert all(len(r) == 7 and r[6].startswith("gfx") for r in rows)
     # write a distinctive geometry for class 1 into the cache and read it
     # back in a fresh process, whose first hash loads the file
     with open(path, "w") as f:

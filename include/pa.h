@@ -221,6 +221,28 @@ uint64_t pa_plan_transform_len(pa_plan_t plan);
  * still in flight. */
 pa_status pa_plan_destroy(pa_plan_t plan);
 
+/*
+ * Diagnostics of the transform itself, for testing the kernels below the
+ * hash (the convolution theorem of Sec. 2.3, Eq. (4), checked directly):
+ *
+ * pa_cyclic_convolution: out[k] = sum_j a[j] * b[(k - j) mod L] for
+ *   0 <= k < L = transform_len, with a the na bits of a_bits and b the nb
+ *   bits of b_bits (1 <= na, nb <= L; padding bits ignored), computed by
+ *   the hash's own passes (forward column pass of both, row pass, inverse
+ *   column pass) with the inverse pass storing every canonical residue
+ *   instead of the packed parity window.  The values are exact integers in
+ *   [0, min(na, nb)].  out: L int32, device.  Uses the stream's workspace.
+ *   PA_ERR_UNSUPPORTED_SIZE for an unsupported length.
+ * pa_plan_spectrum: copies the plan's resident seed spectrum to out (L
+ *   int32, device, stream-ordered): the length-L number-theoretic
+ *   transform of the seed's first min(seed_len_bits, L) bits, values
+ *   reduced to |v| <= P/2 + 4 (P = 27*2^20 + 1), in the transform's own
+ *   (digit-reversed) order.
+ */
+pa_status pa_cyclic_convolution(const uint64_t *a_bits, uint64_t na, const uint64_t *b_bits, uint64_t nb,
+                                uint64_t transform_len, int32_t *out, void *stream);
+pa_status pa_plan_spectrum(pa_plan_t plan, int32_t *out, void *stream);
+
 /* Smallest supported transform length for (n, m); 0 if unsupported or
  * invalid.  Pure host function. */
 uint64_t pa_transform_len(uint64_t n, uint64_t m);

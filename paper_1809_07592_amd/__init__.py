@@ -138,6 +138,10 @@ def lib():
                 L.pa_alu_probe.restype = st
                 L.pa_final_key_length.argtypes = [u64, u64, u64]
                 L.pa_final_key_length.restype = u64
+                L.pa_cyclic_convolution.argtypes = [vp, u64, vp, u64, u64, vp, vp]
+                L.pa_cyclic_convolution.restype = st
+                L.pa_plan_spectrum.argtypes = [vp, vp, vp]
+                L.pa_plan_spectrum.restype = st
                 L.pa_tune_set_geometry.argtypes = [u64, u32, ctypes.POINTER(TuneGeometry)]
                 L.pa_tune_set_geometry.restype = st
                 L.pa_tune_get_geometry.argtypes = [u64, u32, ctypes.POINTER(TuneGeometry)]
@@ -369,6 +373,20 @@ def toeplitz_hash_noalloc(key, n: int, seed, m: int, out, stream=None):
 NOALLOC_SCRATCH_BYTES = 113246208
 
 
+def cyclic_convolution(a, na: int, b, nb: int, transform_len: int, out=None, stream=None):
+    """pa_cyclic_convolution: the exact length-L cyclic convolution of two
+    bit strings (int32 tensor of L values), computed by the hash's passes."""
+    import torch
+    L = int(transform_len)
+    if out is None:
+        out = torch.empty(L, dtype=torch.int32, device=a.device)
+    if not out.is_cuda or out.dtype != torch.int32 or not out.is_contiguous() or out.numel() < L:
+        raise ValueError("out must be a contiguous int32 device tensor of transform_len values")
+    _check(lib().pa_cyclic_convolution(_ptr(a, words(na), "a"), int(na), _ptr(b, words(nb), "b"), int(nb), L,
+                                       out.data_ptr(), _stream_handle(stream)))
+    return out
+
+
 def toeplitz_hash_batched(blocks, stream=None):
     """blocks: sequence of (key, n, seed, m, out) tuples; returns the outs."""
     arr = _blocks(blocks, lambda n, m: (n + m + 62) >> 6)
@@ -493,6 +511,18 @@ class Plan:
             out = torch.empty(max(words(m), 1), dtype=torch.int64, device=key.device)
         _check(lib().pa_plan_hash(self._h, _ptr(key, words(n), "key"), int(n), int(m),
                                   _ptr(out, words(m), "out"), _stream_handle(stream)))
+        return out
+
+    def spectrum(self, out=None, stream=None):
+        """The resident seed spectrum (int32 tensor of transform_len values,
+        reduced residues in transform order)."""
+        import torch
+        L = self.transform_len
+        if out is None:
+            out = torch.empty(L, dtype=torch.int32, device="cuda")
+        if not out.is_cuda or out.dtype != torch.int32 or not out.is_contiguous() or out.numel() < L:
+            raise ValueError("out must be a contiguous int32 device tensor of transform_len values")
+        _check(lib().pa_plan_spectrum(self._h, out.data_ptr(), _stream_handle(stream)))
         return out
 
     def destroy(self):

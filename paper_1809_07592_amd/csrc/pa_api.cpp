@@ -996,6 +996,45 @@ pa_status pa_plan_hash(pa_plan_t plan, const uint64_t *key_bits, uint64_t n, uin
     return run_key_path(plan->lp, key_bits, n, m, plan->Shat, (int32_t *)ws, out_bits, (hipStream_t)stream);
 }
 
+pa_status pa_plan_spectrum(pa_plan_t plan, int32_t *out, void *stream) {
+    if (!plan || !out) return fail(PA_ERR_INVALID_ARG, "null argument");
+    int dev = 0;
+    PA_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != plan->device) return fail(PA_ERR_INVALID_ARG, "plan belongs to another device");
+    PA_HIP(hipMemcpyAsync(out, plan->Shat, (size_t)(4 * plan->L), hipMemcpyDeviceToDevice, (hipStream_t)stream),
+           "spectrum copy");
+    return PA_OK;
+}
+
+pa_status pa_cyclic_convolution(const uint64_t *a_bits, uint64_t na, const uint64_t *b_bits, uint64_t nb,
+                                uint64_t transform_len, int32_t *out, void *stream) {
+    if (!a_bits || !b_bits || !out) return fail(PA_ERR_INVALID_ARG, "null pointer");
+    const uint64_t L = transform_len;
+    const auto &lens = pa::supported_lengths();
+    if (std::find(lens.begin(), lens.end(), L) == lens.end())
+        return fail(PA_ERR_UNSUPPORTED_SIZE, "transform_len " + std::to_string(L) + " is not a supported length");
+    if (na == 0 || nb == 0 || na > L || nb > L) return fail(PA_ERR_INVALID_ARG, "need 1 <= na, nb <= transform_len");
+    hipStream_t s = (hipStream_t)stream;
+    pa::PlanRef p{};
+    PA_TRY(plan_for(L, 0, &p));
+    void *ws = nullptr;
+    PA_TRY(get_workspace(s, (size_t)(8 * L), &ws));
+    pa::JobArgs ja{};
+    pa::JobDesc &j = ja.one;
+    j.key = a_bits;
+    j.n = (uint32_t)na;
+    j.shift = 0;
+    j.seed = b_bits;
+    j.seed_bits = (uint32_t)nb;
+    j.m = 1;
+    j.off0 = 0;
+    j.A = (int32_t *)ws;
+    j.S = (int32_t *)ws + L;
+    j.Shat = j.S;
+    j.res_out = out;
+    return run_plain(p, ja, 1, words8(na) + words8(nb), 4.0 * (double)L, s);
+}
+
 pa_status pa_plan_destroy(pa_plan_t plan) {
     if (!plan) return PA_OK;
     hipError_t e = plan->Shat ? hipFree(plan->Shat) : hipSuccess;

@@ -137,6 +137,7 @@ struct JobDesc {
     uint32_t key_off;      // source 0 starts at this bit of `key` (modified Toeplitz: m)
     const uint64_t *xor_src;  // non-null: P3 XORs output bit i with bit i of this array
     uint32_t plan_idx;     // flat launches: index of the job's plan in the launch's plan array
+    int32_t *res_out;      // non-null (diagnostics): P3 stores all L canonical residues here instead of bits
 };
 
 // Jobs of a launch: either one descriptor passed inline in the kernel

@@ -516,6 +516,7 @@ __device__ __forceinline__ JobDesc job_of(const JobArgs &ja, unsigned idx) {
     j.shift = uni(j.shift);
     j.key_off = uni(j.key_off);
     j.xor_src = uni(j.xor_src);
+    j.res_out = uni(j.res_out);
     return j;
 }
 
@@ -832,7 +833,17 @@ __global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan
     };
     // Every wave runs whole iterations of the item loop (items and blockDim
     // are multiples of 64), so each ballot sees all 64 lanes.
+    // diagnostic jobs (job.res_out set): every position's canonical residue,
+    // i.e. the exact cyclic convolution, instead of the packed parity window
+    const bool res_mode = job.res_out != nullptr;
+    const rsrc_t rbuf = make_rsrc(job.res_out, res_mode ? (uint32_t)(lp.L * 4) : 0u);
     auto store_bits = [&](NoCtx, auto &v, Geo g) PA_INLINE {
+        if (res_mode) {
+#pragma unroll
+            for (int l = 0; l < group_size(v); ++l)
+                st32(rbuf, ((g.q0 + (l * g.J)) * C + c0 + g.c) * 4, (int)canonical(v[l]));
+            return;
+        }
         uint32_t par = 0;  // parity of the exact convolution values of this group
 #pragma unroll
         for (int l = 0; l < group_size(v); ++l) par |= ((uint32_t)(int)canonical(v[l]) & 1u) << l;

@@ -270,3 +270,21 @@ def test_geometry_overrides(lib):
         pa.plan_info(3 * 2**19, log2_rows=16)
     with pytest.raises(pa.PAError):
         pa.plan_info(12345)
+
+
+@pytest.mark.parametrize("a,na,b,nb,L,out,status", [
+    (None, 10, FAKE, 10, 4096, FAKE, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 10, None, 10, 4096, FAKE, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 10, FAKE, 10, 4096, None, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 0, FAKE, 10, 4096, FAKE, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 4097, FAKE, 10, 4096, FAKE, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 10, FAKE, 4097, 4096, FAKE, pa.PA_ERR_INVALID_ARG),
+    (FAKE, 10, FAKE, 10, 5000, FAKE, pa.PA_ERR_UNSUPPORTED_SIZE),
+])
+def test_cyclic_convolution_rejects_before_device_work(lib, a, na, b, nb, L, out, status):
+    assert lib.pa_cyclic_convolution(a, na, b, nb, L, out, None) == status
+    assert len(pa.last_error()) > 0
+
+
+def test_plan_spectrum_rejects_null(lib):
+    assert lib.pa_plan_spectrum(None, FAKE, None) == pa.PA_ERR_INVALID_ARG

@@ -414,6 +414,44 @@ def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30, streams=4
             "latency": "completion minus scheduled Poisson arrival (open loop)"}
 
 
+def only_run(pa, wl, torch, np, args):
+    """One workload, for profilers: the same inputs, autotuning and launch
+    form as the full run, --steps timed steps after --warmup."""
+    stream = torch.cuda.current_stream()
+    if args.only in ("plain", "batched", "large"):
+        n, m = (12_800_000, 1_280_000) if args.only == "large" else (N_BITS, M_BITS)
+        count = args.batch if args.only == "batched" else 1
+        L = pa.transform_len(n, m)
+        if not args.no_tune:
+            pa.autotune(L, count=count, reps=3 if count > 1 else 20, stream=stream)
+        cfg = {"plain": 2, "batched": 4, "large": 3}[args.only]
+        blocks = []
+        for i in range(count):
+            k, s_ = wl.key_and_seed(cfg, n, m, i)
+            blocks.append((torch.from_numpy(k.view(np.int64)).cuda(), n, torch.from_numpy(s_.view(np.int64)).cuda(),
+                           m, torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")))
+        if count == 1:
+            b = blocks[0]
+            step = lambda: pa.toeplitz_hash(b[0], n, b[2], m, b[4], stream=stream)
+        else:
+            step = lambda: pa.toeplitz_hash_batched(blocks, stream=stream)
+        geo = pa.tune_get_geometry(L, 0 if count == 1 else 1)
+        bits = n * count
+    else:
+        shapes = wl.batched_shapes(args.batch, 4)
+        blocks = []
+        for i, sh in enumerate(shapes):
+            k, s_ = wl.key_and_seed(8, sh.n, sh.m, i)
+            blocks.append((torch.from_numpy(k.view(np.int64)).cuda(), sh.n, torch.from_numpy(s_.view(np.int64)).cuda(),
+                           sh.m, torch.zeros(wl.words(sh.m), dtype=torch.int64, device="cuda")))
+        step = lambda: pa.toeplitz_hash_batched(blocks, stream=stream)
+        geo = {"lengths": len({pa.transform_len(sh.n, sh.m) for sh in shapes})}
+        bits = sum(sh.n for sh in shapes)
+    ms, _ = time_steps(step, args.steps, args.warmup, torch)
+    print(json.dumps({"only": args.only, "ms_per_step": ms, "Gbs": bits / (ms * 1e-3) / 1e9, "geometry": geo,
+                      "steps": args.steps, "kernel_source_hash": kernel_source_hash()}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -424,6 +462,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in default splits")
     ap.add_argument("--serving", type=int, default=10000, help="requests in the serving run (0: skip)")
     ap.add_argument("--load", type=float, default=0.7, help="offered load as a fraction of saturated capacity")
+    ap.add_argument("--only", choices=["plain", "batched", "large", "uneven"],
+                    help="run one workload for --steps steps (after the same untimed autotuning as the full "
+                         "run) and print its time and geometry: for profiling runs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -451,6 +492,9 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written": b.numel() * 4}))
         return
     pa.lib()  # fails loudly if the HIP library is missing
+    if args.only:
+        only_run(pa, wl, torch, np, args)
+        return
     n, m = N_BITS, M_BITS
     key, seed = wl.key_and_seed(2, n, m, 0)
     dk = torch.from_numpy(key.view(np.int64)).cuda()

@@ -776,7 +776,8 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
 // Grid: (tiles, jobs) with plan[0] the launch's plan, or, in a flat
 // launch, one dimension covering every job's tiles, each with its own plan,
 // plan[job.plan_idx].
-template <int MAXLG>
+// RES: the diagnostic form (job.res_out set), which stores every residue.
+template <int MAXLG, bool RES>
 __global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan,
                                                                                        JobArgs ja) {
     uint32_t jidx, tile;
@@ -835,10 +836,9 @@ __global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan
     // are multiples of 64), so each ballot sees all 64 lanes.
     // diagnostic jobs (job.res_out set): every position's canonical residue,
     // i.e. the exact cyclic convolution, instead of the packed parity window
-    const bool res_mode = job.res_out != nullptr;
-    const rsrc_t rbuf = make_rsrc(job.res_out, res_mode ? (uint32_t)(lp.L * 4) : 0u);
+    const rsrc_t rbuf = make_rsrc(job.res_out, RES ? (uint32_t)(lp.L * 4) : 0u);
     auto store_bits = [&](NoCtx, auto &v, Geo g) PA_INLINE {
-        if (res_mode) {
+        if constexpr (RES) {
 #pragma unroll
             for (int l = 0; l < group_size(v); ++l)
                 st32(rbuf, ((g.q0 + (l * g.J)) * C + c0 + g.c) * 4, (int)canonical(v[l]));
@@ -903,7 +903,8 @@ static hipError_t set_lds_limits(int *limit) {
                              (const void *)k_rowconv<4>, (const void *)k_rowconv<5>, (const void *)k_rowconv<6>,
                              (const void *)k_rowconv<7>, (const void *)k_colfwd<3, false>, (const void *)k_colfwd<4, false>,
                              (const void *)k_colfwd<3, true>, (const void *)k_colfwd<4, true>,
-                             (const void *)k_colinv<3>, (const void *)k_colinv<4>};
+                             (const void *)k_colinv<3, false>, (const void *)k_colinv<4, false>,
+                             (const void *)k_colinv<3, true>, (const void *)k_colinv<4, true>};
         for (const void *f : fns) {
             e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
             if (e != hipSuccess) return e;
@@ -1098,10 +1099,15 @@ hipError_t launch_rowconv_flat(const FlatLaunch &fl, const LenPlan *plans, int m
 static hipError_t colinv_launch(bool lg3, dim3 grid, int threads, size_t lds, const LenPlan *dp, const JobArgs &ja,
                                 hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 block((unsigned)threads);
-    if (lg3)
-        hipExtLaunchKernelGGL(k_colinv<3>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja);
-    else
-        hipExtLaunchKernelGGL(k_colinv<4>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja);
+    // the residue-storing form only for a single diagnostic job
+    const bool res = !ja.table && ja.one.res_out;
+#define PA_CI(LG, R) hipExtLaunchKernelGGL((k_colinv<LG, R>), grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja)
+    if (lg3) {
+        if (res) PA_CI(3, true); else PA_CI(3, false);
+    } else {
+        if (res) PA_CI(4, true); else PA_CI(4, false);
+    }
+#undef PA_CI
     return hipGetLastError();
 }
 
@@ -1135,7 +1141,7 @@ int col_wgs_per_cu(bool inverse, int lg, int threads, size_t lds) {
     int &rc = regs_cache[inverse ? 1 : 0][lg];
     if (rc == 0) {
         hipFuncAttributes a{};
-        const void *fn = inverse ? (lg == 3 ? (const void *)k_colinv<3> : (const void *)k_colinv<4>)
+        const void *fn = inverse ? (lg == 3 ? (const void *)k_colinv<3, false> : (const void *)k_colinv<4, false>)
                                  : (lg == 3 ? (const void *)k_colfwd<3, false> : (const void *)k_colfwd<4, false>);
         if (hipFuncGetAttributes(&a, fn) != hipSuccess) return 0;
         rc = a.numRegs > 0 ? a.numRegs : 128;

@@ -69,9 +69,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str):
-    """HBM bytes per launch from committed rocprofv3 PMC runs, if they were
-    taken on the current kernel source (else None)."""
+def load_traffic(kernel: str, workload: str = "plain"):
+    """Measured bytes per launch leaving the L2 (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE, calibrated by a copy) for one pass of a profiled workload
+    ("plain", "batched" or "large"), if the counters were taken on the
+    current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
@@ -82,8 +84,25 @@ def load_traffic(kernel: str):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    k = d.get("kernels", {}).get(kernel)
+    k = d.get("workloads", {}).get(workload, {}).get("kernels", {}).get(kernel)
     return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def kernel_figures(prof: dict, workload: str) -> dict:
+    """Per-pass figures from the library's profiler (HIP events recorded by
+    each launch on its stream): average duration, algorithmic bytes and fp64
+    operations per launch, and their fractions of the HBM and fp64 peaks."""
+    out = {}
+    for name, st in prof.items():
+        avg_s = st["avg_ms"] * 1e-3
+        b = st["alg_bytes"] / st["launches"]
+        o = st["alg_ops"] / st["launches"]
+        t = load_traffic(name, workload)
+        out[name] = {"avg_us": st["avg_ms"] * 1e3, "launches": st["launches"], "alg_bytes_per_launch": b,
+                     "alg_ops_per_launch": o, "hbm_GBs": b / avg_s / 1e9, "hbm_frac": b / avg_s / 1e9 / HBM_PEAK_GBS,
+                     "fp64_Tops": o / avg_s / 1e12, "alu_frac": o / avg_s / 1e12 / FP64_VALU_PEAK_TOPS,
+                     "traffic": t, "traffic_over_alg": None if t is None else t / b}
+    return out
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -229,11 +248,20 @@ def large_block_run(pa, wl, torch, np, stream, steps, tune):
     dk = torch.from_numpy(k.view(np.int64)).cuda()
     ds = torch.from_numpy(s.view(np.int64)).cuda()
     out = torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")
-    ms, _ = time_steps(lambda: pa.toeplitz_hash(dk, n, ds, m, out, stream=stream), steps, 3, torch)
+    step = lambda: pa.toeplitz_hash(dk, n, ds, m, out, stream=stream)
+    ms, _ = time_steps(step, steps, 3, torch)
+    pa.profile_collect()
+    pa.profile_enable(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    prof = pa.profile_collect()
+    pa.profile_enable(False)
     L = pa.transform_len(n, m)
     g = pa.plan_info(L, *pa.tune_get(L, 0))
     res = {"value": n / (ms * 1e-3) / 1e9, "unit": "Gb/s", "ms_per_block": ms, "n": n, "m": m, "transform_len": L,
-           "rows": g["rows"], "cols": g["cols"], "row_round_size": g["row_round_size"]}
+           "rows": g["rows"], "cols": g["cols"], "row_round_size": g["row_round_size"],
+           "kernels": kernel_figures(prof, "large")}
     return res, (k, s, n, m, out.cpu().numpy().view(np.uint64)[: wl.words(m)].copy())
 
 
@@ -528,19 +556,13 @@ def main():
     torch.cuda.synchronize()
     prof = pa.profile_collect()
     pa.profile_enable(False)
-    kernels = {}
+    kernels = kernel_figures(prof, "plain")
     for name, st in prof.items():
-        avg_s = st["avg_ms"] * 1e-3
-        b = st["alg_bytes"] / st["launches"]
-        o = st["alg_ops"] / st["launches"]
-        kernels[name] = {"avg_us": st["avg_ms"] * 1e3, "alg_bytes_per_launch": b, "alg_ops_per_launch": o,
-                         "hbm_GBs": b / avg_s / 1e9, "hbm_frac": b / avg_s / 1e9 / HBM_PEAK_GBS,
-                         "fp64_Tops": o / avg_s / 1e12, "alu_frac": o / avg_s / 1e12 / FP64_VALU_PEAK_TOPS,
-                         "share_of_step": st["total_ms"] / st["launches"] / ms}
+        kernels[name]["share_of_step"] = st["total_ms"] / st["launches"] / ms
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
     kd = kernels[dom]
     bound = "alu" if kd["alu_frac"] >= kd["hbm_frac"] else "hbm"
-    traffic = load_traffic(dom)
+    traffic = kd["traffic"]
     if bound == "alu":
         roofline = {"bound": "alu", "kernel": dom, "achieved": kd["fp64_Tops"], "peak": FP64_VALU_PEAK_TOPS,
                     "unit": "Tops/s (fp64 FMA/add)", "frac": kd["alu_frac"], "traffic": traffic}
@@ -581,12 +603,7 @@ def main():
         torch.cuda.synchronize()
         bprof = pa.profile_collect()
         pa.profile_enable(False)
-        bk = {}
-        for name, st in bprof.items():
-            avg_s = st["avg_ms"] * 1e-3
-            bk[name] = {"avg_us": st["avg_ms"] * 1e3,
-                        "hbm_frac": st["alg_bytes"] / st["launches"] / avg_s / 1e9 / HBM_PEAK_GBS,
-                        "alu_frac": st["alg_ops"] / st["launches"] / avg_s / 1e12 / FP64_VALU_PEAK_TOPS}
+        bk = kernel_figures(bprof, "batched")
         batched = {"value": args.batch * n / (bms * 1e-3) / 1e9, "unit": "Gb/s", "blocks": args.batch,
                    "ms_per_batch": bms, "kernels": bk,
                    "speedup_vs_plain": args.batch * n / (bms * 1e-3) / 1e9 / value,

@@ -319,8 +319,10 @@ size_t pa_workspace_bytes(uint64_t n, uint64_t m);
  *   (installed only on a device of that architecture); it validates every
  *   line before installing any (PA_ERR_INVALID_ARG with the line number
  *   otherwise).
- * PA_TUNE_CACHE: read once per process, on the first hash call, with the
- *   rules of pa_tune_load (a missing or invalid file is ignored).
+ * PA_TUNE_CACHE: read once per process, before the first hash or tuning
+ *   call, with the rules of pa_tune_load (a missing or invalid file is
+ *   ignored); settings made through these calls afterwards take precedence,
+ *   and an autotune's write keeps the file's other rows.
  */
 typedef struct pa_tune_geometry {
     uint32_t log2_rows;

@@ -154,7 +154,8 @@ pa_status write_file(const char *path, const std::string &arch, bool keep_others
 namespace pa {
 namespace rt {
 
-// PA_TUNE_CACHE: read once per process, on the first plan lookup, the rows
+// PA_TUNE_CACHE: read once per process, before the first plan lookup or
+// tuning call (so later explicit settings win over it), the rows
 // of the current device's architecture (a missing file is not an error).
 void load_tune_cache_once() {
     static std::once_flag once;
@@ -183,6 +184,7 @@ pa_status pa_tune_set(uint64_t transform_len, uint32_t batch_class, uint32_t log
 
 pa_status pa_tune_set_geometry(uint64_t transform_len, uint32_t batch_class, const pa_tune_geometry *g) {
     if (!g) return fail(PA_ERR_INVALID_ARG, "null geometry");
+    pa::rt::load_tune_cache_once();
     PA_TRY(check_geometry(transform_len, batch_class, geo_of(*g)));
     try {
         pa::set_tuned_geometry(transform_len, (int)batch_class, geo_of(*g));
@@ -194,6 +196,7 @@ pa_status pa_tune_set_geometry(uint64_t transform_len, uint32_t batch_class, con
 
 pa_status pa_tune_get_geometry(uint64_t transform_len, uint32_t batch_class, pa_tune_geometry *g) {
     if (!g) return fail(PA_ERR_INVALID_ARG, "null out-pointer");
+    pa::rt::load_tune_cache_once();
     PA_TRY(check_geometry(transform_len, batch_class, pa::Geometry{}));
     pa::LenPlan lp;
     try {
@@ -219,11 +222,13 @@ pa_status pa_tune_get(uint64_t transform_len, uint32_t batch_class, uint32_t *lo
 
 pa_status pa_tune_save(const char *path) {
     if (!path) return fail(PA_ERR_INVALID_ARG, "null path");
+    pa::rt::load_tune_cache_once();
     return write_file(path, device_arch(), false);
 }
 
 pa_status pa_tune_load(const char *path) {
     if (!path) return fail(PA_ERR_INVALID_ARG, "null path");
+    pa::rt::load_tune_cache_once();
     const std::string arch = device_arch();
     std::vector<Row> rows;
     PA_TRY(parse_file(path, &rows, arch));
@@ -238,6 +243,7 @@ pa_status pa_autotune(uint64_t transform_len, uint32_t count, uint32_t reps, voi
         return fail(PA_ERR_INVALID_ARG, "count in [1, 65535] and reps in [1, 1000] required");
     const uint64_t L = transform_len;
     PA_TRY(check_geometry(L, 0, pa::Geometry{}));
+    pa::rt::load_tune_cache_once();
     hipStream_t s = (hipStream_t)stream;
     // Largest block with n = 4m whose required length fits L (m a multiple of 64).
     const uint64_t m = std::max<uint64_t>(64, L / 320 * 64), n = 4 * m;

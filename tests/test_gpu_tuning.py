@@ -180,3 +180,30 @@ def test_tune_cache_file_is_written_and_read(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr[-2000:]
     assert "'log2_rows': 7, 'tile_width': 32, 'row_first': 0, 'row_threads': 512" in out.stdout
+
+
+def test_tune_cache_is_read_before_queries_and_kept_by_autotune(tmp_path):
+    # a fresh process: a query before any hash already sees the file's row,
+    # a setting made afterwards wins over the file, and an autotune of
+    # another length rewrites the file with the rows it did not tune
+    import os
+    import subprocess
+    import sys
+    L = pa.transform_len(N, M)
+    path = str(tmp_path / "cache.txt")
+    with open(path, "w") as f:
+        f.write("%d 1 7 32 0 512 gfx950\n%d 0 9 32 0 0 gfx950\n" % (L, 2**20))
+    code = ("import paper_1809_07592_amd as pa\n"
+            "print('q', pa.tune_get_geometry(%d, 1))\n"
+            "pa.tune_set(%d, 0, 8, 16)\n"
+            "print('s', pa.tune_get_geometry(%d, 0))\n"
+            "pa.autotune(%d, count=1, reps=1)\n" % (L, 2**20, 2**20, 2**12))
+    env = dict(os.environ, PA_TUNE_CACHE=path)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert "q {'log2_rows': 7, 'tile_width': 32, 'row_first': 0, 'row_threads': 512}" in out.stdout
+    assert "s {'log2_rows': 8, 'tile_width': 16," in out.stdout
+    rows = [ln.split()[:6] for ln in open(path) if not ln.startswith("#")]
+    assert [str(L), "1", "7", "32", "0", "512"] in rows
+    assert [str(2**20), "0", "8", "16", "0", "0"] in rows
+    assert any(r[0] == str(2**12) for r in rows) or len(rows) == 2

@@ -205,22 +205,59 @@ using RegArrN = double[NA][(N3 == 0 ? 1 : N3 == 1 ? 3 : N3 == 2 ? 9 : 27) << N2]
 // the round's first stage most significant.  Memory position:
 // b*M + lin*J_last + jj.
 
+// Twiddle sources of a round's stages.  TwDirect loads each stage's
+// factors as the stage starts (wave-uniform indices become scalar loads);
+// TwRegs holds factors that the round loaded together before its data, so
+// that per-lane table loads (blocks or positions that differ across a wave)
+// are in flight together instead of one stage after another.  A stage asks
+// for entry t of the table and passes i, its compile-time slot in TwRegs.
+struct TwDirect {
+    const ctwpair *tw;
+    __device__ __forceinline__ double2 operator()(int t, int) const { return ld_const(tw, t); }
+};
+template <int NT>
+struct TwRegs {
+    double2 w[NT > 0 ? NT : 1];
+    __device__ __forceinline__ double2 operator()(int, int i) const { return w[i]; }
+};
+
+// Slots: forward stage K holds before(K) * (r - 1) factors, inverse stage K
+// after(K) * (r - 1); forward slots in stage order, inverse slots in the
+// order the stages run (K = Q-1 first).
+template <int N3, int N2>
+struct TwSlots {
+    using S = Shape<N3, N2>;
+    static constexpr int fbase(int K) {
+        int s = 0;
+        for (int k = 0; k < K; ++k) s += S::before(k) * (S::radix(k) - 1);
+        return s;
+    }
+    static constexpr int ibase(int K) {
+        int s = 0;
+        for (int k = S::Q - 1; k > K; --k) s += S::after(k) * (S::radix(k) - 1);
+        return s;
+    }
+    static constexpr int F = fbase(S::Q), I = ibase(-1);
+};
+
 // Forward Cooley-Tukey stage K of a round: block index b_full = b*before+sb,
 // input u multiplied by gamma^u (table entry), then r-point DFT.
 // NA arrays (NA = 2: the seed and key rows of the fused row pass) share
 // each stage's twiddles.  TRIV: the transform's first stage, whose one
 // block has gamma = 1, so its inputs enter the DFT unmultiplied (they are
 // reduced residues or bits, within the bound a product would give).
-template <int N3, int N2, int K, int NA, bool TRIV = false>
-__device__ __forceinline__ void fwd_stage(RegArrN<N3, N2, NA> &v, int b, const ctwpair *tw, int off) {
+template <int N3, int N2, int K, int NA, bool TRIV = false, class TW>
+__device__ __forceinline__ void fwd_stage(RegArrN<N3, N2, NA> &v, int b, const TW &tw, int off) {
     using S = Shape<N3, N2>;
     constexpr int r = S::radix(K), rb = S::before(K), ra = S::after(K);
+    constexpr int slot = TwSlots<N3, N2>::fbase(K);
     static_assert(!TRIV || rb == 1, "only the first stage has a single block");
 #pragma unroll
     for (int sb = 0; sb < rb; ++sb) {
         const int t = off + (b * rb + sb) * (r - 1);
+        const int i = slot + sb * (r - 1);
         if constexpr (r == 2) {
-            const double2 w = TRIV ? make_double2(1.0, 0.0) : ld_const(tw, t);
+            const double2 w = TRIV ? make_double2(1.0, 0.0) : tw(t, i);
 #pragma unroll
             for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -232,7 +269,7 @@ __device__ __forceinline__ void fwd_stage(RegArrN<N3, N2, NA> &v, int b, const c
                     v[a][i1] = y - mm;
                 }
         } else {
-            const double2 w1 = TRIV ? make_double2(1.0, 0.0) : ld_const(tw, t), w2 = TRIV ? make_double2(1.0, 0.0) : ld_const(tw, t + 1);
+            const double2 w1 = TRIV ? make_double2(1.0, 0.0) : tw(t, i), w2 = TRIV ? make_double2(1.0, 0.0) : tw(t + 1, i + 1);
 #pragma unroll
             for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -254,17 +291,18 @@ __device__ __forceinline__ void fwd_stage(RegArrN<N3, N2, NA> &v, int b, const c
 // inverse DFT multiplied by omega_M^(-j' i), j' = x*J_last + jj.  TRIV: the
 // transform's last stage (inverted first), whose sub-blocks have length 1,
 // so j' = 0 and the factor is 1; its inputs are reduced residues.
-template <int N3, int N2, int K, bool TRIV = false>
-__device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, const ctwpair *tw,
-                                          int off) {
+template <int N3, int N2, int K, bool TRIV = false, class TW>
+__device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, const TW &tw, int off) {
     using S = Shape<N3, N2>;
     constexpr int r = S::radix(K), rb = S::before(K), ra = S::after(K);
+    constexpr int slot = TwSlots<N3, N2>::ibase(K);
     static_assert(!TRIV || ra == 1, "only the last stage has unit sub-blocks");
 #pragma unroll
     for (int x = 0; x < ra; ++x) {
         const int t = off + (x * jlast + jj) * (r - 1);
+        const int i = slot + x * (r - 1);
         if constexpr (r == 2) {
-            const double2 w = TRIV ? make_double2(1.0, 0.0) : ld_const(tw, t);
+            const double2 w = TRIV ? make_double2(1.0, 0.0) : tw(t, i);
 #pragma unroll
             for (int sb = 0; sb < rb; ++sb) {
                 const int i0 = sb * 2 * ra + x, i1 = i0 + ra;
@@ -274,7 +312,7 @@ __device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, 
                 v[i1] = a - mm;
             }
         } else {
-            const double2 w1 = TRIV ? make_double2(1.0, 0.0) : ld_const(tw, t), w2 = TRIV ? make_double2(1.0, 0.0) : ld_const(tw, t + 1);
+            const double2 w1 = TRIV ? make_double2(1.0, 0.0) : tw(t, i), w2 = TRIV ? make_double2(1.0, 0.0) : tw(t + 1, i + 1);
 #pragma unroll
             for (int sb = 0; sb < rb; ++sb) {
                 const int i0 = sb * 3 * ra + x, i1 = i0 + ra, i2 = i1 + ra;
@@ -298,9 +336,9 @@ template <int N3, int N2>
 constexpr bool kStageFence = Shape<N3, N2>::RHO > 8 && Shape<N3, N2>::RHO != 16;
 
 // FIRST: the round holds the transform's first stage (K = 0 is trivial).
-template <int N3, int N2, int K, int NA, bool FIRST = false>
-__device__ __forceinline__ void fwd_stages(RegArrN<N3, N2, NA> &v, int b, const CXDesc &xd,
-                                           const ctwpair *tw, int s0) {
+template <int N3, int N2, int K, int NA, bool FIRST = false, class TW>
+__device__ __forceinline__ void fwd_stages(RegArrN<N3, N2, NA> &v, int b, const CXDesc &xd, const TW &tw,
+                                           int s0) {
     if constexpr (K < Shape<N3, N2>::Q) {
         fwd_stage<N3, N2, K, NA, FIRST && K == 0>(v, b, tw, xd.fwd_off[s0 + K]);
         if constexpr (kStageFence<N3, N2>) __builtin_amdgcn_sched_barrier(0);
@@ -308,10 +346,44 @@ __device__ __forceinline__ void fwd_stages(RegArrN<N3, N2, NA> &v, int b, const 
     }
 }
 
+// Every factor of a non-first forward round's stages for block b.
+template <int N3, int N2, int K = 0>
+__device__ __forceinline__ void fwd_tw_fetch(TwRegs<TwSlots<N3, N2>::F> &o, int b, const CXDesc &xd,
+                                             const ctwpair *tw, int s0) {
+    using S = Shape<N3, N2>;
+    if constexpr (K < S::Q) {
+        constexpr int r = S::radix(K), rb = S::before(K);
+#pragma unroll
+        for (int sb = 0; sb < rb; ++sb)
+#pragma unroll
+            for (int e = 0; e < r - 1; ++e)
+                o.w[TwSlots<N3, N2>::fbase(K) + sb * (r - 1) + e] =
+                    ld_const(tw, xd.fwd_off[s0 + K] + (b * rb + sb) * (r - 1) + e);
+        fwd_tw_fetch<N3, N2, K + 1>(o, b, xd, tw, s0);
+    }
+}
+
+// Every factor of a non-last inverse round's stages for position jj.
+template <int N3, int N2, int K = Shape<N3, N2>::Q - 1>
+__device__ __forceinline__ void inv_tw_fetch(TwRegs<TwSlots<N3, N2>::I> &o, int jj, int jlast, const CXDesc &xd,
+                                             const ctwpair *tw, int s0) {
+    using S = Shape<N3, N2>;
+    if constexpr (K >= 0) {
+        constexpr int r = S::radix(K), ra = S::after(K);
+#pragma unroll
+        for (int x = 0; x < ra; ++x)
+#pragma unroll
+            for (int e = 0; e < r - 1; ++e)
+                o.w[TwSlots<N3, N2>::ibase(K) + x * (r - 1) + e] =
+                    ld_const(tw, xd.inv_off[s0 + K] + (x * jlast + jj) * (r - 1) + e);
+        inv_tw_fetch<N3, N2, K - 1>(o, jj, jlast, xd, tw, s0);
+    }
+}
+
 // LAST: the round holds the transform's last stage (K = Q-1 is trivial).
-template <int N3, int N2, int K, bool LAST = false>
-__device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast, const CXDesc &xd,
-                                           const ctwpair *tw, int s0) {
+template <int N3, int N2, int K, bool LAST = false, class TW>
+__device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast, const CXDesc &xd, const TW &tw,
+                                           int s0) {
     if constexpr (K >= 0) {
         inv_stage<N3, N2, K, LAST && K == Shape<N3, N2>::Q - 1>(v, jj, jlast, tw, xd.inv_off[s0 + K]);
         if constexpr (kStageFence<N3, N2>) __builtin_amdgcn_sched_barrier(0);
@@ -335,6 +407,15 @@ __device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast,
 // forward round and of the first inverse round are wave-uniform.
 
 enum { MODE_FWD = 0, MODE_INV = 1, MODE_CONV = 2 };
+
+// Which rounds load their per-lane twiddles before their data: forward
+// rounds (the column pass's last round; about 3% off the batched forward
+// column pass), inverse rounds, and the fused forward-product-inverse
+// rounds of the row pass.  The last two measured within run-to-run noise
+// and would raise the row pass's registers, so they load stage by stage.
+constexpr bool kPrefetchFwd = true;
+constexpr bool kPrefetchInv = false;
+constexpr bool kPrefetchConv = false;
 
 struct Geo {
     int q0, J, c, lbase, lstep;
@@ -369,6 +450,10 @@ __device__ __forceinline__ void round_io(const CRoundDesc &rd, const CXDesc &xd,
     // the block index b = item >> (wsh + jl) is the same on all 64 lanes of
     // a wave when wsh + jl >= 6: its twiddles then come from scalar loads
     const bool b_uniform = FIRST || (wsh + jl >= 6);
+    // a round whose factors differ across a wave loads them all first
+    constexpr bool kPfF = kPrefetchFwd && !FIRST && (MODE == MODE_FWD || (MODE == MODE_CONV && kPrefetchConv));
+    constexpr bool kPfI = kPrefetchInv && !LAST && (MODE == MODE_INV || (MODE == MODE_CONV && kPrefetchConv));
+    const TwDirect fd{ftw}, id{itw};
     for (int item = threadIdx.x; item < items; item += blockDim.x) {
         const int c = item & (W - 1);
         const int g = item >> wsh;
@@ -376,39 +461,54 @@ __device__ __forceinline__ void round_io(const CRoundDesc &rd, const CXDesc &xd,
         const int jj = LAST ? 0 : (FIRST ? g : (g & (J - 1)));
         const int q0 = FIRST ? jj : (b * rd.M + jj);
         Geo G{q0, J, c, ((q0 + (q0 >> lgp)) << wsh) + c, lstep};
-        auto ctx = pre(c, b, jj);
-        RegArrN<N3, N2, NA> v;
+        auto body = [&](const auto &fs, const auto &is, int bf) __attribute__((always_inline)) {
+            auto ctx = pre(c, b, jj);
+            RegArrN<N3, N2, NA> v;
 #pragma unroll
-        for (int l = 0; l < RHO; ++l) {
+            for (int l = 0; l < RHO; ++l) {
+                if constexpr (NA == 1) {
+                    v[0][l] = load(ctx, G, l);
+                } else {
+                    const double2 p = load(ctx, G, l);
+                    v[0][l] = p.x;
+                    v[1][l] = p.y;
+                }
+            }
+            if constexpr (MODE == MODE_FWD || MODE == MODE_CONV) fwd_stages<N3, N2, 0, NA, FIRST>(v, bf, xd, fs, rd.s0);
             if constexpr (NA == 1) {
-                v[0][l] = load(ctx, G, l);
+                if constexpr (MODE == MODE_CONV) mid(ctx, v[0], launder(G));
+                if constexpr (MODE == MODE_INV || MODE == MODE_CONV)
+                    inv_stages<N3, N2, Shape<N3, N2>::Q - 1, LAST>(v[0], jj, J, xd, is, rd.s0);
+                store(ctx, v[0], launder(G));
             } else {
-                const double2 p = load(ctx, G, l);
-                v[0][l] = p.x;
-                v[1][l] = p.y;
+                if constexpr (MODE == MODE_CONV) {
+                    mid(ctx, v, launder(G));
+                    inv_stages<N3, N2, Shape<N3, N2>::Q - 1, LAST>(v[1], jj, J, xd, is, rd.s0);
+                    store(ctx, v[1], launder(G));
+                } else {
+                    store(ctx, v, launder(G));
+                }
             }
-        }
-        if constexpr (MODE == MODE_FWD || MODE == MODE_CONV) {
-            if (FIRST)
-                fwd_stages<N3, N2, 0, NA, FIRST>(v, 0, xd, ftw, rd.s0);
-            else if (b_uniform)
-                fwd_stages<N3, N2, 0, NA>(v, __builtin_amdgcn_readfirstlane(b), xd, ftw, rd.s0);
-            else
-                fwd_stages<N3, N2, 0, NA>(v, b, xd, ftw, rd.s0);
-        }
-        if constexpr (NA == 1) {
-            if constexpr (MODE == MODE_CONV) mid(ctx, v[0], launder(G));
-            if constexpr (MODE == MODE_INV || MODE == MODE_CONV)
-                inv_stages<N3, N2, Shape<N3, N2>::Q - 1, LAST>(v[0], jj, J, xd, itw, rd.s0);
-            store(ctx, v[0], launder(G));
+        };
+        auto with_inv = [&](const auto &fs, int bf) __attribute__((always_inline)) {
+            if constexpr (kPfI) {
+                TwRegs<TwSlots<N3, N2>::I> ir;
+                inv_tw_fetch<N3, N2>(ir, jj, J, xd, itw, rd.s0);
+                body(fs, ir, bf);
+            } else {
+                body(fs, id, bf);
+            }
+        };
+        if constexpr (FIRST) {
+            with_inv(fd, 0);
+        } else if (b_uniform) {
+            with_inv(fd, __builtin_amdgcn_readfirstlane(b));
+        } else if constexpr (kPfF) {
+            TwRegs<TwSlots<N3, N2>::F> fr;
+            fwd_tw_fetch<N3, N2>(fr, b, xd, ftw, rd.s0);
+            with_inv(fr, b);
         } else {
-            if constexpr (MODE == MODE_CONV) {
-                mid(ctx, v, launder(G));
-                inv_stages<N3, N2, Shape<N3, N2>::Q - 1, LAST>(v[1], jj, J, xd, itw, rd.s0);
-                store(ctx, v[1], launder(G));
-            } else {
-                store(ctx, v, launder(G));
-            }
+            with_inv(fd, b);
         }
     }
 }

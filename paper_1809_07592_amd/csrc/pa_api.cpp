@@ -18,6 +18,7 @@
 #include "pa_kernels.h"
 #include "pa_plan.h"
 #include "pa_runtime.h"
+#include "pa_workspace.h"
 
 namespace pa {
 namespace rt {
@@ -83,9 +84,24 @@ struct StageSlot {
     hipEvent_t staged = nullptr;  // recorded after the copy out of `pinned`
 };
 
+// HIP binding of the workspace's device operations (pa_workspace.h).
+struct HipWsDev {
+    hipStream_t s;
+    hipError_t err = hipSuccess;
+    const char *what = "";
+    bool check(hipError_t e, const char *op) {
+        if (e == hipSuccess) return true;
+        err = e;
+        what = op;
+        return false;
+    }
+    bool sync() { return check(hipStreamSynchronize(s), "hipStreamSynchronize"); }
+    bool release(void *p) { return check(hipFree(p), "hipFree"); }
+    bool allocate(void **p, size_t n) { return check(hipMalloc(p, n), "hipMalloc workspace"); }
+};
+
 struct Workspace {
-    void *ptr = nullptr;
-    size_t bytes = 0;
+    pa::StreamWorkspace<HipWsDev> buf;
     StageSlot slot[kStageSlots];
     int next_slot = 0;
     // side streams that run length groups of a batched call concurrently
@@ -101,25 +117,22 @@ struct Workspace {
 std::mutex g_ws_mu;
 std::map<std::pair<int, void *>, Workspace> g_ws;
 
-// Library workspace for (current device, stream), grown on demand.  Growth
-// waits for the stream so an older buffer is never freed under running work.
-pa_status get_workspace(hipStream_t s, size_t bytes, void **out) {
+// Library workspace for (current device, stream), grown on demand, with
+// its lease moved into *hold: the caller keeps it until its launches that
+// use the buffer are enqueued.  Growth waits for the stream, so an older
+// buffer is never freed under work enqueued on it, and the lease keeps
+// another host thread on the same stream from freeing the buffer between a
+// call's reading its address and enqueueing its work.
+pa_status get_workspace(hipStream_t s, size_t bytes, void **out, std::unique_lock<std::mutex> *hold) {
     int dev = 0;
     PA_HIP(hipGetDevice(&dev), "hipGetDevice");
-    std::lock_guard<std::mutex> lk(g_ws_mu);
-    Workspace &w = g_ws[{dev, (void *)s}];
-    if (w.bytes < bytes) {
-        if (w.ptr) {
-            PA_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
-            PA_HIP(hipFree(w.ptr), "hipFree");
-            w.ptr = nullptr;
-            w.bytes = 0;
-        }
-        const size_t alloc = std::max(bytes, (size_t)1 << 20);
-        PA_HIP(hipMalloc(&w.ptr, alloc), "hipMalloc workspace");
-        w.bytes = alloc;
+    Workspace *w = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        w = &g_ws[{dev, (void *)s}];  // map nodes keep their address
     }
-    *out = w.ptr;
+    HipWsDev d{s};
+    if (!w->buf.acquire(d, bytes, out, hold)) return from_hip(d.err, d.what);
     return PA_OK;
 }
 
@@ -178,7 +191,7 @@ void release_stream_state(hipStream_t s) {
         if (sl.pinned) (void)hipHostFree(sl.pinned);
     }
     if (w.readback) (void)hipHostFree(w.readback);
-    if (w.ptr) (void)hipFree(w.ptr);
+    if (w.buf.ptr) (void)hipFree(w.buf.ptr);
     g_ws.erase(it);
 }
 
@@ -459,7 +472,8 @@ pa_status hash_one(const uint64_t *key, uint64_t n, const uint64_t *seed, uint64
     pa::PlanRef p{};
     PA_TRY(plan_for(L, 0, &p));
     void *ws = nullptr;
-    PA_TRY(get_workspace(s, (size_t)(8 * L), &ws));
+    std::unique_lock<std::mutex> ws_hold;
+    PA_TRY(get_workspace(s, (size_t)(8 * L), &ws, &ws_hold));
     pa::JobArgs ja{};
     ja.one = plain_job(key, n, seed, m, out, (int32_t *)ws, (int32_t *)ws + L);
     return run_plain(p, ja, 1, words8(n) + words8(n + m - 1), words8(m), s);
@@ -606,7 +620,8 @@ pa_status pa_modified_toeplitz_hash(const uint64_t *key_bits, uint64_t n, const 
     pa::PlanRef p{};
     PA_TRY(plan_for(L, 0, &p));
     void *ws = nullptr;
-    PA_TRY(get_workspace(s, (size_t)(8 * L), &ws));
+    std::unique_lock<std::mutex> ws_hold;
+    PA_TRY(get_workspace(s, (size_t)(8 * L), &ws, &ws_hold));
     pa::JobArgs ja{};
     ja.one = modified_job(key_bits, n, v_bits, m, out_bits, (int32_t *)ws, (int32_t *)ws + L);
     return run_plain(p, ja, 1, words8(n) + words8(n - 1) + words8(m), words8(m), s);
@@ -929,7 +944,8 @@ pa_status hash_batched(const pa_block *blocks, uint32_t count, hipStream_t s, bo
     BatchPrep bp;
     PA_TRY(prepare_batch(blocks, count, modified, &bp, batch_form(kFormFlat)));
     void *ws = nullptr;
-    PA_TRY(get_workspace(s, bp.total_bytes, &ws));
+    std::unique_lock<std::mutex> ws_hold;
+    PA_TRY(get_workspace(s, bp.total_bytes, &ws, &ws_hold));
     build_table(bp, ws);
     PA_TRY(stage_upload(s, ws, bp.blob.data(), bp.blob.size()));
     return launch_batch(bp, ws, s);
@@ -992,7 +1008,8 @@ pa_status pa_plan_hash(pa_plan_t plan, const uint64_t *key_bits, uint64_t n, uin
     PA_HIP(hipGetDevice(&dev), "hipGetDevice");
     if (dev != plan->device) return fail(PA_ERR_INVALID_ARG, "plan belongs to another device");
     void *ws = nullptr;
-    PA_TRY(get_workspace((hipStream_t)stream, (size_t)(4 * plan->L), &ws));
+    std::unique_lock<std::mutex> ws_hold;
+    PA_TRY(get_workspace((hipStream_t)stream, (size_t)(4 * plan->L), &ws, &ws_hold));
     return run_key_path(plan->lp, key_bits, n, m, plan->Shat, (int32_t *)ws, out_bits, (hipStream_t)stream);
 }
 
@@ -1018,7 +1035,8 @@ pa_status pa_cyclic_convolution(const uint64_t *a_bits, uint64_t na, const uint6
     pa::PlanRef p{};
     PA_TRY(plan_for(L, 0, &p));
     void *ws = nullptr;
-    PA_TRY(get_workspace(s, (size_t)(8 * L), &ws));
+    std::unique_lock<std::mutex> ws_hold;
+    PA_TRY(get_workspace(s, (size_t)(8 * L), &ws, &ws_hold));
     pa::JobArgs ja{};
     pa::JobDesc &j = ja.one;
     j.key = a_bits;

@@ -136,7 +136,8 @@ pa_status pa_toeplitz_hash_pair_fft(const uint64_t *key_a, const uint64_t *key_b
     }
     const size_t ws_bytes = pa::fft::fft_workspace(L, m);
     void *ws = nullptr;
-    PA_TRY(get_workspace(s, ws_bytes + 256, &ws));
+    std::unique_lock<std::mutex> ws_hold;
+    PA_TRY(get_workspace(s, ws_bytes + 256, &ws, &ws_hold));
     unsigned long long *dmax = (unsigned long long *)((char *)ws + ws_bytes);
     PA_HIP(pa::fft::launch_pair(p, key_a, key_b, (int64_t)n, seed, (int64_t)m, out_a, out_b, ws, dmax, s),
            "FFT pair launch");
@@ -148,6 +149,7 @@ pa_status pa_toeplitz_hash_pair_fft(const uint64_t *key_a, const uint64_t *key_b
     double err = 0.0;
     memcpy(&err, rb, sizeof(err));
     rb_hold.unlock();
+    ws_hold.unlock();  // the pass is complete; the exact fallback takes the lease again
     if (max_error) *max_error = err;
     const bool fallback = err >= guard;
     if (fell_back) *fell_back = fallback ? 1 : 0;

@@ -45,7 +45,7 @@ pa_status check_block(const uint64_t *key, uint64_t n, const uint64_t *seed, uin
                       uint64_t *L);
 // Library workspace of at least `bytes` for (current device, stream s);
 // growth waits for s so an older buffer is never freed under running work.
-pa_status get_workspace(hipStream_t s, size_t bytes, void **out);
+pa_status get_workspace(hipStream_t s, size_t bytes, void **out, std::unique_lock<std::mutex> *hold);
 // Copies host data to device address dst on stream s through the stream's
 // pinned staging slots (stream-ordered; the host may reuse src at once).
 pa_status stage_upload(hipStream_t s, void *dst, const void *src, size_t bytes);

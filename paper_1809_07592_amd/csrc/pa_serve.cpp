@@ -189,19 +189,20 @@ struct pa_server_s {
     void complete_locked(Req *r, Clock::time_point t, size_t stream, pa_status status);
     pa_status launch(std::vector<Req *> &batch_reqs, Batch *b);
     bool admit_locked(Req *r, std::vector<Spectrum *> *builds);
-    bool evict_one_locked();
+    bool evict_one_locked(const Spectrum *keep);
     pa_status build_spectrum(Spectrum *sp);
 };
 
-// Frees the least recently used spectrum that no admitted request uses and
-// whose build has finished (lock held).  False if there is none.
-bool pa_server_s::evict_one_locked() {
+// Frees the least recently used spectrum that no admitted request uses,
+// whose build has finished and which is not `keep` (lock held).  False if
+// there is none.
+bool pa_server_s::evict_one_locked(const Spectrum *keep) {
     Spectrum *best = nullptr;
     Seed *best_seed = nullptr;
     for (Seed &sd : seeds)
         for (auto &kv : sd.spectra) {
             Spectrum &sp = kv.second;
-            if (sp.users || !sp.launched) continue;
+            if (sp.users || !sp.launched || &sp == keep) continue;
             if (!sp.built && !sim) {
                 const hipError_t q = hipEventQuery(sp.ready);
                 if (q == hipErrorNotReady) continue;
@@ -224,14 +225,16 @@ bool pa_server_s::evict_one_locked() {
 
 // Admission of the request at the head of the queue (lock held): its
 // workspace and, if the (seed, length) spectrum is not resident, room for
-// the spectrum, evicting unused spectra while that helps.  New spectra are
-// appended to *builds.  False if the pool cannot hold them yet.
+// the spectrum, evicting other unused spectra while that helps (never the
+// one this request needs).  New spectra are appended to *builds.  False if
+// the pool cannot hold them yet.
 bool pa_server_s::admit_locked(Req *r, std::vector<Spectrum *> *builds) {
     Seed &sd = seeds[r->seed];
-    auto it = sd.spectra.find(r->L);
-    const bool have = it != sd.spectra.end();
     const uint64_t sbytes = 4 * r->L;
     for (;;) {
+        // looked up on every pass: an eviction erases map entries
+        auto it = sd.spectra.find(r->L);
+        const bool have = it != sd.spectra.end();
         uint64_t off = 0, soff = 0;
         if (pool->alloc(r->need, &off)) {
             if (have || pool->alloc(sbytes, &soff)) {
@@ -259,7 +262,7 @@ bool pa_server_s::admit_locked(Req *r, std::vector<Spectrum *> *builds) {
             }
             pool->release(off, r->need);
         }
-        if (!evict_one_locked()) return false;
+        if (!evict_one_locked(have ? &it->second : nullptr)) return false;
     }
 }
 

@@ -123,6 +123,31 @@ def test_unused_spectra_are_evicted_when_the_pool_needs_room():
         assert st["bytes_in_flight"] == st["spectrum_bytes"] == ws(n, m)
 
 
+def test_the_spectrum_a_request_needs_is_never_evicted_for_it():
+    # room for two spectra and one workspace.  Seeds A and B both resident,
+    # A least recently used; while a request on B runs, a request on A must
+    # wait for the running one's workspace instead of evicting A's spectrum
+    # (which it is about to use) to make room
+    n, m = 200_000, 50_000
+    u = ws(n, m)
+    budget = 3 * u + 4096
+    with pa.Server(budget, max_inflight=8, executor=pa.EXEC_SIMULATED, sim_bits_per_us=1e4) as s:
+        a = s.register_seed(FAKE_SEED, n + m)
+        b = s.register_seed(FAKE_SEED + 0x1000, n + m)
+        s.wait(s.submit(a, FAKE_KEY, n, m, FAKE_OUT))
+        s.wait(s.submit(b, FAKE_KEY, n, m, FAKE_OUT))
+        assert s.stats()["spectra_resident"] == 2
+        running = s.submit(b, FAKE_KEY, n, m, FAKE_OUT)       # about 20 ms
+        waiting = s.submit(a, FAKE_KEY, n, m, FAKE_OUT)
+        s.wait(running)
+        s.wait(waiting)
+        st = s.stats()
+        assert st["completed"] == 4 and st["failed"] == 0
+        assert st["spectra_built"] == 2 and st["spectra_evicted"] == 0 and st["spectra_resident"] == 2
+        assert st["peak_bytes_in_flight"] <= budget
+        assert st["bytes_in_flight"] == st["spectrum_bytes"] == 2 * u
+
+
 def test_cancel_a_queued_request():
     with pa.Server(8 << 20, max_inflight=1, executor=pa.EXEC_SIMULATED, sim_bits_per_us=1.0) as s:
         sid = s.register_seed(FAKE_SEED, 5_000_000)

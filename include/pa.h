@@ -469,7 +469,15 @@ pa_status pa_server_destroy(pa_server_t server);
 /* Static text for a status code. */
 const char *pa_status_string(pa_status s);
 
-/* Thread-local text of the last failure in the calling thread ("" if none). */
+/* Thread-local text of the last failure in the calling thread ("" if none).
+ *
+ * PA_LOG (environment, read once per process) writes diagnostic lines
+ * "[pa] <level>: <text>" to stderr: 0 or "off" (default); 1 or "error":
+ * every failing call with its status and this text, and failed serving
+ * requests; 2 or "info": also device plans as they are built, workspace
+ * growth, tuning results and tuning-cache files, server set-up; 3 or
+ * "debug": also batched-call forms and the serving scheduler's spectrum
+ * builds and evictions. */
 const char *pa_last_error(void);
 
 /* Library / kernel build identification string. */

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -25,8 +26,35 @@ namespace rt {
 
 thread_local std::string g_last_error;
 
+int log_level() {
+    static const int level = [] {
+        const char *v = std::getenv("PA_LOG");
+        if (!v || !*v) return 0;
+        const std::string t(v);
+        if (t == "off") return 0;
+        if (t == "error") return (int)LOG_ERROR;
+        if (t == "info") return (int)LOG_INFO;
+        if (t == "debug") return (int)LOG_DEBUG;
+        char *end = nullptr;
+        const long x = std::strtol(v, &end, 10);
+        return (end && !*end) ? (int)std::max(0L, std::min(x, (long)LOG_DEBUG)) : 0;
+    }();
+    return level;
+}
+
+void logf(int level, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    static const char *names[] = {"", "error", "info", "debug"};
+    std::fprintf(stderr, "[pa] %s: %s\n", names[std::max(0, std::min(level, (int)LOG_DEBUG))], buf);
+}
+
 pa_status fail(pa_status s, const std::string &msg) {
     g_last_error = msg;
+    if (s != PA_OK) PA_LOG_AT(LOG_ERROR, "%s: %s", pa_status_string(s), msg.c_str());
     return s;
 }
 
@@ -132,7 +160,9 @@ pa_status get_workspace(hipStream_t s, size_t bytes, void **out, std::unique_loc
         w = &g_ws[{dev, (void *)s}];  // map nodes keep their address
     }
     HipWsDev d{s};
-    if (!w->buf.acquire(d, bytes, out, hold)) return from_hip(d.err, d.what);
+    bool grew = false;
+    if (!w->buf.acquire(d, bytes, out, hold, &grew)) return from_hip(d.err, d.what);
+    if (grew) PA_LOG_AT(LOG_INFO, "workspace of stream %p on device %d: %zu bytes", (void *)s, dev, w->buf.bytes);
     return PA_OK;
 }
 
@@ -943,6 +973,9 @@ pa_status hash_batched(const pa_block *blocks, uint32_t count, hipStream_t s, bo
     if (count == 0) return PA_OK;
     BatchPrep bp;
     PA_TRY(prepare_batch(blocks, count, modified, &bp, batch_form(kFormFlat)));
+    PA_LOG_AT(LOG_DEBUG, "batched call: %u blocks, %zu lengths, %s form, %zu launches, workspace %zu bytes", count,
+              bp.groups.size(), bp.form == kFormFlat ? "flat" : "lanes",
+              bp.form == kFormFlat ? bp.launches.size() : 3 * bp.groups.size(), bp.total_bytes);
     void *ws = nullptr;
     std::unique_lock<std::mutex> ws_hold;
     PA_TRY(get_workspace(s, bp.total_bytes, &ws, &ws_hold));

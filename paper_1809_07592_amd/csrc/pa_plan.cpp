@@ -28,6 +28,7 @@
 
 #include "pa_internal.h"
 #include "pa_plan.h"
+#include "pa_runtime.h"
 
 namespace pa {
 
@@ -487,6 +488,10 @@ PlanRef get_len_plan(uint64_t L, const Geometry &geo) {
         throw std::runtime_error("hipMemcpy of plan failed");
     e->dplan = (LenPlan *)d;
 
+    PA_LOG_AT(rt::LOG_INFO,
+              "plan L=%llu on device %d: R=%d C=%d W=%d, first row round %d, row workgroup %d%s, column LDS %d B",
+              (unsigned long long)L, dev, lp.R, lp.C, lp.W, lp.rho0, lp.row_threads,
+              lp.row_threads_fixed ? " (tuned)" : "", lp.col_lds * 4);
     PlanRef out{&e->plan, e->dplan};
     g_plans[key] = std::move(e);
     return out;

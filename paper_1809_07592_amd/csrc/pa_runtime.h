@@ -36,7 +36,21 @@ namespace rt {
 // side streams (four in all, as many as the default hardware queues).
 constexpr int kMaxLanes = 4;
 
-// Records msg as the calling thread's last error and returns s.
+// Diagnostic log on stderr, one line per event, prefixed "[pa]".  PA_LOG
+// (read once per process) sets the level: 0 or "off" (default), 1 or
+// "error" (every failing call with its message), 2 or "info" (plans built,
+// workspace growth, tuning results and cache files, server set-up), 3 or
+// "debug" (batch forms, spectrum builds and evictions).
+enum { LOG_ERROR = 1, LOG_INFO = 2, LOG_DEBUG = 3 };
+int log_level();
+void logf(int level, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+#define PA_LOG_AT(level, ...)                                          \
+    do {                                                               \
+        if (::pa::rt::log_level() >= (level)) ::pa::rt::logf((level), __VA_ARGS__); \
+    } while (0)
+
+// Records msg as the calling thread's last error and returns s (logged at
+// the error level).
 pa_status fail(pa_status s, const std::string &msg);
 // PA_OK for hipSuccess, else PA_ERR_OUT_OF_MEMORY / PA_ERR_DEVICE with text.
 pa_status from_hip(hipError_t e, const char *what);

@@ -214,6 +214,8 @@ bool pa_server_s::evict_one_locked(const Spectrum *keep) {
             }
         }
     if (!best) return false;
+    PA_LOG_AT(LOG_DEBUG, "server: evicting the spectrum of seed %u at L=%llu (%llu bytes)", best->seed,
+              (unsigned long long)best->L, (unsigned long long)best->bytes);
     pool->release(best->off, best->bytes);
     st.spectrum_bytes -= best->bytes;
     st.spectra_resident--;
@@ -269,6 +271,7 @@ bool pa_server_s::admit_locked(Req *r, std::vector<Spectrum *> *builds) {
 // Enqueues the spectrum build on the build stream and records its event;
 // nothing waits for it here.
 pa_status pa_server_s::build_spectrum(Spectrum *sp) {
+    PA_LOG_AT(LOG_DEBUG, "server: building the spectrum of seed %u at L=%llu", sp->seed, (unsigned long long)sp->L);
     if (sim) {
         sp->built = sp->launched = true;
         return PA_OK;
@@ -393,6 +396,8 @@ void pa_server_s::complete_locked(Req *r, Clock::time_point t, size_t stream, pa
     r->t_done = t;
     r->done = true;
     r->status = status;
+    if (status != PA_OK && status != PA_ERR_CANCELLED)
+        PA_LOG_AT(LOG_ERROR, "server: request %llu failed: %s", (unsigned long long)r->ticket, pa_status_string(status));
     pool->release(r->ws_off, r->need);
     if (r->spec) {
         r->spec->users--;
@@ -581,6 +586,8 @@ pa_status pa_server_create(const pa_server_config *cfg_in, pa_server_t *server) 
             if (e != hipSuccess) return from_hip(e, "server stream setup");
         }
     }
+    PA_LOG_AT(LOG_INFO, "server: budget %llu bytes, %u streams, at most %u requests in flight, %s executor",
+              (unsigned long long)s->pool->size(), cfg->streams, cfg->max_inflight, s->sim ? "simulated" : "GPU");
     pa_server_s *raw = s.release();
     raw->th = std::thread([raw] { raw->loop(); });
     *server = raw;

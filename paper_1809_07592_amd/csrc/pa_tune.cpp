@@ -167,8 +167,13 @@ void load_tune_cache_once() {
         const std::string arch = device_arch();
         std::vector<Row> rows;
         if (parse_file(path, &rows, arch) != PA_OK) return;
+        int used = 0;
         for (const Row &r : rows)
-            if (r.arch.empty() || r.arch == arch) pa::set_tuned_geometry(r.L, (int)r.cls, r.g);
+            if (r.arch.empty() || r.arch == arch) {
+                pa::set_tuned_geometry(r.L, (int)r.cls, r.g);
+                ++used;
+            }
+        PA_LOG_AT(LOG_INFO, "tuning cache %s: %d of %zu rows for %s", path, used, rows.size(), arch.c_str());
     });
 }
 
@@ -360,6 +365,11 @@ pa_status pa_autotune(uint64_t transform_len, uint32_t count, uint32_t reps, voi
     r.row_first = (uint32_t)best.row_first;
     r.row_threads = (uint32_t)best.row_threads;
     pa::set_tuned_geometry(L, count > 1 ? 1 : 0, best == defg ? pa::Geometry{} : best);
+    PA_LOG_AT(pa::rt::LOG_INFO,
+              "autotune L=%llu count=%u: %u candidates, log2 R=%d W=%d row_first=%d row_threads=%d at %.2f us "
+              "(default %.2f us)",
+              (unsigned long long)L, count, r.candidates, best.log2R, best.W, best.row_first, best.row_threads,
+              r.best_us, r.default_us);
     *result = r;
     // PA_TUNE_CACHE: keep the table for later processes on this architecture
     if (const char *path = std::getenv("PA_TUNE_CACHE"))

@@ -31,10 +31,12 @@ struct StreamWorkspace {
     void *ptr = nullptr;
     size_t bytes = 0;
 
-    // At least `need` bytes at *out, with the lease moved into *hold.  On
+    // At least `need` bytes at *out, with the lease moved into *hold;
+    // *grew (optional) tells whether the buffer was (re)allocated.  On
     // failure returns false with dev.what set and holds nothing.
-    bool acquire(Dev &dev, size_t need, void **out, std::unique_lock<std::mutex> *hold) {
+    bool acquire(Dev &dev, size_t need, void **out, std::unique_lock<std::mutex> *hold, bool *grew = nullptr) {
         std::unique_lock<std::mutex> lk(use);
+        if (grew) *grew = bytes < need;
         if (bytes < need) {
             if (ptr) {
                 if (!dev.sync()) return false;

@@ -636,6 +636,17 @@ def main():
     alu = pa.alu_probe(stream)
     alu["fma_frac_of_peak"] = alu["fma_Tops"] / FP64_VALU_PEAK_TOPS
     progress("fp64 FMA: %.1f T/s, modular products: %.0f G/s" % (alu["fma_Tops"], alu["mulmod_Gops"]))
+    # the fixed cost of each of the plain step's three launches (an empty
+    # kernel of the same shape, back to back), and what one launch with
+    # grid barriers or per-tile releases would cost instead
+    pg = tuning["plain_geometry"]
+    launch = {"colfwd_us": pa.launch_probe(2 * pg["col_tiles"], pg["col_threads"], stream=stream),
+              "rowconv_us": pa.launch_probe(pg["rows"], pg["row_threads"], stream=stream),
+              "colinv_us": pa.launch_probe(pg["col_tiles"], pg["col_threads"], stream=stream)}
+    launch["step_floor_us"] = launch["colfwd_us"] + launch["rowconv_us"] + launch["colinv_us"]
+    phase = pa.phase_probe(stream)
+    progress("launch floor of the plain step: %.1f us; three phases %.1f us as launches, %.1f us with grid barriers"
+             % (launch["step_floor_us"], phase["three_launches_us"], phase["cooperative_grid_sync_us"]))
     # the timed outputs against the CPU oracle, word for word
     plain_out = out.cpu().numpy().view(np.uint64)[: wl.words(m)].copy()
     cases = {"small_block_n262144": [small_io], "large_block_n12800000": [large_io]}
@@ -666,7 +677,8 @@ def main():
         "batched": batched, "batched_uneven": uneven, "large_block": large, "small_block": small, "modified_toeplitz": modified,
         "plan_path": planr, "fft_pair": fftp,
         "serving": serving,
-        "tuning": tuning, "copy_bandwidth": copy, "alu_probe": alu, "cpu_baseline": cpu,
+        "tuning": tuning, "copy_bandwidth": copy, "alu_probe": alu, "launch_probe": launch, "phase_probe": phase,
+        "cpu_baseline": cpu,
         "context": {"paper_Mbps": 116, "paper_setting": "Virtex-6 FPGA at 200 MHz, modified Toeplitz, float FFT, "
                     "n = 2^20 (input rate; a different variant and hardware, so not a target)"},
         "kernel_source_hash": kernel_source_hash(),

@@ -361,6 +361,38 @@ pa_status pa_tune_load(const char *path);
 pa_status pa_alu_probe(void *stream, double *fma_tops, double *mulmod_gops);
 
 /*
+ * Launch costs (measurement only; no result of the hash depends on them).
+ * pa_launch_probe: microseconds per launch of an empty kernel of
+ * `workgroups` x `threads` (threads a multiple of 64, at most 1024),
+ * launched `reps` times back to back on `stream` and timed by events
+ * around the run; waits for the stream.
+ * pa_phase_probe: with one workgroup of 768 threads per CU (the row pass's
+ * shape for one block), three dependent phases in which every workgroup
+ * copies the 48 KiB tile another workgroup wrote in the previous phase:
+ *   three_launches_us         as three ordinary launches,
+ *   cooperative_grid_sync_us  as one cooperative launch with a grid-wide
+ *                             barrier between the phases,
+ * the same data checked equal in both forms (else PA_ERR_DEVICE); an empty
+ * kernel of that shape launched normally and cooperatively; and `tiles`
+ * tiles of 48 KiB written with no release (tiles_no_release_us) or each
+ * followed by an agent-scope release and a counter increment
+ * (tiles_release_us), the hand-off a persistent kernel with per-block
+ * phase counters needs.  Allocates about 150 MB for the call, waits for
+ * the stream.  PA_ERR_UNSUPPORTED_SIZE if the device cannot launch
+ * cooperatively.
+ */
+pa_status pa_launch_probe(void *stream, uint32_t workgroups, uint32_t threads, uint32_t reps, double *us_per_launch);
+typedef struct pa_phase_probe_result {
+    uint32_t workgroups, threads;
+    double phase_bytes;  /* bytes written per phase */
+    double empty_launch_us, empty_cooperative_us;
+    double three_launches_us, cooperative_grid_sync_us;
+    uint32_t tiles;
+    double tiles_no_release_us, tiles_release_us;
+} pa_phase_probe_result;
+pa_status pa_phase_probe(void *stream, pa_phase_probe_result *result);
+
+/*
  * Kernel timing (tracing).  While enabled, the library records a pair of
  * HIP events with every kernel it launches, carrying that kernel's own
  * start and end timestamps on the launch's stream, and notes the launch's algorithmic HBM bytes (what the

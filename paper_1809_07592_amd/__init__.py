@@ -75,6 +75,14 @@ class TuneResult(ctypes.Structure):
                 ("row_first", ctypes.c_uint32), ("row_threads", ctypes.c_uint32)]
 
 
+class PhaseProbeResult(ctypes.Structure):
+    _fields_ = [("workgroups", ctypes.c_uint32), ("threads", ctypes.c_uint32), ("phase_bytes", ctypes.c_double),
+                ("empty_launch_us", ctypes.c_double), ("empty_cooperative_us", ctypes.c_double),
+                ("three_launches_us", ctypes.c_double), ("cooperative_grid_sync_us", ctypes.c_double),
+                ("tiles", ctypes.c_uint32), ("tiles_no_release_us", ctypes.c_double),
+                ("tiles_release_us", ctypes.c_double)]
+
+
 class TuneGeometry(ctypes.Structure):
     _fields_ = [("log2_rows", ctypes.c_uint32), ("tile_width", ctypes.c_uint32), ("row_first", ctypes.c_uint32),
                 ("row_threads", ctypes.c_uint32)]
@@ -94,6 +102,13 @@ def lib():
                 if not os.path.exists(LIB_PATH):
                     raise RuntimeError("libpa.so is not built (run: python -m paper_1809_07592_amd.build); "
                                        "there is no CPU fallback")
+                # torch ships its own HIP runtime under the soname libpa
+                # needs; the first one loaded serves the whole process, and
+                # torch fails on any other, so it is loaded first
+                try:
+                    import torch  # noqa: F401
+                except ImportError:
+                    pass
                 L = ctypes.CDLL(LIB_PATH)
                 vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
                 st = ctypes.c_int
@@ -136,6 +151,10 @@ def lib():
                 L.pa_toeplitz_hash_pair_fft.restype = st
                 L.pa_alu_probe.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
                 L.pa_alu_probe.restype = st
+                L.pa_launch_probe.argtypes = [vp, u32, u32, u32, ctypes.POINTER(ctypes.c_double)]
+                L.pa_launch_probe.restype = st
+                L.pa_phase_probe.argtypes = [vp, ctypes.POINTER(PhaseProbeResult)]
+                L.pa_phase_probe.restype = st
                 L.pa_final_key_length.argtypes = [u64, u64, u64]
                 L.pa_final_key_length.restype = u64
                 L.pa_cyclic_convolution.argtypes = [vp, u64, vp, u64, u64, vp, vp]
@@ -484,6 +503,21 @@ def alu_probe(stream=None) -> dict:
     f, m = ctypes.c_double(), ctypes.c_double()
     _check(lib().pa_alu_probe(_stream_handle(stream), ctypes.byref(f), ctypes.byref(m)))
     return {"fma_Tops": f.value, "mulmod_Gops": m.value}
+
+
+def launch_probe(workgroups: int, threads: int, reps: int = 200, stream=None) -> float:
+    """Microseconds per back-to-back launch of an empty kernel of this shape."""
+    us = ctypes.c_double()
+    _check(lib().pa_launch_probe(_stream_handle(stream), int(workgroups), int(threads), int(reps), ctypes.byref(us)))
+    return us.value
+
+
+def phase_probe(stream=None) -> dict:
+    """Three dependent phases as three launches and as one cooperative
+    launch with grid barriers; per-tile release cost (see include/pa.h)."""
+    r = PhaseProbeResult()
+    _check(lib().pa_phase_probe(_stream_handle(stream), ctypes.byref(r)))
+    return {f: (getattr(r, f) if isinstance(getattr(r, f), float) else int(getattr(r, f))) for f, _ in r._fields_}
 
 
 def final_key_length(n: int, t: int, s: int) -> int:

@@ -281,3 +281,17 @@ def test_alu_probe_rates_are_plausible():
     # product costing about three FMAs
     assert 5.0 < r["fma_Tops"] < 45.0
     assert 0.15 < r["mulmod_Gops"] * 1e-3 / r["fma_Tops"] < 0.5
+
+
+def test_launch_and_phase_probes():
+    # an empty launch costs a few microseconds; the phase probe checks the
+    # two forms of its three phases against each other before timing them
+    us = pa.launch_probe(256, 768, reps=100)
+    assert 0.2 < us < 100.0
+    r = pa.phase_probe()
+    assert r["workgroups"] >= 1 and r["threads"] == 768 and r["tiles"] == 8 * r["workgroups"]
+    for k in ("empty_launch_us", "empty_cooperative_us", "three_launches_us", "cooperative_grid_sync_us",
+              "tiles_no_release_us", "tiles_release_us"):
+        assert 0.0 < r[k] < 10_000.0, k
+    with pytest.raises(pa.PAError):
+        pa.launch_probe(1, 100)

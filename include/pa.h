@@ -112,6 +112,11 @@ typedef struct pa_block {
  * A bad block fails the whole call with PA_ERR_INVALID_ARG or
  * PA_ERR_UNSUPPORTED_SIZE before anything is enqueued; count = 0 is a
  * no-op.  Results are identical to calling pa_toeplitz_hash per block.
+ * Launch form: blocks are grouped by transform length, and each group's
+ * three passes run as one launch each over its blocks, the groups spread
+ * over up to four concurrent stream lanes (default); PA_BATCH_FORM=flat
+ * instead runs each pass as launches over flat workgroup lists that span
+ * all lengths (fewer launches, no overlap between lengths).
  */
 pa_status pa_toeplitz_hash_batched(const pa_block *blocks, uint32_t count,
                                    void *stream);

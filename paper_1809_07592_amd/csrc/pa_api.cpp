@@ -972,7 +972,7 @@ pa_status launch_batch(const BatchPrep &bp, void *ws, hipStream_t s) {
 pa_status hash_batched(const pa_block *blocks, uint32_t count, hipStream_t s, bool modified) {
     if (count == 0) return PA_OK;
     BatchPrep bp;
-    PA_TRY(prepare_batch(blocks, count, modified, &bp, batch_form(kFormFlat)));
+    PA_TRY(prepare_batch(blocks, count, modified, &bp, batch_form(kFormLanes)));
     PA_LOG_AT(LOG_DEBUG, "batched call: %u blocks, %zu lengths, %s form, %zu launches, workspace %zu bytes", count,
               bp.groups.size(), bp.form == kFormFlat ? "flat" : "lanes",
               bp.form == kFormFlat ? bp.launches.size() : 3 * bp.groups.size(), bp.total_bytes);

@@ -299,10 +299,9 @@ static int choose_log2R(uint64_t L) {
     int k, j;
     factor_len(L, k, j);
     // R^2 ~ L/16 balances the column-tile count (C/16) with the row count.
-    // Between 2^22 and 2^23 the larger R is taken: its rows of at most 6912
-    // values need one register round fewer than rows twice as long, and the
-    // single blocks of those lengths (9*2^19 and 27*2^18) measured 3-7%
-    // faster.
+    // Between 2^22 and 2^23 the larger R is taken: the single blocks of
+    // those lengths measured faster with it (9*2^19: 7%, whose rows then
+    // need one register round fewer; 27*2^18: 3%, shorter rows in LDS).
     const double lg = std::log2((double)L);
     int a = lg > 22.0 ? (int)std::ceil((lg - 4.0) / 2.0) : (int)std::lround((lg - 4.0) / 2.0);
     a = std::min(a, std::min(10, k - 6));

@@ -164,10 +164,13 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def batched_uneven_run(pa, wl, torch, np, count, stream):
+def batched_uneven_run(pa, wl, torch, np, count, stream, tune):
     """Uneven batch: `count` blocks with n log-uniform in [2^18, 2^22] and
     m/n uniform in [0.05, 0.5], each with its own key and seed, in one
-    pa_toeplitz_hash_batched call (the library groups them by length)."""
+    pa_toeplitz_hash_batched call (the library groups them by length).
+    With tune, the library's autotuner first picks the batch-class geometry
+    of every length on that length's own blocks (untimed); the batch is
+    timed before and after."""
     shapes = wl.batched_shapes(count, 4)
     blocks = []
     for i, sh in enumerate(shapes):
@@ -180,8 +183,20 @@ def batched_uneven_run(pa, wl, torch, np, count, stream):
 
     bits = sum(sh.n for sh in shapes)
     lens = sorted({pa.transform_len(sh.n, sh.m) for sh in shapes})
+    tuning = None
+    if tune:
+        untuned_ms, _ = time_steps(step, 5, 2, torch)
+        per_len = {}
+        for L in lens:
+            c = sum(1 for sh in shapes if pa.transform_len(sh.n, sh.m) == L)
+            r = pa.autotune(L, count=min(c, 16), reps=3, stream=stream)
+            per_len[str(L)] = {"blocks": c, "log2_rows": r["log2_rows"], "tile_width": r["tile_width"],
+                               "row_first": r["row_first"], "row_threads": r["row_threads"],
+                               "best_us": r["best_us"], "default_us": r["default_us"]}
+        tuning = {"untuned_ms_per_batch": untuned_ms, "untuned_Gbs": bits / (untuned_ms * 1e-3) / 1e9,
+                  "lengths": per_len}
     # both launch forms, as direct calls and as captured graphs (the
-    # library's defaults: flat for calls, lanes for graphs)
+    # library's default for both is the lanes form)
     forms = {}
     old = os.environ.get("PA_BATCH_FORM")
     try:
@@ -203,9 +218,9 @@ def batched_uneven_run(pa, wl, torch, np, count, stream):
             os.environ.pop("PA_BATCH_FORM", None)
         else:
             os.environ["PA_BATCH_FORM"] = old
-    bms, gms = forms["flat"]["ms_per_batch"], forms["lanes"]["graph_ms_per_batch"]
+    bms, gms = forms["lanes"]["ms_per_batch"], forms["lanes"]["graph_ms_per_batch"]
     return {"value": bits / (bms * 1e-3) / 1e9, "unit": "Gb/s", "blocks": count, "ms_per_batch": bms,
-            "graph_Gbs": bits / (gms * 1e-3) / 1e9, "graph_ms_per_batch": gms, "forms": forms,
+            "graph_Gbs": bits / (gms * 1e-3) / 1e9, "graph_ms_per_batch": gms, "forms": forms, "tuning": tuning,
             "sum_n": bits, "distinct_lengths": len(lens), "min_len": lens[0], "max_len": lens[-1],
             "shapes": "n = round(2^U(18,22)), m = max(1, round(n U(0.05, 0.5))), own seed per block"}
 
@@ -611,7 +626,7 @@ def main():
         del blocks
         progress("batched: %.3f ms per %d blocks, %.2f Gb/s" % (bms, args.batch, batched["value"]))
 
-    uneven = batched_uneven_run(pa, wl, torch, np, args.batch, stream) if args.batch > 0 else None
+    uneven = batched_uneven_run(pa, wl, torch, np, args.batch, stream, not args.no_tune) if args.batch > 0 else None
     if uneven is not None:
         progress("batched uneven: %.3f ms per %d blocks, %.2f Gb/s" % (uneven["ms_per_batch"], args.batch,
                                                                        uneven["value"]))

@@ -10,8 +10,8 @@ transforms and the result), on lengths 2^12, 3 * 2^11, 9 * 2^9 and
 the forward-inverse round trip the identity (and a shifted impulse a
 rotation); all-ones inputs reach the largest values.  The resident
 spectrum of a plan is the length-L transform of its seed: the unit impulse
-transforms to all ones, and the next unit vector to every L-th root of
-unity exactly once.
+transforms to all ones, the next unit vector to every L-th root of unity
+exactly once, and a random seed to the values a CPU transform gives.
 """
 import numpy as np
 import pytest
@@ -104,6 +104,43 @@ def test_spectrum_of_unit_vectors(L):
             assert np.unique(r).size == L
             assert all(pow(int(x), L, P) == 1 for x in r[:: max(1, L // 257)])
             assert all(pow(int(x), L, P) == 1 for x in r)
+
+
+def cpu_ntt(x, w):
+    """Length-N transform X_k = sum_i x_i w^(ik) mod P (N = 2^a 3^b), by
+    recursive decimation in time: a plain model of the transform, not of
+    the kernels' rounds or order."""
+    N = x.size
+    if N == 1:
+        return x % P
+    r = 2 if N % 2 == 0 else 3
+    M = N // r
+    parts = [cpu_ntt(x[i::r], pow(w, r, P)) for i in range(r)]
+    wk = np.ones(N, dtype=np.int64)
+    for k in range(1, N):
+        wk[k] = wk[k - 1] * w % P
+    k = np.arange(N)
+    out = np.zeros(N, dtype=np.int64)
+    for i in range(r):
+        out = (out + parts[i][k % M] * wk[(i * k) % N]) % P
+    return out
+
+
+@pytest.mark.parametrize("L", LENGTHS)
+def test_spectrum_values_match_a_cpu_transform(L):
+    # the resident spectrum of a random seed holds the values of its
+    # length-L transform (in the kernels' own order): the same multiset
+    # as a CPU transform at any primitive L-th root of unity
+    g = np.random.default_rng(L + 7)
+    bits = g.integers(0, 2, L).astype(np.uint8)
+    with pa.Plan(dev(pack(bits)), L, transform_len=L) as plan:
+        spec = plan.spectrum()
+        torch.cuda.synchronize()
+        v = spec.cpu().numpy().astype(np.int64)
+    assert np.all(np.abs(v) <= P // 2 + 4)
+    w = pow(5, (P - 1) // L, P)
+    want = cpu_ntt(bits.astype(np.int64), w)
+    assert np.array_equal(np.sort(np.mod(v, P)), np.sort(want))
 
 
 def test_bits_of_the_convolution_give_the_hash():

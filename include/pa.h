@@ -462,6 +462,9 @@ typedef struct pa_server_config {
     uint32_t streams;           /* HIP streams batches go to */
     uint32_t executor;          /* PA_EXEC_GPU or PA_EXEC_SIMULATED */
     double sim_bits_per_us;     /* simulated executor speed */
+    uint32_t sim_fail_every;    /* simulated executor: requests whose ticket is a multiple
+                                   of this complete with PA_ERR_DEVICE (0: none), to test
+                                   failure handling without a device */
 } pa_server_config;
 
 typedef struct pa_server_stats {

@@ -59,7 +59,7 @@ class KernelStat(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
                 ("max_queue", ctypes.c_uint32), ("streams", ctypes.c_uint32), ("executor", ctypes.c_uint32),
-                ("sim_bits_per_us", ctypes.c_double)]
+                ("sim_bits_per_us", ctypes.c_double), ("sim_fail_every", ctypes.c_uint32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -585,9 +585,9 @@ class Server:
     """
 
     def __init__(self, hbm_budget_bytes: int, max_inflight: int = 256, max_queue: int = 1 << 20,
-                 streams: int = 4, executor: int = EXEC_GPU, sim_bits_per_us: float = 1e4):
+                 streams: int = 4, executor: int = EXEC_GPU, sim_bits_per_us: float = 1e4, sim_fail_every: int = 0):
         cfg = ServerConfig(int(hbm_budget_bytes), int(max_inflight), int(max_queue), int(streams), int(executor),
-                           float(sim_bits_per_us))
+                           float(sim_bits_per_us), int(sim_fail_every))
         h = ctypes.c_void_p()
         _check(lib().pa_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -422,7 +422,11 @@ bool pa_server_s::retire_locked() {
         Batch &b = running[i];
         if (sim) {
             if (now >= b.sim_done) {
-                for (Req *r : b.reqs) complete_locked(r, now, b.stream, PA_OK);
+                for (Req *r : b.reqs) {
+                    const bool fail_it = cfg.sim_fail_every && r->ticket % cfg.sim_fail_every == 0;
+                    if (fail_it && drain_error.empty()) drain_error = "simulated executor failure";
+                    complete_locked(r, now, b.stream, fail_it ? PA_ERR_DEVICE : PA_OK);
+                }
                 b.parts_done = b.parts.size();
                 any = true;
             }

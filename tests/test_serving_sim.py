@@ -211,3 +211,32 @@ def test_budget_from_environment(monkeypatch):
     monkeypatch.delenv("PA_HBM_BUDGET")
     with pa.Server(0, executor=pa.EXEC_SIMULATED) as s:
         assert s.stats()["budget_bytes"] == 16 << 30
+
+
+def test_executor_failures_fail_only_their_requests():
+    # the simulated executor fails every 5th ticket: those requests complete
+    # with PA_ERR_DEVICE, the others as usual; a drain reports the failure
+    # once, and the server keeps serving (no sticky error)
+    with pa.Server(64 << 20, max_inflight=4, executor=pa.EXEC_SIMULATED, sim_bits_per_us=1e6,
+                   sim_fail_every=5) as s:
+        sid = s.register_seed(FAKE_SEED, 2_000_000)
+        tickets = [s.submit(sid, FAKE_KEY, 300_000, 60_000, FAKE_OUT) for _ in range(23)]
+        with pytest.raises(pa.PAError) as e:
+            s.drain()
+        assert e.value.status == pa.PA_ERR_DEVICE
+        for t in tickets:
+            assert s.poll(t)
+            if t % 5 == 0:
+                with pytest.raises(pa.PAError) as e:
+                    s.wait(t)
+                assert e.value.status == pa.PA_ERR_DEVICE
+            else:
+                s.wait(t)
+        st = s.stats()
+        assert st["failed"] == sum(1 for t in tickets if t % 5 == 0) and st["completed"] == 23
+        assert st["inflight"] == 0 and st["bytes_in_flight"] == st["spectrum_bytes"]
+        # later work is served, and a drain with no new failure succeeds
+        t = s.submit(sid, FAKE_KEY, 300_000, 60_000, FAKE_OUT)
+        if t % 5:
+            s.wait(t)
+            s.drain()

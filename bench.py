@@ -218,11 +218,18 @@ def batched_uneven_run(pa, wl, torch, np, count, stream, tune):
             os.environ.pop("PA_BATCH_FORM", None)
         else:
             os.environ["PA_BATCH_FORM"] = old
+    # every 8th block of the last timed run (a lanes-form graph replay,
+    # with the tuned geometries), for the oracle comparison
+    sample = []
+    for i in range(0, count, 8):
+        k_i, s_i = wl.key_and_seed(8, shapes[i].n, shapes[i].m, i)
+        sample.append((k_i, s_i, shapes[i].n, shapes[i].m,
+                       blocks[i][4].cpu().numpy().view(np.uint64)[: wl.words(shapes[i].m)].copy()))
     bms, gms = forms["lanes"]["ms_per_batch"], forms["lanes"]["graph_ms_per_batch"]
     return {"value": bits / (bms * 1e-3) / 1e9, "unit": "Gb/s", "blocks": count, "ms_per_batch": bms,
             "graph_Gbs": bits / (gms * 1e-3) / 1e9, "graph_ms_per_batch": gms, "forms": forms, "tuning": tuning,
             "sum_n": bits, "distinct_lengths": len(lens), "min_len": lens[0], "max_len": lens[-1],
-            "shapes": "n = round(2^U(18,22)), m = max(1, round(n U(0.05, 0.5))), own seed per block"}
+            "shapes": "n = round(2^U(18,22)), m = max(1, round(n U(0.05, 0.5))), own seed per block"}, sample
 
 
 def modified_run(pa, wl, torch, np, n, m, count, stream, steps):
@@ -626,7 +633,8 @@ def main():
         del blocks
         progress("batched: %.3f ms per %d blocks, %.2f Gb/s" % (bms, args.batch, batched["value"]))
 
-    uneven = batched_uneven_run(pa, wl, torch, np, args.batch, stream, not args.no_tune) if args.batch > 0 else None
+    uneven, uneven_io = (batched_uneven_run(pa, wl, torch, np, args.batch, stream, not args.no_tune)
+                         if args.batch > 0 else (None, []))
     if uneven is not None:
         progress("batched uneven: %.3f ms per %d blocks, %.2f Gb/s" % (uneven["ms_per_batch"], args.batch,
                                                                        uneven["value"]))
@@ -667,6 +675,8 @@ def main():
     cases = {"small_block_n262144": [small_io], "large_block_n12800000": [large_io]}
     if batched_io:
         cases["batched_256_n1e6"] = batched_io
+    if uneven_io:
+        cases["batched_uneven_every_8th_block"] = uneven_io
     parity = oracle_parity(cases)
     if args.no_cpu:
         import oracle

@@ -103,3 +103,46 @@ def test_modified_batch_in_each_form(form):
         blocks.append((dev(key), n, dev(v), m, torch.full((wl.words(m),), -1, dtype=torch.int64, device="cuda")))
     pa.modified_toeplitz_hash_batched(blocks)
     _check(blocks, items, form + " modified")
+
+
+def _set_other_geometries(lengths, rng):
+    """A valid non-default batch-class geometry for every length (other row
+    count, wider tiles, another first row round, a fixed row workgroup)."""
+    chosen = {}
+    for L in lengths:
+        a0 = int(pa.plan_info(L)["rows"]).bit_length() - 1
+        cands = [(a, w, rf, rt) for a in (a0 - 1, a0 + 1, a0) for w in (64, 32, 16) for rf in (0, 2, 3, 4)
+                 for rt in (512, 768, 1024, 0)]
+        rng.shuffle(cands)
+        for a, w, rf, rt in cands:
+            if (a, w, rf, rt) == (a0, 16, 0, 0):
+                continue
+            try:
+                pa.tune_set(L, 1, a, w, row_first=rf, row_threads=rt)
+            except pa.PAError:
+                continue
+            chosen[L] = (a, w, rf, rt)
+            break
+    return chosen
+
+
+@pytest.mark.parametrize("form", ["flat", "lanes"])
+def test_uneven_batch_with_tuned_geometries(form, uneven):
+    # the batch kernels with geometries an autotune may pick (each length
+    # its own), direct and replayed, against the oracle
+    os.environ["PA_BATCH_FORM"] = form
+    lengths = sorted({pa.transform_len(n, m) for _, _, n, m, _ in uneven})
+    chosen = _set_other_geometries(lengths, np.random.default_rng(65 if form == "flat" else 66))
+    try:
+        assert len(chosen) == len(lengths)
+        blocks = _blocks(uneven)
+        pa.toeplitz_hash_batched(blocks)
+        _check(blocks, uneven, form + " tuned geometries %s" % chosen)
+        for b in blocks:
+            b[4].fill_(-1)
+        with pa.BatchGraph(blocks) as g:
+            g.launch()
+            _check(blocks, uneven, form + " tuned geometries, graph")
+    finally:
+        for L in lengths:
+            pa.tune_set(L, 1, 0, 0)

@@ -664,11 +664,17 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
     auto pre = [&](int, int, int) PA_INLINE { return NoCtx{}; };
     auto mid = [&](const auto &, auto &, Geo) PA_INLINE {};
     auto load_bits = [&](const auto &, const Geo &g, int l) PA_INLINE -> double {
-        // branch-free: a negative p reads out of range (0); bits >= nbits are masked
-        const int p = (g.q0 + (l * g.J)) * C + c0 + g.c - shift;
-        const int pr = p + ro;
-        const unsigned w = (unsigned)ld32(bits, (pr >> 5) * 4);
-        const unsigned bit = (w >> (pr & 31)) & ((unsigned)p < (unsigned)nbits ? 1u : 0u);
+        // Element l of the item is bit p = p0 + l * J * C.  C is a multiple
+        // of 64, so every element's bit has the same position in its 32-bit
+        // word as element 0's, and the words are J * C / 32 apart.
+        // Branch-free: a negative offset reads out of range (0), and bits
+        // outside [0, nbits) get a zero-width field.
+        const int p0 = g.q0 * C + c0 + g.c - shift;
+        const int jc = g.J * C;
+        const int p = p0 + l * jc;
+        const int pr0 = p0 + ro;
+        const unsigned w = (unsigned)ld32(bits, ((pr0 >> 5) + l * (jc >> 5)) * 4);
+        const unsigned bit = __builtin_amdgcn_ubfe(w, (unsigned)(pr0 & 31), (unsigned)p < (unsigned)nbits ? 1u : 0u);
         return (double)bit;
     };
     auto load_lds = [&](const auto &, const Geo &g, int l) PA_INLINE -> double {
@@ -914,7 +920,6 @@ __global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan
 #pragma unroll
         for (int l = 0; l < group_size(v); ++l) lds[g.lbase + l * g.lstep] = (int)v[l];
     };
-    const int olim = (int)(64 * ((m + 63) / 64));
     const int mm = (int)m, off = (int)off0;
     const int lane = threadIdx.x & 63;
     // modified Toeplitz: output bit i ^= bit i of xor_src (i < m)
@@ -922,13 +927,15 @@ __global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan
     // (a zero-size resource when absent: any access is out of range)
     const rsrc_t xbuf = make_rsrc(job.xor_src, do_xor ? (uint32_t)((m + 63) / 64 * 8) : 0u);
     // bits [pos, pos + W) of xor_src that lie below m, as the low W bits
+    // (0 for a chunk at or past m; a negative pos reads out of range, 0)
     auto xor_chunk = [&](int pos) PA_INLINE -> uint64_t {
+        const int keep = mm - pos;
+        if (keep <= 0) return 0ull;
         uint64_t x;
         if (W == 64)
             x = (uint64_t)(uint32_t)ld32(xbuf, (pos >> 6) * 8) | ((uint64_t)(uint32_t)ld32(xbuf, (pos >> 6) * 8 + 4) << 32);
         else
             x = (uint64_t)((uint32_t)ld32(xbuf, (pos >> 5) * 4) >> (pos & 31 & (W == 16 ? 16 : 0)));
-        const int keep = mm - pos;  // >= 1 for a stored chunk
         if (keep < 64) x &= (1ull << keep) - 1ull;
         return W == 64 ? x : (x & ((1ull << W) - 1ull));
     };
@@ -937,28 +944,51 @@ __global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan
     // diagnostic jobs (job.res_out set): every position's canonical residue,
     // i.e. the exact cyclic convolution, instead of the packed parity window
     const rsrc_t rbuf = make_rsrc(job.res_out, RES ? (uint32_t)(lp.L * 4) : 0u);
+    // The group's elements sit at positions pos0 + l * J * C of the output
+    // window (a wave holds 64 / W groups of W consecutive columns).  One
+    // ballot per element gathers the parities of the exact convolution
+    // values; then the first lane of each group stores its W-bit chunks
+    // (all ballots first: fewer registers than storing after each).
+    // Chunks before the window (negative positions) or past its last word
+    // fall outside the output buffer and are dropped by the hardware range
+    // check; those in the last word past m carry zero bits.
     auto store_bits = [&](NoCtx, auto &v, Geo g) PA_INLINE {
+        constexpr int RHO = (int)(sizeof(v) / sizeof(v[0]));
         if constexpr (RES) {
 #pragma unroll
-            for (int l = 0; l < group_size(v); ++l)
+            for (int l = 0; l < RHO; ++l)
                 st32(rbuf, ((g.q0 + (l * g.J)) * C + c0 + g.c) * 4, (int)canonical(v[l]));
             return;
         }
-        uint32_t par = 0;  // parity of the exact convolution values of this group
+        const int pos0 = g.q0 * C + c0 + g.c - off;
+        const int jc = g.J * C;
+        uint64_t mask[RHO];
 #pragma unroll
-        for (int l = 0; l < group_size(v); ++l) par |= ((uint32_t)(int)canonical(v[l]) & 1u) << l;
+        for (int l = 0; l < RHO; ++l) {
+            const int pos = pos0 + l * jc;
+            mask[l] = __ballot((((int)canonical(v[l]) & 1) != 0) && pos >= 0 && pos < mm);
+        }
+        if (g.c == 0) {
+            if (W == 64) {
 #pragma unroll
-        for (int l = 0; l < group_size(v); ++l) {
-            const int pos = (g.q0 + (l * g.J)) * C + c0 + g.c - off;
-            const uint64_t mask = __ballot(((par >> l) & 1u) && pos >= 0 && pos < mm);
-            if (g.c == 0 && pos >= 0 && pos < olim) {
-                const uint64_t x = (do_xor && pos < mm) ? xor_chunk(pos) : 0ull;
-                if (W == 64)
-                    st64(obuf, (pos >> 6) * 8, mask ^ x);
-                else if (W == 32)
-                    st32(obuf, (pos >> 5) * 4, (int)((uint32_t)(mask >> (lane & 32)) ^ (uint32_t)x));
-                else
-                    st16(obuf, (pos >> 4) * 2, ((unsigned)(mask >> (lane & 48)) ^ (unsigned)x) & 0xFFFFu);
+                for (int l = 0; l < RHO; ++l) {
+                    const int pos = pos0 + l * jc;
+                    st64(obuf, (pos >> 6) * 8, mask[l] ^ (do_xor ? xor_chunk(pos) : 0ull));
+                }
+            } else if (W == 32) {
+#pragma unroll
+                for (int l = 0; l < RHO; ++l) {
+                    const int pos = pos0 + l * jc;
+                    const uint32_t x = do_xor ? (uint32_t)xor_chunk(pos) : 0u;
+                    st32(obuf, (pos >> 5) * 4, (int)((uint32_t)(mask[l] >> (lane & 32)) ^ x));
+                }
+            } else {
+#pragma unroll
+                for (int l = 0; l < RHO; ++l) {
+                    const int pos = pos0 + l * jc;
+                    const unsigned x = do_xor ? (unsigned)xor_chunk(pos) : 0u;
+                    st16(obuf, (pos >> 4) * 2, ((unsigned)(mask[l] >> (lane & 48)) ^ x) & 0xFFFFu);
+                }
             }
         }
     };

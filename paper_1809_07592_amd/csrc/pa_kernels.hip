@@ -433,7 +433,8 @@ __device__ __forceinline__ Geo launder(Geo g) {
 // and CONV modes): load returns the (seed, key) pair of element l, both
 // are transformed, mid/store receive both arrays, and in CONV mode only the
 // key array (index 1) is inverse-transformed.
-template <int MODE, int N3, int N2, bool FIRST, bool LAST, int NA = 1, bool GENJ = false, class Pre, class Load, class Mid,
+template <int MODE, int N3, int N2, bool FIRST, bool LAST, int NA = 1, bool GENJ = false, bool LND = true, class Pre,
+          class Load, class Mid,
           class Store>
 __device__ __forceinline__ void round_io(const CRoundDesc &rd, const CXDesc &xd, const ctwpair *ftw,
                                          const ctwpair *itw, int wsh, Pre &pre, Load &load, Mid &mid,
@@ -461,6 +462,10 @@ __device__ __forceinline__ void round_io(const CRoundDesc &rd, const CXDesc &xd,
         const int jj = LAST ? 0 : (FIRST ? g : (g & (J - 1)));
         const int q0 = FIRST ? jj : (b * rd.M + jj);
         Geo G{q0, J, c, ((q0 + (q0 >> lgp)) << wsh) + c, lstep};
+        // LND: the stores recompute element addresses rather than keep the
+        // loads' (fewer registers; measured better for the row pass, worse
+        // for the inverse column pass)
+        auto keep = [](Geo x) __attribute__((always_inline)) { return LND ? launder(x) : x; };
         auto body = [&](const auto &fs, const auto &is, int bf) __attribute__((always_inline)) {
             auto ctx = pre(c, b, jj);
             RegArrN<N3, N2, NA> v;
@@ -476,17 +481,17 @@ __device__ __forceinline__ void round_io(const CRoundDesc &rd, const CXDesc &xd,
             }
             if constexpr (MODE == MODE_FWD || MODE == MODE_CONV) fwd_stages<N3, N2, 0, NA, FIRST>(v, bf, xd, fs, rd.s0);
             if constexpr (NA == 1) {
-                if constexpr (MODE == MODE_CONV) mid(ctx, v[0], launder(G));
+                if constexpr (MODE == MODE_CONV) mid(ctx, v[0], keep(G));
                 if constexpr (MODE == MODE_INV || MODE == MODE_CONV)
                     inv_stages<N3, N2, Shape<N3, N2>::Q - 1, LAST>(v[0], jj, J, xd, is, rd.s0);
-                store(ctx, v[0], launder(G));
+                store(ctx, v[0], keep(G));
             } else {
                 if constexpr (MODE == MODE_CONV) {
-                    mid(ctx, v, launder(G));
+                    mid(ctx, v, keep(G));
                     inv_stages<N3, N2, Shape<N3, N2>::Q - 1, LAST>(v[1], jj, J, xd, is, rd.s0);
-                    store(ctx, v[1], launder(G));
+                    store(ctx, v[1], keep(G));
                 } else {
-                    store(ctx, v, launder(G));
+                    store(ctx, v, keep(G));
                 }
             }
         };
@@ -517,7 +522,8 @@ __device__ __forceinline__ void round_io(const CRoundDesc &rd, const CXDesc &xd,
 // bounds the kinds the plan can give this pass (kColMaxLg / kRowMaxLg).
 // MIX: the plan may also give this pass rounds that hold the last radix-3
 // stage (kinds 3 and 6, after a 9-value first round).
-template <int MODE, bool FIRST, bool LAST, int MAXLG, int NA = 1, bool MIX = false, class Pre, class Load, class Mid,
+template <int MODE, bool FIRST, bool LAST, int MAXLG, int NA = 1, bool MIX = false, bool LND = true, class Pre,
+          class Load, class Mid,
           class Store>
 __device__ __forceinline__ void round_p2(const CXDesc &xd, const ctwpair *ftw,
                                          const ctwpair *itw, int r, int wsh, Pre &pre, Load &load,
@@ -525,18 +531,18 @@ __device__ __forceinline__ void round_p2(const CXDesc &xd, const ctwpair *ftw,
     const CRoundDesc &rd = xd.round[r];
     switch (rd.kind) {
         case 4:
-            if constexpr (MIX) round_io<MODE, 1, 0, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store);
+            if constexpr (MIX) round_io<MODE, 1, 0, FIRST, LAST, NA, false, LND>(rd, xd, ftw, itw, wsh, pre, load, mid, store);
             break;
         case 5:
-            if constexpr (MIX) round_io<MODE, 1, 1, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store);
+            if constexpr (MIX) round_io<MODE, 1, 1, FIRST, LAST, NA, false, LND>(rd, xd, ftw, itw, wsh, pre, load, mid, store);
             break;
 
-        case 0: round_io<MODE, 0, 1, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
-        case 1: round_io<MODE, 0, 2, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
-        case 2: round_io<MODE, 0, 3, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
+        case 0: round_io<MODE, 0, 1, FIRST, LAST, NA, false, LND>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
+        case 1: round_io<MODE, 0, 2, FIRST, LAST, NA, false, LND>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
+        case 2: round_io<MODE, 0, 3, FIRST, LAST, NA, false, LND>(rd, xd, ftw, itw, wsh, pre, load, mid, store); break;
         case 3:
             if constexpr (MAXLG >= 4)
-                round_io<MODE, 0, 4, FIRST, LAST, NA>(rd, xd, ftw, itw, wsh, pre, load, mid, store);
+                round_io<MODE, 0, 4, FIRST, LAST, NA, false, LND>(rd, xd, ftw, itw, wsh, pre, load, mid, store);
             break;
         default: break;
     }
@@ -993,16 +999,16 @@ __global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan
         }
     };
     if (nr == 1) {
-        round_p2<MODE_INV, true, true, MAXLG>(xd, ftw, itw, 0, wsh, pre, load_glb, mid, store_bits);
+        round_p2<MODE_INV, true, true, MAXLG, 1, false, false>(xd, ftw, itw, 0, wsh, pre, load_glb, mid, store_bits);
         return;
     }
-    round_p2<MODE_INV, false, true, MAXLG>(xd, ftw, itw, nr - 1, wsh, pre, load_glb, mid, store_lds);
+    round_p2<MODE_INV, false, true, MAXLG, 1, false, false>(xd, ftw, itw, nr - 1, wsh, pre, load_glb, mid, store_lds);
     __syncthreads();
     for (int r = nr - 2; r >= 1; --r) {
-        round_p2<MODE_INV, false, false, MAXLG>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
+        round_p2<MODE_INV, false, false, MAXLG, 1, false, false>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
         __syncthreads();
     }
-    round_p2<MODE_INV, true, false, MAXLG>(xd, ftw, itw, 0, wsh, pre, load_lds, mid, store_bits);
+    round_p2<MODE_INV, true, false, MAXLG, 1, false, false>(xd, ftw, itw, 0, wsh, pre, load_lds, mid, store_bits);
 }
 
 // ----------------------------------------------------------------- launchers

@@ -385,6 +385,9 @@ def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30, streams=4
         offs.append(tot)
         tot += wl.words(r.m)
     outs = torch.zeros(tot, dtype=torch.int64, device="cuda")
+    # the server's streams are not ordered after torch's: the seeds, keys
+    # and zeroed outputs must be complete before the server touches them
+    torch.cuda.synchronize()
 
     def out_ptr(i):
         return outs.data_ptr() + 8 * offs[i]

@@ -437,7 +437,11 @@ pa_status pa_profile_collect(pa_kernel_stat *stats, uint32_t capacity, uint32_t 
  * same block.
  *
  * Pointers passed to submit are device pointers owned by the caller and
- * must stay valid until the request completes.  executor =
+ * must stay valid until the request completes.  The server's streams are
+ * not ordered after any caller stream: the seed bits (at registration) and
+ * the key bits (at submit) must already be complete in device memory, e.g.
+ * after synchronizing the stream that wrote them, and no other work may
+ * write out_bits until the request completes.  executor =
  * PA_EXEC_SIMULATED runs the scheduler without touching the device
  * (requests complete after n / sim_bits_per_us microseconds, outputs are
  * not written, spectra take pool memory but are not built): for testing

@@ -35,10 +35,12 @@ def test_served_results_equal_alone_and_oracle():
         ids = [srv.register_seed(dseeds[k], seeds[k].size * 64) for k in range(2)]
         outs, tickets, keep = [], [], []
         for sid, key, n, m in reqs:
-            dk = dev(key)
-            out = torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")
-            keep.append(dk)
-            outs.append(out)
+            keep.append(dev(key))
+            outs.append(torch.zeros(wl.words(m), dtype=torch.int64, device="cuda"))
+        # the server's streams are not ordered after torch's: inputs must be
+        # complete, and no zero-fill pending, before the requests go in
+        torch.cuda.synchronize()
+        for (sid, key, n, m), dk, out in zip(reqs, keep, outs):
             tickets.append(srv.submit(ids[sid], dk, n, m, out))
         srv.drain()
         st = srv.stats()
@@ -75,6 +77,7 @@ def test_small_request_does_not_wait_for_a_large_one():
             ks = dev(wl.random_bits(n_small, wl.rng(32, wl.ROLE_KEY, 2 * i + 1)))
             ob = torch.zeros(wl.words(m_big), dtype=torch.int64, device="cuda")
             os_ = torch.zeros(wl.words(m_small), dtype=torch.int64, device="cuda")
+            torch.cuda.current_stream().synchronize()   # inputs complete before the server's streams read them
             tb = srv.submit(sid, kb, n_big, m_big, ob)
             ts = srv.submit(sid, ks, n_small, m_small, os_)
             pairs.append((tb, ts, kb, ks, ob, os_))
@@ -113,6 +116,8 @@ def test_spectra_built_on_demand_evicted_and_rebuilt_under_a_small_budget():
             out = torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")
             keys.append(key)
             outs.append(out)
+            # torch's stream only: earlier requests stay on the device
+            torch.cuda.current_stream().synchronize()
             reqs.append((sid, n, m, srv.submit(ids[sid], key, n, m, out)))
         srv.drain()
         st = srv.stats()

@@ -32,6 +32,9 @@ def test_serving_stream_matches_alone_and_oracle():
         offs.append(tot)
         tot += wl.words(r.m)
     served = torch.zeros(tot, dtype=torch.int64, device="cuda")
+    # the server's streams are not ordered after torch's: seeds, keys and the
+    # zeroed outputs must be complete before the server reads or writes them
+    torch.cuda.synchronize()
     with pa.Server(16 << 30, max_inflight=512, streams=4) as srv:
         ids = [srv.register_seed(d, SEED_BITS) for d in dseeds]
         for i, r in enumerate(reqs):

@@ -42,7 +42,8 @@ class PlanInfo(ctypes.Structure):
                 ("tile_width", ctypes.c_uint32), ("col_tiles", ctypes.c_uint32), ("col_threads", ctypes.c_uint32),
                 ("row_threads", ctypes.c_uint32), ("col_lds_bytes", ctypes.c_uint32),
                 ("row_lds_bytes", ctypes.c_uint32), ("col_rounds", ctypes.c_uint32), ("row_rounds", ctypes.c_uint32),
-                ("col_round_size", ctypes.c_uint32 * 6), ("row_round_size", ctypes.c_uint32 * 6)]
+                ("col_round_size", ctypes.c_uint32 * 6), ("row_round_size", ctypes.c_uint32 * 6),
+                ("row_shape", ctypes.c_uint32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -96,6 +96,83 @@ struct XDesc {
     const double2 *inv_tw;    // device: inverse DIT twiddles (w, w/P)
 };
 
+constexpr int kind_index(int n3, int n2) {
+    for (int i = 0; i < kNumKinds; ++i)
+        if (kKindN3[i] == n3 && kKindN2[i] == n2) return i;
+    return -1;
+}
+
+constexpr int log2_exact(long long v) {
+    int k = 0;
+    while (v > 1 && (v & 1) == 0) {
+        v >>= 1;
+        ++k;
+    }
+    return k;
+}
+
+// Descriptor fields (everything but the twiddle tables) of a length-N
+// transform whose nrounds register rounds hold rn3[r] radix-3 and rn2[r]
+// radix-2 stages, the radix-3 stages first.  Returns false when the rounds
+// do not multiply to N, a round has no kind, or a round after the first
+// would need a stride that is not a power of two.  The planner builds every
+// descriptor with it, and the row kernels' fixed shapes are built with it
+// at compile time, so the two agree field by field.
+constexpr bool describe_rounds(int N, int nrounds, const int *rn3, const int *rn2, XDesc &x) {
+    if (nrounds < 1 || nrounds > kMaxRounds || N < 2) return false;
+    int k3 = 0, k2 = 0;
+    long long prod = 1;
+    for (int r = 0; r < nrounds; ++r) {
+        if (rn3[r] < 0 || rn2[r] < 0) return false;
+        k3 += rn3[r];
+        k2 += rn2[r];
+        for (int i = 0; i < rn3[r]; ++i) prod *= 3;
+        prod <<= rn2[r];
+    }
+    if (prod != N || k3 + k2 > kMaxStages) return false;
+    x.N = N;
+    x.nstages = k3 + k2;
+    x.nrounds = nrounds;
+    int s = 0;
+    long long before = 1;  // product of the radices of the stages before s
+    for (int r = 0; r < nrounds; ++r) {
+        int rho = 1;
+        for (int i = 0; i < rn3[r]; ++i) rho *= 3;
+        rho <<= rn2[r];
+        RoundDesc &rd = x.round[r];
+        rd.kind = kind_index(rn3[r], rn2[r]);
+        if (rd.kind < 0) return false;
+        rd.s0 = s;
+        rd.M = (int)(N / before);
+        const int jl = rd.M / rho;
+        // every round but the first needs a power-of-two stride (its block
+        // index is a shift of the item); the first may be 3 * 2^k
+        if (jl * rho != rd.M || (r > 0 && (jl & (jl - 1)))) return false;
+        rd.J = jl;
+        rd.jl_log2 = log2_exact(jl);
+        rd.ngroups = N / rho;
+        s += rn3[r] + rn2[r];
+        before *= rho;
+    }
+    const RoundDesc &last = x.round[nrounds - 1];
+    const int rho_last = last.M / last.J;
+    x.lgpad = (rho_last & (rho_last - 1)) ? 4 : log2_exact(rho_last);  // a single mixed round: any pad works
+    // twiddle-table offsets: stage st has before(st) * (r - 1) forward
+    // factors and J(st) * (r - 1) inverse ones
+    int fo = 0, io = 0;
+    before = 1;
+    for (int st = 0; st < x.nstages; ++st) {
+        const int r = st < k3 ? 3 : 2;
+        const long long J = N / (before * r);
+        x.fwd_off[st] = fo;
+        x.inv_off[st] = io;
+        fo += (int)(before * (r - 1));
+        io += (int)(J * (r - 1));
+        before *= r;
+    }
+    return true;
+}
+
 // Four-step layout of one transform length L = R * C (R = 2^a rows,
 // C = 3^b * 2^c columns, row-major R x C view of the length-L sequence).
 // Lives in device memory; kernels read it through a pointer.

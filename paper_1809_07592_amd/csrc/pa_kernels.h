@@ -63,4 +63,8 @@ int col_wgs_per_cu(bool inverse, int lg, int threads, size_t lds);
 // example inside a stream capture).
 hipError_t warm_launch_state(const LenPlan &hp);
 
+// The fixed row-kernel shape whose descriptor equals x field by field, or
+// 0 (the general row kernel, which reads the descriptor from the plan).
+int row_shape_id(const XDesc &x);
+
 }  // namespace pa

@@ -26,6 +26,8 @@
 
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "pa_internal.h"
 #include "pa_kernels.h"
 
@@ -328,6 +330,127 @@ __device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, 
     }
 }
 
+// ------------------------------------------------ transform descriptors
+//
+// The stage helpers and round drivers read a transform's descriptor
+// through these accessors: from a plan in device memory (CXDesc), or from
+// a fixed row shape whose fields are compile-time constants (FixedRow).
+
+__device__ __forceinline__ int lgpad_of(const CXDesc &x) { return x.lgpad; }
+__device__ __forceinline__ int fwd_off_of(const CXDesc &x, int s) { return x.fwd_off[s]; }
+__device__ __forceinline__ int inv_off_of(const CXDesc &x, int s) { return x.inv_off[s]; }
+
+// Row transforms of fixed shape.  A plan whose row descriptor equals one of
+// these field by field runs a row kernel compiled for it: every round's
+// kind, stride, group count and twiddle offset is then a constant, so an
+// element's LDS address is one base register plus an immediate offset (a
+// run-time stride costs an integer add per access), and the seed and key
+// rows share that base.  Shape 0 is the general kernel, which reads the
+// descriptor from the plan.  The shapes are the row lengths of the
+// commonest transform lengths under their default geometry.
+struct RowShapeSpec {
+    int C, nrounds;
+    int n3[kMaxRounds], n2[kMaxRounds];
+};
+// (The default geometries of the lengths 2^18 .. 27 * 2^19 use these.)
+constexpr RowShapeSpec kRowShapeSpec[] = {
+    {0, 0, {}, {}},
+    {2048, 4, {0, 0, 0, 0}, {2, 3, 3, 3}},        // 4 8 8 8
+    {2304, 4, {2, 0, 0, 0}, {0, 3, 3, 2}},        // 9 8 8 4
+    {3072, 4, {1, 0, 0, 0}, {1, 3, 3, 3}},        // 6 8 8 8
+    {3456, 4, {2, 1, 0, 0}, {0, 1, 3, 3}},        // 9 6 8 8
+    {4096, 4, {0, 0, 0, 0}, {3, 3, 3, 3}},        // 8 8 8 8
+    {4608, 4, {2, 0, 0, 0}, {0, 3, 3, 3}},        // 9 8 8 8
+    {6144, 4, {1, 0, 0, 0}, {2, 3, 3, 3}},        // 12 8 8 8
+    {6912, 5, {2, 1, 0, 0, 0}, {0, 1, 3, 2, 2}},  // 9 6 8 4 4
+    {9216, 5, {2, 0, 0, 0, 0}, {0, 3, 3, 2, 2}},  // 9 8 8 4 4
+    {13824, 5, {2, 1, 0, 0, 0}, {0, 1, 3, 3, 2}}, // 9 6 8 8 4
+};
+constexpr int kNumRowShapes = (int)(sizeof(kRowShapeSpec) / sizeof(kRowShapeSpec[0]));
+
+// Descriptor of shape i (all zero for i = 0 or an invalid spec).  Only
+// ever evaluated in constant expressions on the device: a constexpr object
+// that device code refers to becomes a host-writable constant that the
+// compiler cannot fold.
+constexpr XDesc row_shape_desc(int i) {
+    XDesc x{};
+    if (i > 0 && i < kNumRowShapes &&
+        !describe_rounds(kRowShapeSpec[i].C, kRowShapeSpec[i].nrounds, kRowShapeSpec[i].n3, kRowShapeSpec[i].n2, x))
+        x = XDesc{};
+    return x;
+}
+
+template <int SH>
+struct FixedRow {
+    static constexpr int N = row_shape_desc(SH).N;
+    static constexpr int nrounds = row_shape_desc(SH).nrounds;
+    static constexpr int nstages = row_shape_desc(SH).nstages;
+    static constexpr int lgpad = row_shape_desc(SH).lgpad;
+    static constexpr int first_kind = row_shape_desc(SH).round[0].kind;
+    static constexpr int lds_ints = N + (N >> lgpad);
+    static constexpr int k3 = kRowShapeSpec[SH].n3[0] + kRowShapeSpec[SH].n3[1];
+    // product of the radices before stage s (radix-3 stages first); the
+    // forward table holds before(s) * (r - 1) factors per stage and the
+    // inverse table N / before(s + 1) * (r - 1), so both offsets are
+    // telescoping sums
+    static constexpr int before(int s) {
+        int p = 1;
+        for (int i = 0; i < s; ++i) p *= i < k3 ? 3 : 2;
+        return p;
+    }
+    static constexpr int fwd_off(int s) { return before(s) - 1; }
+    static constexpr int inv_off(int s) { return N - N / before(s); }
+    static constexpr bool valid() {
+        const XDesc x = row_shape_desc(SH);
+        if (x.nrounds == 0 || kRowShapeSpec[SH].n3[2] != 0) return false;
+        for (int s = 0; s < x.nstages; ++s)
+            if (x.fwd_off[s] != fwd_off(s) || x.inv_off[s] != inv_off(s)) return false;
+        return true;
+    }
+};
+
+template <int SH, int R>
+struct FixedRound {
+    static constexpr int kind = row_shape_desc(SH).round[R].kind;
+    static constexpr int s0 = row_shape_desc(SH).round[R].s0;
+    static constexpr int jl_log2 = row_shape_desc(SH).round[R].jl_log2;
+    static constexpr int J = row_shape_desc(SH).round[R].J;
+    static constexpr int M = row_shape_desc(SH).round[R].M;
+    static constexpr int ngroups = row_shape_desc(SH).round[R].ngroups;
+};
+
+template <int SH>
+__device__ __forceinline__ constexpr int lgpad_of(const FixedRow<SH> &) { return FixedRow<SH>::lgpad; }
+template <int SH>
+__device__ __forceinline__ constexpr int fwd_off_of(const FixedRow<SH> &, int s) { return FixedRow<SH>::fwd_off(s); }
+template <int SH>
+__device__ __forceinline__ constexpr int inv_off_of(const FixedRow<SH> &, int s) { return FixedRow<SH>::inv_off(s); }
+
+template <int SH>
+constexpr bool fixed_rows_valid() {
+    if constexpr (SH < kNumRowShapes) return FixedRow<SH>::valid() && fixed_rows_valid<SH + 1>();
+    return true;
+}
+static_assert(fixed_rows_valid<1>(), "a fixed row shape has no valid descriptor");
+
+// The fixed shape (or 0) whose descriptor equals x.
+int row_shape_id(const XDesc &x);
+
+int row_shape_id(const XDesc &x) {
+    for (int i = 1; i < kNumRowShapes; ++i) {
+        const XDesc s = row_shape_desc(i);
+        bool same = s.N == x.N && s.nstages == x.nstages && s.nrounds == x.nrounds && s.lgpad == x.lgpad;
+        for (int r = 0; same && r < s.nrounds; ++r) {
+            const RoundDesc &a = s.round[r], &b = x.round[r];
+            same = a.kind == b.kind && a.s0 == b.s0 && a.jl_log2 == b.jl_log2 && a.J == b.J && a.M == b.M &&
+                   a.ngroups == b.ngroups;
+        }
+        for (int st = 0; same && st < s.nstages; ++st) same = s.fwd_off[st] == x.fwd_off[st] && s.inv_off[st] == x.inv_off[st];
+        if (same) return i;
+    }
+    return 0;
+}
+
 // Rounds that keep a scheduling fence between stages: the row pass's
 // mixed first rounds of 9 and of 18 to 27 values, where hoisting every
 // stage's twiddle loads raises register use enough to cost occupancy.
@@ -338,19 +461,19 @@ template <int N3, int N2>
 constexpr bool kStageFence = Shape<N3, N2>::RHO > 8 && Shape<N3, N2>::RHO != 12 && Shape<N3, N2>::RHO != 16;
 
 // FIRST: the round holds the transform's first stage (K = 0 is trivial).
-template <int N3, int N2, int K, int NA, bool FIRST = false, class TW>
-__device__ __forceinline__ void fwd_stages(RegArrN<N3, N2, NA> &v, int b, const CXDesc &xd, const TW &tw,
+template <int N3, int N2, int K, int NA, bool FIRST = false, class TW, class XD>
+__device__ __forceinline__ void fwd_stages(RegArrN<N3, N2, NA> &v, int b, const XD &xd, const TW &tw,
                                            int s0) {
     if constexpr (K < Shape<N3, N2>::Q) {
-        fwd_stage<N3, N2, K, NA, FIRST && K == 0>(v, b, tw, xd.fwd_off[s0 + K]);
+        fwd_stage<N3, N2, K, NA, FIRST && K == 0>(v, b, tw, fwd_off_of(xd, s0 + K));
         if constexpr (kStageFence<N3, N2>) __builtin_amdgcn_sched_barrier(0);
         fwd_stages<N3, N2, K + 1, NA, FIRST>(v, b, xd, tw, s0);
     }
 }
 
 // Every factor of a non-first forward round's stages for block b.
-template <int N3, int N2, int K = 0>
-__device__ __forceinline__ void fwd_tw_fetch(TwRegs<TwSlots<N3, N2>::F> &o, int b, const CXDesc &xd,
+template <int N3, int N2, int K = 0, class XD>
+__device__ __forceinline__ void fwd_tw_fetch(TwRegs<TwSlots<N3, N2>::F> &o, int b, const XD &xd,
                                              const ctwpair *tw, int s0) {
     using S = Shape<N3, N2>;
     if constexpr (K < S::Q) {
@@ -360,14 +483,14 @@ __device__ __forceinline__ void fwd_tw_fetch(TwRegs<TwSlots<N3, N2>::F> &o, int 
 #pragma unroll
             for (int e = 0; e < r - 1; ++e)
                 o.w[TwSlots<N3, N2>::fbase(K) + sb * (r - 1) + e] =
-                    ld_const(tw, xd.fwd_off[s0 + K] + (b * rb + sb) * (r - 1) + e);
+                    ld_const(tw, fwd_off_of(xd, s0 + K) + (b * rb + sb) * (r - 1) + e);
         fwd_tw_fetch<N3, N2, K + 1>(o, b, xd, tw, s0);
     }
 }
 
 // Every factor of a non-last inverse round's stages for position jj.
-template <int N3, int N2, int K = Shape<N3, N2>::Q - 1>
-__device__ __forceinline__ void inv_tw_fetch(TwRegs<TwSlots<N3, N2>::I> &o, int jj, int jlast, const CXDesc &xd,
+template <int N3, int N2, int K = Shape<N3, N2>::Q - 1, class XD>
+__device__ __forceinline__ void inv_tw_fetch(TwRegs<TwSlots<N3, N2>::I> &o, int jj, int jlast, const XD &xd,
                                              const ctwpair *tw, int s0) {
     using S = Shape<N3, N2>;
     if constexpr (K >= 0) {
@@ -377,17 +500,17 @@ __device__ __forceinline__ void inv_tw_fetch(TwRegs<TwSlots<N3, N2>::I> &o, int 
 #pragma unroll
             for (int e = 0; e < r - 1; ++e)
                 o.w[TwSlots<N3, N2>::ibase(K) + x * (r - 1) + e] =
-                    ld_const(tw, xd.inv_off[s0 + K] + (x * jlast + jj) * (r - 1) + e);
+                    ld_const(tw, inv_off_of(xd, s0 + K) + (x * jlast + jj) * (r - 1) + e);
         inv_tw_fetch<N3, N2, K - 1>(o, jj, jlast, xd, tw, s0);
     }
 }
 
 // LAST: the round holds the transform's last stage (K = Q-1 is trivial).
-template <int N3, int N2, int K, bool LAST = false, class TW>
-__device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast, const CXDesc &xd, const TW &tw,
+template <int N3, int N2, int K, bool LAST = false, class TW, class XD>
+__device__ __forceinline__ void inv_stages(RegArr<N3, N2> &v, int jj, int jlast, const XD &xd, const TW &tw,
                                            int s0) {
     if constexpr (K >= 0) {
-        inv_stage<N3, N2, K, LAST && K == Shape<N3, N2>::Q - 1>(v, jj, jlast, tw, xd.inv_off[s0 + K]);
+        inv_stage<N3, N2, K, LAST && K == Shape<N3, N2>::Q - 1>(v, jj, jlast, tw, inv_off_of(xd, s0 + K));
         if constexpr (kStageFence<N3, N2>) __builtin_amdgcn_sched_barrier(0);
         inv_stages<N3, N2, K - 1, LAST>(v, jj, jlast, xd, tw, s0);
     }
@@ -435,17 +558,16 @@ __device__ __forceinline__ Geo launder(Geo g) {
 // and CONV modes): load returns the (seed, key) pair of element l, both
 // are transformed, mid/store receive both arrays, and in CONV mode only the
 // key array (index 1) is inverse-transformed.
-template <int MODE, int N3, int N2, bool FIRST, bool LAST, int NA = 1, bool GENJ = false, bool LND = true, class Pre,
-          class Load, class Mid,
-          class Store>
-__device__ __forceinline__ void round_io(const CRoundDesc &rd, const CXDesc &xd, const ctwpair *ftw,
+template <int MODE, int N3, int N2, bool FIRST, bool LAST, int NA = 1, bool GENJ = false, bool LND = true, class RD,
+          class XD, class Pre, class Load, class Mid, class Store>
+__device__ __forceinline__ void round_io(const RD &rd, const XD &xd, const ctwpair *ftw,
                                          const ctwpair *itw, int wsh, Pre &pre, Load &load, Mid &mid,
                                          Store &store) {
     constexpr int RHO = Shape<N3, N2>::RHO;
     const int W = 1 << wsh;
     const int items = rd.ngroups << wsh;
     const int jl = LAST ? 0 : rd.jl_log2;
-    const int lgp = xd.lgpad;
+    const int lgp = lgpad_of(xd);
     // GENJ: the first round's stride may be 3 * 2^k (a multiple of 2^lgp, so
     // the padded LDS index stays affine in l); other strides are powers of two
     const int J = LAST ? 1 : ((FIRST && GENJ) ? rd.J : 1 << jl);
@@ -735,6 +857,45 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
 // group is q = jj + l*J0 (J0 = C/rho0): its inverse twist is
 // beta(jj) * alpha(l), beta(jj) = omega_L^(-k1 jj), alpha(l) =
 // omega_L^(-k1 J0 l) / L.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for_up(F &&f) {  // B, B+1, ..., E-1
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for_up<B + 1, E>(f);
+    }
+}
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for_down(F &&f) {  // B, B-1, ..., E
+    if constexpr (B >= E) {
+        f(std::integral_constant<int, B>{});
+        static_for_down<B - 1, E>(f);
+    }
+}
+
+// Round r (an int, or a std::integral_constant for a fixed shape) of the
+// row transform; r = 0 is the first round, whose kind is FK.
+template <int MODE, bool LAST, int NA, int FK, int SH, class R, class Pre, class Load, class Mid, class Store>
+__device__ __forceinline__ void row_round(const CXDesc &xd, const ctwpair *ftw, const ctwpair *itw, R r, Pre &pre,
+                                          Load &load, Mid &mid, Store &store) {
+    if constexpr (SH == 0) {
+        // a 9-value first round may be followed by a round with the last
+        // radix-3 stage (lengths with 27 | C)
+        constexpr bool kMix = kKindN3[FK] == 2;
+        if constexpr (std::is_same<R, std::integral_constant<int, 0>>::value)
+            round_fk<MODE, FK, LAST, NA>(xd, ftw, itw, 0, pre, load, mid, store);
+        else
+            round_p2<MODE, false, LAST, kRowMaxLg, NA, kMix>(xd, ftw, itw, (int)r, 0, pre, load, mid, store);
+    } else {
+        using RD = FixedRound<SH, R::value>;
+        constexpr int k = RD::kind;
+        constexpr bool first = R::value == 0;
+        // a 9-value first round leaves a stride of 3 * 2^k
+        round_io<MODE, kKindN3[k], kKindN2[k], first, LAST, NA, first && kKindN3[k] == 2>(
+            RD{}, FixedRow<SH>{}, ftw, itw, 0, pre, load, mid, store);
+    }
+}
+
 struct TwCtx {
     double2 beta;
 };
@@ -742,7 +903,7 @@ struct TwCtx {
 // Grid: (rows, jobs) with plan[0] the launch's plan, or, in a flat launch,
 // one dimension covering every job's rows, each job with its own plan,
 // plan[job.plan_idx].
-template <int FK>
+template <int FK, int SH>
 __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ plan, JobArgs ja, int mode) {
     uint32_t jidx, row;
     const LenPlan *pp = plan;
@@ -758,9 +919,6 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
     const CPlan &lp = *(const CPlan *)pp;
     const CXDesc &xd = lp.row;
     const ctwpair *ftw = (const ctwpair *)uni(xd.fwd_tw), *itw = (const ctwpair *)uni(xd.inv_tw);
-    // a 9-value first round may be followed by a round with the last
-    // radix-3 stage (lengths with 27 | C)
-    constexpr bool kMix = kKindN3[FK] == 2;
     const JobDesc job = job_of(ja, jidx);
     const int C = lp.C, nr = xd.nrounds;
     const size_t rbase = (size_t)row * (size_t)C;
@@ -768,13 +926,35 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
     const rsrc_t rowS = make_rsrc(job.S + rbase, (uint32_t)C * 4);
     const rsrc_t rowH = make_rsrc(job.Shat + rbase, (uint32_t)C * 4);
     int *lds_a = pa_lds;
-    int *lds_s = pa_lds + lp.row_lds;
+    int *lds_s = pa_lds + (SH ? FixedRow<SH>::lds_ints : lp.row_lds);
     const uint32_t k1 = __builtin_bitreverse32(row) >> (32 - lp.log2R);
     const uint32_t L = (uint32_t)lp.L;
     // the row's alpha factors are the same for every item: scalar loads
     const ctwpair *ai = (const ctwpair *)(uni(lp.alpha_i) + (size_t)k1 * lp.rho0);
     const rsrc_t rs_lo = make_rsrc(uni(lp.twist_lo), 4096 * 16);
     const rsrc_t rs_hi = make_rsrc(uni(lp.twist_hi), (uint32_t)((lp.L + 4095) / 4096) * 16);
+
+    // the rounds between the first and the last, in either direction, and
+    // the last round's index
+    auto mid_rounds_up = [&](auto &&f) PA_INLINE {
+        if constexpr (SH == 0) {
+            for (int r = 1; r < nr - 1; ++r) f(r);
+        } else {
+            static_for_up<1, FixedRow<SH>::nrounds - 1>(f);
+        }
+    };
+    auto mid_rounds_down = [&](auto &&f) PA_INLINE {
+        if constexpr (SH == 0) {
+            for (int r = nr - 2; r >= 1; --r) f(r);
+        } else {
+            static_for_down<FixedRow<SH>::nrounds - 2, 1>(f);
+        }
+    };
+    auto last_round = [&]() PA_INLINE {
+        if constexpr (SH == 0) return nr - 1;
+        else return std::integral_constant<int, FixedRow<SH>::nrounds - 1>{};
+    };
+    const std::integral_constant<int, 0> first_round{};
 
     auto pre_none = [&](int, int, int) PA_INLINE { return NoCtx{}; };
     auto pre_inv = [&](int, int, int jj) PA_INLINE {
@@ -794,12 +974,12 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
             for (int l = 0; l < group_size(v); ++l) lds[g.lbase + l * g.lstep] = (int)v[l];
         };
         auto load_l = [&](auto, const Geo &g, int l) PA_INLINE -> double { return (double)lds[g.lbase + l * g.lstep]; };
-        round_fk<MODE_FWD, FK, false>(xd, ftw, itw, 0, pre_none, load_g, mid_none, store_l);
+        row_round<MODE_FWD, false, 1, FK, SH>(xd, ftw, itw, first_round, pre_none, load_g, mid_none, store_l);
         __syncthreads();
-        for (int r = 1; r < nr - 1; ++r) {
-            round_p2<MODE_FWD, false, false, kRowMaxLg, 1, kMix>(xd, ftw, itw, r, 0, pre_none, load_l, mid_none, store_l);
+        mid_rounds_up([&](auto r) PA_INLINE {
+            row_round<MODE_FWD, false, 1, FK, SH>(xd, ftw, itw, r, pre_none, load_l, mid_none, store_l);
             __syncthreads();
-        }
+        });
     };
     auto load_la = [&](auto, const Geo &g, int l) PA_INLINE -> double { return (double)lds_a[g.lbase + l * g.lstep]; };
     auto store_la = [&](auto, auto &v, Geo g) PA_INLINE {
@@ -813,7 +993,7 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
 #pragma unroll
             for (int l = 0; l < group_size(v); ++l) st32_wt(rowS, (g.q0 + (l * g.J)) * 4, (int)reduce_sym(v[l]));
         };
-        round_p2<MODE_FWD, false, true, kRowMaxLg, 1, kMix>(xd, ftw, itw, nr - 1, 0, pre_none, load_la, mid_none, store_g);
+        row_round<MODE_FWD, true, 1, FK, SH>(xd, ftw, itw, last_round(), pre_none, load_la, mid_none, store_g);
         return;
     }
     // Plain path: each work item carries the seed and key groups of one
@@ -846,14 +1026,13 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
                 v[1][l] = mulmod(v[1][l], sp, sp * kPinv);
             }
         };
-        round_fk<MODE_FWD, FK, false, 2>(xd, ftw, itw, 0, pre_none, load_g2, mid_none, store_l2);
+        row_round<MODE_FWD, false, 2, FK, SH>(xd, ftw, itw, first_round, pre_none, load_g2, mid_none, store_l2);
         __syncthreads();
-        for (int r = 1; r < nr - 1; ++r) {
-            round_p2<MODE_FWD, false, false, kRowMaxLg, 2, kMix>(xd, ftw, itw, r, 0, pre_none, load_l2, mid_none, store_l2);
+        mid_rounds_up([&](auto r) PA_INLINE {
+            row_round<MODE_FWD, false, 2, FK, SH>(xd, ftw, itw, r, pre_none, load_l2, mid_none, store_l2);
             __syncthreads();
-        }
-        round_p2<MODE_CONV, false, true, kRowMaxLg, 2, kMix>(xd, ftw, itw, nr - 1, 0, pre_none, load_l2, mid_mul2,
-                                                        store_la);
+        });
+        row_round<MODE_CONV, true, 2, FK, SH>(xd, ftw, itw, last_round(), pre_none, load_l2, mid_mul2, store_la);
     } else {
         // plan path (mode 0): the key row against the resident spectrum
         forward_head(rowA, lds_a);
@@ -864,13 +1043,13 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
                 v[l] = mulmod(v[l], s, s * kPinv);
             }
         };
-        round_p2<MODE_CONV, false, true, kRowMaxLg, 1, kMix>(xd, ftw, itw, nr - 1, 0, pre_none, load_la, mid_mul, store_la);
+        row_round<MODE_CONV, true, 1, FK, SH>(xd, ftw, itw, last_round(), pre_none, load_la, mid_mul, store_la);
     }
     __syncthreads();
-    for (int r = nr - 2; r >= 1; --r) {
-        round_p2<MODE_INV, false, false, kRowMaxLg, 1, kMix>(xd, ftw, itw, r, 0, pre_none, load_la, mid_none, store_la);
+    mid_rounds_down([&](auto r) PA_INLINE {
+        row_round<MODE_INV, false, 1, FK, SH>(xd, ftw, itw, r, pre_none, load_la, mid_none, store_la);
         __syncthreads();
-    }
+    });
     auto store_tw = [&](TwCtx t, auto &v, Geo g) PA_INLINE {
 #pragma unroll
         for (int l = 0; l < group_size(v); ++l) {
@@ -879,7 +1058,7 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
             st32_wt(rowA, (g.q0 + (l * g.J)) * 4, (int)mulmod(y, t.beta.x, t.beta.y));
         }
     };
-    round_fk<MODE_INV, FK, false>(xd, ftw, itw, 0, pre_inv, load_la, mid_none, store_tw);
+    row_round<MODE_INV, false, 1, FK, SH>(xd, ftw, itw, first_round, pre_inv, load_la, mid_none, store_tw);
 }
 
 // P3: inverse column NTT of one tile of job.A, then the output window.
@@ -1015,6 +1194,33 @@ __global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan
 
 // ----------------------------------------------------------------- launchers
 
+// The row kernel for first-round kind fk and fixed shape sh (0: general).
+// The general kernel is instantiated for the first-round kinds plans give
+// it: radix-2 rounds of 2, 4, 8 and the radix-3 kinds of 3, 6, 12, 9
+// values; a fixed shape only with its own first kind.
+template <int SH>
+static const void *fixed_row_fn(int sh, int fk) {
+    if constexpr (SH < kNumRowShapes) {
+        if (sh == SH) return fk == FixedRow<SH>::first_kind ? (const void *)k_rowconv<FixedRow<SH>::first_kind, SH> : nullptr;
+        return fixed_row_fn<SH + 1>(sh, fk);
+    }
+    return nullptr;
+}
+
+static const void *rowconv_fn(int fk, int sh) {
+    if (sh != 0) return fixed_row_fn<1>(sh, fk);
+    switch (fk) {
+        case 0: return (const void *)k_rowconv<0, 0>;
+        case 1: return (const void *)k_rowconv<1, 0>;
+        case 2: return (const void *)k_rowconv<2, 0>;
+        case 4: return (const void *)k_rowconv<4, 0>;
+        case 5: return (const void *)k_rowconv<5, 0>;
+        case 6: return (const void *)k_rowconv<6, 0>;
+        case 7: return (const void *)k_rowconv<7, 0>;
+        default: return nullptr;
+    }
+}
+
 static int g_lds_limit[64];
 
 // Largest column-pass output (bytes per launch) written with write-through
@@ -1037,14 +1243,19 @@ static hipError_t set_lds_limits(int *limit) {
             if (e != hipSuccess) return e;
         }
         const int maxb = optin < 160 * 1024 ? optin : 160 * 1024;
-        const void *fns[] = {(const void *)k_rowconv<0>, (const void *)k_rowconv<1>, (const void *)k_rowconv<2>,
-                             (const void *)k_rowconv<4>, (const void *)k_rowconv<5>, (const void *)k_rowconv<6>,
-                             (const void *)k_rowconv<7>, (const void *)k_colfwd<3, false>, (const void *)k_colfwd<4, false>,
+        const void *fns[] = {(const void *)k_rowconv<0, 0>, (const void *)k_rowconv<1, 0>, (const void *)k_rowconv<2, 0>,
+                             (const void *)k_rowconv<4, 0>, (const void *)k_rowconv<5, 0>, (const void *)k_rowconv<6, 0>,
+                             (const void *)k_rowconv<7, 0>, (const void *)k_colfwd<3, false>, (const void *)k_colfwd<4, false>,
                              (const void *)k_colfwd<3, true>, (const void *)k_colfwd<4, true>,
                              (const void *)k_colinv<3, false>, (const void *)k_colinv<4, false>,
                              (const void *)k_colinv<3, true>, (const void *)k_colinv<4, true>};
         for (const void *f : fns) {
             e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
+            if (e != hipSuccess) return e;
+        }
+        for (int sh = 1; sh < kNumRowShapes; ++sh) {
+            e = hipFuncSetAttribute(rowconv_fn(row_shape_desc(sh).round[0].kind, sh),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
             if (e != hipSuccess) return e;
         }
         g_lds_limit[dev] = maxb;
@@ -1053,7 +1264,7 @@ static hipError_t set_lds_limits(int *limit) {
     return hipSuccess;
 }
 
-static hipError_t rowconv_regs(int fk, int *regs);
+static hipError_t rowconv_regs(int fk, int sh, int *regs);
 
 hipError_t warm_launch_state(const LenPlan &hp) {
     int limit = 0;
@@ -1062,7 +1273,7 @@ hipError_t warm_launch_state(const LenPlan &hp) {
     const int fk = hp.row.round[0].kind;
     if (fk < 0 || fk >= kNumKinds) return hipErrorInvalidConfiguration;
     int regs = 0;
-    return rowconv_regs(fk, &regs);
+    return rowconv_regs(fk, row_shape_id(hp.row), &regs);
 }
 
 // Largest radix-2 round (log2 of its size) of the column transform.
@@ -1113,32 +1324,17 @@ hipError_t launch_colfwd_flat(const FlatLaunch &fl, const LenPlan *plans, const 
     return colfwd_launch(fl.variant == 3, wt, dim3(fl.nwg), fl.threads, fl.lds, plans, ja, s, e0, e1);
 }
 
-// VGPRs per thread of k_rowconv<fk> (cached; from the code object).
-// The row pass is instantiated for the first-round kinds plans give it:
-// radix-2 rounds of 2, 4, 8 and the radix-3 kinds of 3, 6, 12, 9 values.
-static const void *rowconv_fn(int fk) {
-    switch (fk) {
-        case 0: return (const void *)k_rowconv<0>;
-        case 1: return (const void *)k_rowconv<1>;
-        case 2: return (const void *)k_rowconv<2>;
-        case 4: return (const void *)k_rowconv<4>;
-        case 5: return (const void *)k_rowconv<5>;
-        case 6: return (const void *)k_rowconv<6>;
-        case 7: return (const void *)k_rowconv<7>;
-        default: return nullptr;
-    }
-}
-
-static hipError_t rowconv_regs(int fk, int *regs) {
-    static int cache[kNumKinds];
-    if (!rowconv_fn(fk)) return hipErrorInvalidConfiguration;
-    if (cache[fk] == 0) {
+static hipError_t rowconv_regs(int fk, int sh, int *regs) {
+    static int cache[kNumKinds][kNumRowShapes];
+    const void *fn = rowconv_fn(fk, sh);
+    if (!fn) return hipErrorInvalidConfiguration;
+    if (cache[fk][sh] == 0) {
         hipFuncAttributes a{};
-        hipError_t e = hipFuncGetAttributes(&a, rowconv_fn(fk));
+        hipError_t e = hipFuncGetAttributes(&a, fn);
         if (e != hipSuccess) return e;
-        cache[fk] = a.numRegs > 0 ? a.numRegs : 128;
+        cache[fk][sh] = a.numRegs > 0 ? a.numRegs : 128;
     }
-    *regs = cache[fk];
+    *regs = cache[fk][sh];
     return hipSuccess;
 }
 
@@ -1161,11 +1357,12 @@ static int resident_waves(int t, int regs, size_t lds, int lds_limit) {
 // size that keeps the most waves resident per CU (ties: the smaller, whose
 // workgroups do not wait on each other's barriers); a single block's few
 // rows leave one workgroup per CU: the plan's full size.
-static hipError_t row_threads_for(int fk, int plan_threads, size_t rows, size_t lds, int limit, int *threads) {
+static hipError_t row_threads_for(int fk, int sh, int plan_threads, size_t rows, size_t lds, int limit,
+                                  int *threads) {
     *threads = plan_threads;
     if (rows < 512) return hipSuccess;
     int regs = 0;
-    hipError_t e = rowconv_regs(fk, &regs);
+    hipError_t e = rowconv_regs(fk, sh, &regs);
     if (e != hipSuccess) return e;
     int best = 0;
     for (int t : {512, 768, 1024}) {
@@ -1181,23 +1378,16 @@ static hipError_t row_threads_for(int fk, int plan_threads, size_t rows, size_t 
 
 int rowconv_wgs_per_cu(int fk, int threads, size_t lds) {
     int limit = 0, regs = 0;
-    if (set_lds_limits(&limit) != hipSuccess || rowconv_regs(fk, &regs) != hipSuccess) return 0;
+    if (set_lds_limits(&limit) != hipSuccess || rowconv_regs(fk, 0, &regs) != hipSuccess) return 0;
     return resident_waves(threads, regs, lds, limit) * 64 / threads;
 }
 
-static hipError_t rowconv_launch(int fk, dim3 grid, int threads, size_t lds, const LenPlan *dp, int mode,
+static hipError_t rowconv_launch(int fk, int sh, dim3 grid, int threads, size_t lds, const LenPlan *dp, int mode,
                                  const JobArgs &ja, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const dim3 block((unsigned)threads);
-    switch (fk) {
-#define PA_FK(K)                                                                                         \
-    case K:                                                                                              \
-        hipExtLaunchKernelGGL(k_rowconv<K>, grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja, mode);     \
-        break;
-        PA_FK(0) PA_FK(1) PA_FK(2) PA_FK(4) PA_FK(5) PA_FK(6) PA_FK(7)
-#undef PA_FK
-        default: return hipErrorInvalidConfiguration;
-    }
-    return hipGetLastError();
+    const void *fn = rowconv_fn(fk, sh);
+    if (!fn) return hipErrorInvalidConfiguration;
+    void *args[] = {(void *)&dp, (void *)&ja, (void *)&mode};
+    return hipExtLaunchKernel(fn, grid, dim3((unsigned)threads), args, lds, s, e0, e1, 0);
 }
 
 hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int mode, const JobArgs &ja, int njobs,
@@ -1210,12 +1400,13 @@ hipError_t launch_rowconv(const LenPlan &hp, const LenPlan *dp, int mode, const 
         return hipErrorInvalidConfiguration;
     const int fk = hp.row.round[0].kind;
     if (fk < 0 || fk >= kNumKinds) return hipErrorInvalidConfiguration;
+    const int sh = row_shape_id(hp.row);
     int threads = hp.row_threads;
     if (!hp.row_threads_fixed) {
-        e = row_threads_for(fk, hp.row_threads, (size_t)hp.R * (size_t)njobs, lds, limit, &threads);
+        e = row_threads_for(fk, sh, hp.row_threads, (size_t)hp.R * (size_t)njobs, lds, limit, &threads);
         if (e != hipSuccess) return e;
     }
-    return rowconv_launch(fk, dim3((unsigned)hp.R, (unsigned)njobs), threads, lds, dp, mode, ja, s, e0, e1);
+    return rowconv_launch(fk, sh, dim3((unsigned)hp.R, (unsigned)njobs), threads, lds, dp, mode, ja, s, e0, e1);
 }
 
 hipError_t launch_rowconv_flat(const FlatLaunch &fl, const LenPlan *plans, int mode, const JobArgs &ja,
@@ -1223,15 +1414,16 @@ hipError_t launch_rowconv_flat(const FlatLaunch &fl, const LenPlan *plans, int m
     int limit = 0;
     hipError_t e = set_lds_limits(&limit);
     if (e != hipSuccess) return e;
-    if (fl.lds > (size_t)limit || !ja.seg || !ja.table || fl.nwg == 0 || !rowconv_fn(fl.variant))
+    // jobs of several lengths: the general kernel
+    if (fl.lds > (size_t)limit || !ja.seg || !ja.table || fl.nwg == 0 || !rowconv_fn(fl.variant, 0))
         return hipErrorInvalidConfiguration;
     // a negative size is a fixed (tuned) one
     int threads = -fl.threads;
     if (fl.threads > 0) {
-        e = row_threads_for(fl.variant, fl.threads, fl.nwg, fl.lds, limit, &threads);
+        e = row_threads_for(fl.variant, 0, fl.threads, fl.nwg, fl.lds, limit, &threads);
         if (e != hipSuccess) return e;
     }
-    return rowconv_launch(fl.variant, dim3(fl.nwg), threads, fl.lds, plans, mode, ja, s, e0, e1);
+    return rowconv_launch(fl.variant, 0, dim3(fl.nwg), threads, fl.lds, plans, mode, ja, s, e0, e1);
 }
 
 static hipError_t colinv_launch(bool lg3, dim3 grid, int threads, size_t lds, const LenPlan *dp, const JobArgs &ja,

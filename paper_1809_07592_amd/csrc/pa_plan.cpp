@@ -92,12 +92,6 @@ static void factor_len(uint64_t L, int &k, int &j) {
 }
 
 // Kind index of a round with n3 radix-3 and n2 radix-2 stages.
-static int kind_of(int n3, int n2) {
-    for (int i = 0; i < kNumKinds; ++i)
-        if (kKindN3[i] == n3 && kKindN2[i] == n2) return i;
-    throw std::runtime_error("no round kind for this shape");
-}
-
 // Split n3 radix-3 and n2 radix-2 stages into register rounds: all radix-3
 // stages in the first round (with at most 2, 1, 0 radix-2 stages for n3 =
 // 1, 2, 3 -- maxlg - 1, 1, 0 -- and at most maxlg for n3 = 0), later rounds pure radix-2 with at
@@ -195,61 +189,23 @@ struct XTables {
 // host code.
 static XDesc describe_xdesc(int N, int maxlg, XTables *tabs, int first_max = 0, int first_lg = -1) {
     XDesc x{};
-    x.N = N;
     uint64_t tmp = (uint64_t)N;
     int k2, k3;
     factor_len(tmp, k2, k3);
     std::vector<int> radix;
     for (int i = 0; i < k3; ++i) radix.push_back(3);
     for (int i = 0; i < k2; ++i) radix.push_back(2);
-    x.nstages = (int)radix.size();
-    if (x.nstages > kMaxStages) throw std::runtime_error("too many stages");
+    if ((int)radix.size() > kMaxStages) throw std::runtime_error("too many stages");
 
     auto rounds = split_rounds(k3, k2, maxlg, first_max, first_lg);
     if ((int)rounds.size() > kMaxRounds) throw std::runtime_error("too many rounds");
-    x.nrounds = (int)rounds.size();
-    int s = 0;
-    uint64_t P = 1;  // product of radices before stage s
-    for (int r = 0; r < x.nrounds; ++r) {
-        int n3 = rounds[r].first, n2 = rounds[r].second;
-        int rho = 1;
-        for (int i = 0; i < n3; ++i) rho *= 3;
-        rho <<= n2;
-        RoundDesc &rd = x.round[r];
-        rd.kind = kind_of(n3, n2);
-        rd.s0 = s;
-        rd.M = (int)((uint64_t)N / P);
-        int jl = rd.M / rho;
-        // every round but the first needs a power-of-two stride (its block
-        // index is a shift of the item); the first may be 3 * 2^k
-        if (jl * rho != rd.M || (r > 0 && (jl & (jl - 1)))) throw std::runtime_error("round stride not a power of two");
-        rd.J = jl;
-        rd.jl_log2 = __builtin_ctz((unsigned)jl);
-        rd.ngroups = N / rho;
-        s += n3 + n2;
-        P *= (uint64_t)rho;
+    int rn3[kMaxRounds] = {}, rn2[kMaxRounds] = {};
+    for (size_t r = 0; r < rounds.size(); ++r) {
+        rn3[r] = rounds[r].first;
+        rn2[r] = rounds[r].second;
     }
-    {
-        const RoundDesc &last = x.round[x.nrounds - 1];
-        int rho_last = last.M / last.J;
-        x.lgpad = __builtin_ctz((unsigned)rho_last);
-        if (rho_last & (rho_last - 1)) x.lgpad = 4;  // single mixed round: any pad works
-    }
-
-    if (!tabs) {
-        uint64_t Ps = 1;
-        int fo = 0, io = 0;
-        for (int st = 0; st < x.nstages; ++st) {
-            const int r = radix[(size_t)st];
-            const uint64_t J = (uint64_t)N / (Ps * (uint64_t)r);
-            x.fwd_off[st] = fo;
-            x.inv_off[st] = io;
-            fo += (int)(Ps * (uint64_t)(r - 1));
-            io += (int)(J * (uint64_t)(r - 1));
-            Ps *= (uint64_t)r;
-        }
-        return x;
-    }
+    if (!describe_rounds(N, (int)rounds.size(), rn3, rn2, x)) throw std::runtime_error("no valid round descriptor");
+    if (!tabs) return x;
     const uint64_t w = root_of_unity((uint64_t)N);
     std::vector<uint64_t> pw((size_t)N);
     pw[0] = 1;
@@ -262,7 +218,7 @@ static XDesc describe_xdesc(int N, int maxlg, XTables *tabs, int first_max = 0, 
     for (int st = 0; st < x.nstages; ++st) {
         const int r = radix[(size_t)st];
         const uint64_t J = (uint64_t)N / (Ps * (uint64_t)r);
-        x.fwd_off[st] = (int)fwd.size();
+        if (x.fwd_off[st] != (int)fwd.size()) throw std::runtime_error("forward table offset mismatch");
         for (uint64_t b = 0; b < Ps; ++b) {
             // digit reversal of b over radices radix[0..st): most significant
             // digit of b (radix[0]) becomes least significant of D.
@@ -278,7 +234,7 @@ static XDesc describe_xdesc(int N, int maxlg, XTables *tabs, int first_max = 0, 
             }
             for (int u = 1; u < r; ++u) fwd.push_back(tw_pair(pw[(size_t)((D * J * (uint64_t)u) % (uint64_t)N)]));
         }
-        x.inv_off[st] = (int)inv.size();
+        if (x.inv_off[st] != (int)inv.size()) throw std::runtime_error("inverse table offset mismatch");
         for (uint64_t jp = 0; jp < J; ++jp)
             for (int i = 1; i < r; ++i) {
                 uint64_t e = (jp * (uint64_t)i * Ps) % (uint64_t)N;

@@ -279,6 +279,8 @@ typedef struct pa_plan_info {
     uint32_t row_shape;        /* nonzero: the row pass runs a kernel compiled for this row
                                   transform's shape (every stride and twiddle offset a
                                   constant); 0: the general row kernel */
+    uint32_t col_shape;        /* the same for the two column passes (the column transform's
+                                  shape and the tile width) */
 } pa_plan_info;
 
 pa_status pa_plan_describe(uint64_t transform_len, uint32_t log2_rows, uint32_t tile_width, pa_plan_info *info);

@@ -43,7 +43,7 @@ class PlanInfo(ctypes.Structure):
                 ("row_threads", ctypes.c_uint32), ("col_lds_bytes", ctypes.c_uint32),
                 ("row_lds_bytes", ctypes.c_uint32), ("col_rounds", ctypes.c_uint32), ("row_rounds", ctypes.c_uint32),
                 ("col_round_size", ctypes.c_uint32 * 6), ("row_round_size", ctypes.c_uint32 * 6),
-                ("row_shape", ctypes.c_uint32)]
+                ("row_shape", ctypes.c_uint32), ("col_shape", ctypes.c_uint32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -619,6 +619,7 @@ pa_status pa_plan_describe(uint64_t transform_len, uint32_t log2_rows, uint32_t 
     for (int i = 0; i < lp.row.nrounds; ++i)
         r.row_round_size[i] = (uint32_t)(lp.row.round[i].M / lp.row.round[i].J);
     r.row_shape = (uint32_t)pa::row_shape_id(lp.row);
+    r.col_shape = (uint32_t)pa::col_shape_id(lp);
     *info = r;
     return PA_OK;
 }

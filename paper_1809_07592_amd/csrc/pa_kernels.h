@@ -66,5 +66,8 @@ hipError_t warm_launch_state(const LenPlan &hp);
 // The fixed row-kernel shape whose descriptor equals x field by field, or
 // 0 (the general row kernel, which reads the descriptor from the plan).
 int row_shape_id(const XDesc &x);
+// The fixed column-kernel shape of a plan (its column descriptor and tile
+// width), or 0 (the general column kernels).
+int col_shape_id(const LenPlan &hp);
 
 }  // namespace pa

@@ -334,26 +334,26 @@ __device__ __forceinline__ void inv_stage(RegArr<N3, N2> &v, int jj, int jlast, 
 //
 // The stage helpers and round drivers read a transform's descriptor
 // through these accessors: from a plan in device memory (CXDesc), or from
-// a fixed row shape whose fields are compile-time constants (FixedRow).
+// a fixed shape whose fields are compile-time constants (FixedX).
 
 __device__ __forceinline__ int lgpad_of(const CXDesc &x) { return x.lgpad; }
 __device__ __forceinline__ int fwd_off_of(const CXDesc &x, int s) { return x.fwd_off[s]; }
 __device__ __forceinline__ int inv_off_of(const CXDesc &x, int s) { return x.inv_off[s]; }
 
-// Row transforms of fixed shape.  A plan whose row descriptor equals one of
-// these field by field runs a row kernel compiled for it: every round's
-// kind, stride, group count and twiddle offset is then a constant, so an
-// element's LDS address is one base register plus an immediate offset (a
-// run-time stride costs an integer add per access), and the seed and key
-// rows share that base.  Shape 0 is the general kernel, which reads the
-// descriptor from the plan.  The shapes are the row lengths of the
-// commonest transform lengths under their default geometry.
-struct RowShapeSpec {
-    int C, nrounds;
+// Transforms of fixed shape.  A plan whose row (column) descriptor equals
+// one of these field by field runs a row (column) kernel compiled for it:
+// every round's kind, stride, group count and twiddle offset is then a
+// constant, so an element's LDS address is one base register plus an
+// immediate offset (a run-time stride costs an integer add per access),
+// and the seed and key rows share that base.  Shape 0 is the general
+// kernel, which reads the descriptor from the plan.  The shapes are those
+// of the default geometries of the lengths 2^18 .. 27 * 2^19 (column
+// shapes with tiles of kColShapeW columns, the default width).
+struct ShapeSpec {
+    int N, nrounds;
     int n3[kMaxRounds], n2[kMaxRounds];
 };
-// (The default geometries of the lengths 2^18 .. 27 * 2^19 use these.)
-constexpr RowShapeSpec kRowShapeSpec[] = {
+constexpr ShapeSpec kRowShapeSpec[] = {
     {0, 0, {}, {}},
     {2048, 4, {0, 0, 0, 0}, {2, 3, 3, 3}},        // 4 8 8 8
     {2304, 4, {2, 0, 0, 0}, {0, 3, 3, 2}},        // 9 8 8 4
@@ -366,29 +366,43 @@ constexpr RowShapeSpec kRowShapeSpec[] = {
     {9216, 5, {2, 0, 0, 0, 0}, {0, 3, 3, 2, 2}},  // 9 8 8 4 4
     {13824, 5, {2, 1, 0, 0, 0}, {0, 1, 3, 3, 2}}, // 9 6 8 8 4
 };
+constexpr ShapeSpec kColShapeSpec[] = {
+    {0, 0, {}, {}},
+    {128, 2, {0, 0}, {3, 4}},         // 8 16
+    {256, 2, {0, 0}, {4, 4}},         // 16 16
+    {512, 3, {0, 0, 0}, {3, 3, 3}},   // 8 8 8
+    {1024, 3, {0, 0, 0}, {3, 4, 3}},  // 8 16 8
+};
+constexpr int kColShapeW = 16;
+
+enum { TAB_ROW = 0, TAB_COL = 1 };
 constexpr int kNumRowShapes = (int)(sizeof(kRowShapeSpec) / sizeof(kRowShapeSpec[0]));
+constexpr int kNumColShapes = (int)(sizeof(kColShapeSpec) / sizeof(kColShapeSpec[0]));
+constexpr int num_shapes(int tab) { return tab == TAB_ROW ? kNumRowShapes : kNumColShapes; }
+constexpr const ShapeSpec &shape_spec(int tab, int i) { return tab == TAB_ROW ? kRowShapeSpec[i] : kColShapeSpec[i]; }
 
 // Descriptor of shape i (all zero for i = 0 or an invalid spec).  Only
 // ever evaluated in constant expressions on the device: a constexpr object
 // that device code refers to becomes a host-writable constant that the
 // compiler cannot fold.
-constexpr XDesc row_shape_desc(int i) {
+constexpr XDesc shape_desc(int tab, int i) {
     XDesc x{};
-    if (i > 0 && i < kNumRowShapes &&
-        !describe_rounds(kRowShapeSpec[i].C, kRowShapeSpec[i].nrounds, kRowShapeSpec[i].n3, kRowShapeSpec[i].n2, x))
-        x = XDesc{};
+    if (i > 0 && i < num_shapes(tab)) {
+        const ShapeSpec &sp = shape_spec(tab, i);
+        if (!describe_rounds(sp.N, sp.nrounds, sp.n3, sp.n2, x)) x = XDesc{};
+    }
     return x;
 }
 
-template <int SH>
-struct FixedRow {
-    static constexpr int N = row_shape_desc(SH).N;
-    static constexpr int nrounds = row_shape_desc(SH).nrounds;
-    static constexpr int nstages = row_shape_desc(SH).nstages;
-    static constexpr int lgpad = row_shape_desc(SH).lgpad;
-    static constexpr int first_kind = row_shape_desc(SH).round[0].kind;
+template <int TAB, int SH>
+struct FixedX {
+    static constexpr int N = shape_desc(TAB, SH).N;
+    static constexpr int nrounds = shape_desc(TAB, SH).nrounds;
+    static constexpr int lgpad = shape_desc(TAB, SH).lgpad;
+    static constexpr int first_kind = shape_desc(TAB, SH).round[0].kind;
+    static constexpr int last_lg = kKindN2[shape_desc(TAB, SH).round[nrounds > 0 ? nrounds - 1 : 0].kind];
     static constexpr int lds_ints = N + (N >> lgpad);
-    static constexpr int k3 = kRowShapeSpec[SH].n3[0] + kRowShapeSpec[SH].n3[1];
+    static constexpr int k3 = shape_spec(TAB, SH).n3[0] + shape_spec(TAB, SH).n3[1];
     // product of the radices before stage s (radix-3 stages first); the
     // forward table holds before(s) * (r - 1) factors per stage and the
     // inverse table N / before(s + 1) * (r - 1), so both offsets are
@@ -401,44 +415,46 @@ struct FixedRow {
     static constexpr int fwd_off(int s) { return before(s) - 1; }
     static constexpr int inv_off(int s) { return N - N / before(s); }
     static constexpr bool valid() {
-        const XDesc x = row_shape_desc(SH);
-        if (x.nrounds == 0 || kRowShapeSpec[SH].n3[2] != 0) return false;
+        const XDesc x = shape_desc(TAB, SH);
+        if (x.nrounds == 0 || shape_spec(TAB, SH).n3[2] != 0) return false;
         for (int s = 0; s < x.nstages; ++s)
             if (x.fwd_off[s] != fwd_off(s) || x.inv_off[s] != inv_off(s)) return false;
         return true;
     }
 };
+template <int SH>
+using FixedRow = FixedX<TAB_ROW, SH>;
+template <int SH>
+using FixedCol = FixedX<TAB_COL, SH>;
 
-template <int SH, int R>
+template <int TAB, int SH, int R>
 struct FixedRound {
-    static constexpr int kind = row_shape_desc(SH).round[R].kind;
-    static constexpr int s0 = row_shape_desc(SH).round[R].s0;
-    static constexpr int jl_log2 = row_shape_desc(SH).round[R].jl_log2;
-    static constexpr int J = row_shape_desc(SH).round[R].J;
-    static constexpr int M = row_shape_desc(SH).round[R].M;
-    static constexpr int ngroups = row_shape_desc(SH).round[R].ngroups;
+    static constexpr int kind = shape_desc(TAB, SH).round[R].kind;
+    static constexpr int s0 = shape_desc(TAB, SH).round[R].s0;
+    static constexpr int jl_log2 = shape_desc(TAB, SH).round[R].jl_log2;
+    static constexpr int J = shape_desc(TAB, SH).round[R].J;
+    static constexpr int M = shape_desc(TAB, SH).round[R].M;
+    static constexpr int ngroups = shape_desc(TAB, SH).round[R].ngroups;
 };
 
-template <int SH>
-__device__ __forceinline__ constexpr int lgpad_of(const FixedRow<SH> &) { return FixedRow<SH>::lgpad; }
-template <int SH>
-__device__ __forceinline__ constexpr int fwd_off_of(const FixedRow<SH> &, int s) { return FixedRow<SH>::fwd_off(s); }
-template <int SH>
-__device__ __forceinline__ constexpr int inv_off_of(const FixedRow<SH> &, int s) { return FixedRow<SH>::inv_off(s); }
+template <int TAB, int SH>
+__device__ __forceinline__ constexpr int lgpad_of(const FixedX<TAB, SH> &) { return FixedX<TAB, SH>::lgpad; }
+template <int TAB, int SH>
+__device__ __forceinline__ constexpr int fwd_off_of(const FixedX<TAB, SH> &, int s) { return FixedX<TAB, SH>::fwd_off(s); }
+template <int TAB, int SH>
+__device__ __forceinline__ constexpr int inv_off_of(const FixedX<TAB, SH> &, int s) { return FixedX<TAB, SH>::inv_off(s); }
 
-template <int SH>
-constexpr bool fixed_rows_valid() {
-    if constexpr (SH < kNumRowShapes) return FixedRow<SH>::valid() && fixed_rows_valid<SH + 1>();
+template <int TAB, int SH>
+constexpr bool fixed_shapes_valid() {
+    if constexpr (SH < num_shapes(TAB)) return FixedX<TAB, SH>::valid() && fixed_shapes_valid<TAB, SH + 1>();
     return true;
 }
-static_assert(fixed_rows_valid<1>(), "a fixed row shape has no valid descriptor");
+static_assert(fixed_shapes_valid<TAB_ROW, 1>() && fixed_shapes_valid<TAB_COL, 1>(),
+              "a fixed shape has no valid descriptor");
 
-// The fixed shape (or 0) whose descriptor equals x.
-int row_shape_id(const XDesc &x);
-
-int row_shape_id(const XDesc &x) {
-    for (int i = 1; i < kNumRowShapes; ++i) {
-        const XDesc s = row_shape_desc(i);
+static int shape_id(int tab, const XDesc &x) {
+    for (int i = 1; i < num_shapes(tab); ++i) {
+        const XDesc s = shape_desc(tab, i);
         bool same = s.N == x.N && s.nstages == x.nstages && s.nrounds == x.nrounds && s.lgpad == x.lgpad;
         for (int r = 0; same && r < s.nrounds; ++r) {
             const RoundDesc &a = s.round[r], &b = x.round[r];
@@ -450,6 +466,10 @@ int row_shape_id(const XDesc &x) {
     }
     return 0;
 }
+
+int row_shape_id(const XDesc &x) { return shape_id(TAB_ROW, x); }
+
+int col_shape_id(const LenPlan &hp) { return hp.W == kColShapeW ? shape_id(TAB_COL, hp.col) : 0; }
 
 // Rounds that keep a scheduling fence between stages: the row pass's
 // mixed first rounds of 9 and of 18 to 27 values, where hoisting every
@@ -750,12 +770,70 @@ __device__ __forceinline__ JobDesc job_of(const JobArgs &ja, unsigned idx) {
     return j;
 }
 
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for_up(F &&f) {  // B, B+1, ..., E-1
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for_up<B + 1, E>(f);
+    }
+}
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for_down(F &&f) {  // B, B-1, ..., E
+    if constexpr (B >= E) {
+        f(std::integral_constant<int, B>{});
+        static_for_down<B - 1, E>(f);
+    }
+}
+
+// Round r (an int, or a std::integral_constant for a fixed shape) of the
+// row transform; r = 0 is the first round, whose kind is FK.
+template <int MODE, bool LAST, int NA, int FK, int SH, class R, class Pre, class Load, class Mid, class Store>
+__device__ __forceinline__ void row_round(const CXDesc &xd, const ctwpair *ftw, const ctwpair *itw, R r, Pre &pre,
+                                          Load &load, Mid &mid, Store &store) {
+    if constexpr (SH == 0) {
+        // a 9-value first round may be followed by a round with the last
+        // radix-3 stage (lengths with 27 | C)
+        constexpr bool kMix = kKindN3[FK] == 2;
+        if constexpr (std::is_same<R, std::integral_constant<int, 0>>::value)
+            round_fk<MODE, FK, LAST, NA>(xd, ftw, itw, 0, pre, load, mid, store);
+        else
+            round_p2<MODE, false, LAST, kRowMaxLg, NA, kMix>(xd, ftw, itw, (int)r, 0, pre, load, mid, store);
+    } else {
+        using RD = FixedRound<TAB_ROW, SH, R::value>;
+        constexpr int k = RD::kind;
+        constexpr bool first = R::value == 0;
+        // a 9-value first round leaves a stride of 3 * 2^k
+        round_io<MODE, kKindN3[k], kKindN2[k], first, LAST, NA, first && kKindN3[k] == 2>(
+            RD{}, FixedRow<SH>{}, ftw, itw, 0, pre, load, mid, store);
+    }
+}
+
+// Round r (an int, or a std::integral_constant for a fixed shape) of the
+// column transform over tiles of W = 2^wsh columns (a fixed shape's own
+// width).
+template <int MODE, bool FIRST, bool LAST, int MAXLG, bool LND, int CS, class R, class Pre, class Load, class Mid,
+          class Store>
+__device__ __forceinline__ void col_round(const CXDesc &xd, const ctwpair *ftw, const ctwpair *itw, R r, int wsh,
+                                          Pre &pre, Load &load, Mid &mid, Store &store) {
+    if constexpr (CS == 0) {
+        round_p2<MODE, FIRST, LAST, MAXLG, 1, false, LND>(xd, ftw, itw, (int)r, wsh, pre, load, mid, store);
+    } else {
+        using RD = FixedRound<TAB_COL, CS, R::value>;
+        static_assert(kKindN3[RD::kind] == 0, "column transforms are radix-2");
+        round_io<MODE, 0, kKindN2[RD::kind], FIRST, LAST, 1, false, LND>(RD{}, FixedCol<CS>{}, ftw, itw,
+                                                                         log2_exact(kColShapeW), pre, load, mid,
+                                                                         store);
+    }
+}
+
 // MAXLG: largest radix-2 round of the plan's column transform (3: rounds of
 // at most 8 values, compiled without the 16-value case and its registers).
+// CS: a fixed column shape (its rounds and tile width compiled in), or 0.
 // Grid: (tiles, sources, jobs) with plan[0] the launch's plan, or, in a
 // flat launch, one dimension covering every job's tiles of source 0 then
 // source 1, each job with its own plan, plan[job.plan_idx].
-template <int MAXLG, bool WT>
+template <int MAXLG, bool WT, int CS>
 __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan, JobArgs ja) {
     uint32_t jidx, tile;
     bool src;
@@ -788,7 +866,7 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
     const uint32_t *base = (const uint32_t *)(src ? job.seed : job.key) + (koff >> 5);
     const rsrc_t bits = make_rsrc(base, (uint32_t)(((uint32_t)nbits + (uint32_t)ro + 31) / 32 * 4));
     const rsrc_t out = make_rsrc(src ? job.S : job.A, (uint32_t)(lp.L * 4));
-    const int W = lp.W, wsh = __builtin_ctz((unsigned)W), C = lp.C;
+    const int W = CS ? kColShapeW : lp.W, wsh = CS ? log2_exact(kColShapeW) : __builtin_ctz((unsigned)W), C = lp.C;
     const int c0 = xcd_tile((int)tile, lp.ntiles) * W;
     int *lds = pa_lds;
     auto pre = [&](int, int, int) PA_INLINE { return NoCtx{}; };
@@ -818,7 +896,7 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
     const rsrc_t rs_hi = make_rsrc(uni(lp.twist_hi), (uint32_t)((lp.L + 4095) / 4096) * 16);
     // last round (unit stride, block b of RHO rows): twist by
     // omega_L^(k1 c), then store; the twist's table loads start with the round
-    const int lg_last = kKindN2[xd.round[xd.nrounds - 1].kind];
+    const int lg_last = CS ? FixedCol<CS>::last_lg : kKindN2[xd.round[xd.nrounds - 1].kind];
     auto pre_tw = [&](int c, int b, int) PA_INLINE {
         return column_twist_load<0>(rs_lo, rs_hi, lp.log2R - lg_last, (uint32_t)(c0 + c), (uint32_t)b);
     };
@@ -832,18 +910,33 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
                 st32(out, off, (int)x);
         });
     };
-    const int nr = xd.nrounds;
-    if (nr == 1) {
-        round_p2<MODE_FWD, true, true, MAXLG>(xd, ftw, itw, 0, wsh, pre_tw, load_bits, mid, store_glb);
-        return;
-    }
-    round_p2<MODE_FWD, true, false, MAXLG>(xd, ftw, itw, 0, wsh, pre, load_bits, mid, store_lds);
-    __syncthreads();
-    for (int r = 1; r < nr - 1; ++r) {
-        round_p2<MODE_FWD, false, false, MAXLG>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
+    const std::integral_constant<int, 0> first_round{};
+    if constexpr (CS == 0) {
+        const int nr = xd.nrounds;
+        if (nr == 1) {
+            col_round<MODE_FWD, true, true, MAXLG, true, 0>(xd, ftw, itw, 0, wsh, pre_tw, load_bits, mid, store_glb);
+            return;
+        }
+        col_round<MODE_FWD, true, false, MAXLG, true, 0>(xd, ftw, itw, 0, wsh, pre, load_bits, mid, store_lds);
         __syncthreads();
+        for (int r = 1; r < nr - 1; ++r) {
+            col_round<MODE_FWD, false, false, MAXLG, true, 0>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
+            __syncthreads();
+        }
+        col_round<MODE_FWD, false, true, MAXLG, true, 0>(xd, ftw, itw, nr - 1, wsh, pre_tw, load_lds, mid, store_glb);
+    } else {
+        constexpr int nr = FixedCol<CS>::nrounds;
+        static_assert(nr >= 2, "fixed column shapes have two or more rounds");
+        col_round<MODE_FWD, true, false, MAXLG, true, CS>(xd, ftw, itw, first_round, wsh, pre, load_bits, mid,
+                                                          store_lds);
+        __syncthreads();
+        static_for_up<1, nr - 1>([&](auto r) PA_INLINE {
+            col_round<MODE_FWD, false, false, MAXLG, true, CS>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
+            __syncthreads();
+        });
+        col_round<MODE_FWD, false, true, MAXLG, true, CS>(xd, ftw, itw, std::integral_constant<int, nr - 1>{}, wsh,
+                                                          pre_tw, load_lds, mid, store_glb);
     }
-    round_p2<MODE_FWD, false, true, MAXLG>(xd, ftw, itw, nr - 1, wsh, pre_tw, load_lds, mid, store_glb);
 }
 
 // P2: one row of the twisted column spectra (the column pass applied the
@@ -857,45 +950,6 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
 // group is q = jj + l*J0 (J0 = C/rho0): its inverse twist is
 // beta(jj) * alpha(l), beta(jj) = omega_L^(-k1 jj), alpha(l) =
 // omega_L^(-k1 J0 l) / L.
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for_up(F &&f) {  // B, B+1, ..., E-1
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for_up<B + 1, E>(f);
-    }
-}
-
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for_down(F &&f) {  // B, B-1, ..., E
-    if constexpr (B >= E) {
-        f(std::integral_constant<int, B>{});
-        static_for_down<B - 1, E>(f);
-    }
-}
-
-// Round r (an int, or a std::integral_constant for a fixed shape) of the
-// row transform; r = 0 is the first round, whose kind is FK.
-template <int MODE, bool LAST, int NA, int FK, int SH, class R, class Pre, class Load, class Mid, class Store>
-__device__ __forceinline__ void row_round(const CXDesc &xd, const ctwpair *ftw, const ctwpair *itw, R r, Pre &pre,
-                                          Load &load, Mid &mid, Store &store) {
-    if constexpr (SH == 0) {
-        // a 9-value first round may be followed by a round with the last
-        // radix-3 stage (lengths with 27 | C)
-        constexpr bool kMix = kKindN3[FK] == 2;
-        if constexpr (std::is_same<R, std::integral_constant<int, 0>>::value)
-            round_fk<MODE, FK, LAST, NA>(xd, ftw, itw, 0, pre, load, mid, store);
-        else
-            round_p2<MODE, false, LAST, kRowMaxLg, NA, kMix>(xd, ftw, itw, (int)r, 0, pre, load, mid, store);
-    } else {
-        using RD = FixedRound<SH, R::value>;
-        constexpr int k = RD::kind;
-        constexpr bool first = R::value == 0;
-        // a 9-value first round leaves a stride of 3 * 2^k
-        round_io<MODE, kKindN3[k], kKindN2[k], first, LAST, NA, first && kKindN3[k] == 2>(
-            RD{}, FixedRow<SH>{}, ftw, itw, 0, pre, load, mid, store);
-    }
-}
-
 struct TwCtx {
     double2 beta;
 };
@@ -1070,7 +1124,8 @@ __global__ void __launch_bounds__(1024) k_rowconv(const LenPlan *__restrict__ pl
 // launch, one dimension covering every job's tiles, each with its own plan,
 // plan[job.plan_idx].
 // RES: the diagnostic form (job.res_out set), which stores every residue.
-template <int MAXLG, bool RES>
+// CS: a fixed column shape (its rounds and tile width compiled in), or 0.
+template <int MAXLG, bool RES, int CS>
 __global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan,
                                                                                        JobArgs ja) {
     uint32_t jidx, tile;
@@ -1091,7 +1146,7 @@ __global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan
     const int32_t *A = job.A;
     uint64_t *out = job.out;
     const uint32_t off0 = job.off0, m = job.m;
-    const int W = lp.W, wsh = __builtin_ctz((unsigned)W), C = lp.C, nr = xd.nrounds;
+    const int W = CS ? kColShapeW : lp.W, wsh = CS ? log2_exact(kColShapeW) : __builtin_ctz((unsigned)W), C = lp.C;
     const int c0 = xcd_tile((int)tile, lp.ntiles) * W;
     int *lds = pa_lds;
     const rsrc_t ain = make_rsrc(A, (uint32_t)(lp.L * 4));
@@ -1179,17 +1234,31 @@ __global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan
             }
         }
     };
-    if (nr == 1) {
-        round_p2<MODE_INV, true, true, MAXLG, 1, false, false>(xd, ftw, itw, 0, wsh, pre, load_glb, mid, store_bits);
-        return;
-    }
-    round_p2<MODE_INV, false, true, MAXLG, 1, false, false>(xd, ftw, itw, nr - 1, wsh, pre, load_glb, mid, store_lds);
-    __syncthreads();
-    for (int r = nr - 2; r >= 1; --r) {
-        round_p2<MODE_INV, false, false, MAXLG, 1, false, false>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
+    const std::integral_constant<int, 0> first_round{};
+    if constexpr (CS == 0) {
+        const int nr = xd.nrounds;
+        if (nr == 1) {
+            col_round<MODE_INV, true, true, MAXLG, false, 0>(xd, ftw, itw, 0, wsh, pre, load_glb, mid, store_bits);
+            return;
+        }
+        col_round<MODE_INV, false, true, MAXLG, false, 0>(xd, ftw, itw, nr - 1, wsh, pre, load_glb, mid, store_lds);
         __syncthreads();
+        for (int r = nr - 2; r >= 1; --r) {
+            col_round<MODE_INV, false, false, MAXLG, false, 0>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
+            __syncthreads();
+        }
+    } else {
+        constexpr int nr = FixedCol<CS>::nrounds;
+        static_assert(nr >= 2, "fixed column shapes have two or more rounds");
+        col_round<MODE_INV, false, true, MAXLG, false, CS>(xd, ftw, itw, std::integral_constant<int, nr - 1>{}, wsh,
+                                                           pre, load_glb, mid, store_lds);
+        __syncthreads();
+        static_for_down<nr - 2, 1>([&](auto r) PA_INLINE {
+            col_round<MODE_INV, false, false, MAXLG, false, CS>(xd, ftw, itw, r, wsh, pre, load_lds, mid, store_lds);
+            __syncthreads();
+        });
     }
-    round_p2<MODE_INV, true, false, MAXLG, 1, false, false>(xd, ftw, itw, 0, wsh, pre, load_lds, mid, store_bits);
+    col_round<MODE_INV, true, false, MAXLG, false, CS>(xd, ftw, itw, first_round, wsh, pre, load_lds, mid, store_bits);
 }
 
 // ----------------------------------------------------------------- launchers
@@ -1221,6 +1290,39 @@ static const void *rowconv_fn(int fk, int sh) {
     }
 }
 
+// The column kernels: the general ones by largest round (lg3: rounds of at
+// most 8 values) and store kind, or those compiled for fixed shape cs (all
+// rounds of at most 16 values).
+template <int CS>
+static const void *fixed_colfwd_fn(int cs, bool wt) {
+    if constexpr (CS < kNumColShapes) {
+        if (cs == CS) return wt ? (const void *)k_colfwd<4, true, CS> : (const void *)k_colfwd<4, false, CS>;
+        return fixed_colfwd_fn<CS + 1>(cs, wt);
+    }
+    return nullptr;
+}
+
+template <int CS>
+static const void *fixed_colinv_fn(int cs) {
+    if constexpr (CS < kNumColShapes) {
+        if (cs == CS) return (const void *)k_colinv<4, false, CS>;
+        return fixed_colinv_fn<CS + 1>(cs);
+    }
+    return nullptr;
+}
+
+static const void *colfwd_fn(bool lg3, bool wt, int cs) {
+    if (cs != 0) return fixed_colfwd_fn<1>(cs, wt);
+    if (lg3) return wt ? (const void *)k_colfwd<3, true, 0> : (const void *)k_colfwd<3, false, 0>;
+    return wt ? (const void *)k_colfwd<4, true, 0> : (const void *)k_colfwd<4, false, 0>;
+}
+
+static const void *colinv_fn(bool lg3, bool res, int cs) {
+    if (cs != 0) return res ? nullptr : fixed_colinv_fn<1>(cs);
+    if (lg3) return res ? (const void *)k_colinv<3, true, 0> : (const void *)k_colinv<3, false, 0>;
+    return res ? (const void *)k_colinv<4, true, 0> : (const void *)k_colinv<4, false, 0>;
+}
+
 static int g_lds_limit[64];
 
 // Largest column-pass output (bytes per launch) written with write-through
@@ -1245,19 +1347,23 @@ static hipError_t set_lds_limits(int *limit) {
         const int maxb = optin < 160 * 1024 ? optin : 160 * 1024;
         const void *fns[] = {(const void *)k_rowconv<0, 0>, (const void *)k_rowconv<1, 0>, (const void *)k_rowconv<2, 0>,
                              (const void *)k_rowconv<4, 0>, (const void *)k_rowconv<5, 0>, (const void *)k_rowconv<6, 0>,
-                             (const void *)k_rowconv<7, 0>, (const void *)k_colfwd<3, false>, (const void *)k_colfwd<4, false>,
-                             (const void *)k_colfwd<3, true>, (const void *)k_colfwd<4, true>,
-                             (const void *)k_colinv<3, false>, (const void *)k_colinv<4, false>,
-                             (const void *)k_colinv<3, true>, (const void *)k_colinv<4, true>};
+                             (const void *)k_rowconv<7, 0>, colfwd_fn(true, false, 0), colfwd_fn(false, false, 0),
+                             colfwd_fn(true, true, 0), colfwd_fn(false, true, 0), colinv_fn(true, false, 0),
+                             colinv_fn(false, false, 0), colinv_fn(true, true, 0), colinv_fn(false, true, 0)};
         for (const void *f : fns) {
             e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
             if (e != hipSuccess) return e;
         }
         for (int sh = 1; sh < kNumRowShapes; ++sh) {
-            e = hipFuncSetAttribute(rowconv_fn(row_shape_desc(sh).round[0].kind, sh),
+            e = hipFuncSetAttribute(rowconv_fn(shape_desc(TAB_ROW, sh).round[0].kind, sh),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
             if (e != hipSuccess) return e;
         }
+        for (int cs = 1; cs < kNumColShapes; ++cs)
+            for (const void *f : {colfwd_fn(false, false, cs), colfwd_fn(false, true, cs), colinv_fn(false, false, cs)}) {
+                e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
+                if (e != hipSuccess) return e;
+            }
         g_lds_limit[dev] = maxb;
     }
     *limit = g_lds_limit[dev];
@@ -1286,17 +1392,12 @@ int col_max_lg(const LenPlan &hp) {
     return mx;
 }
 
-static hipError_t colfwd_launch(bool lg3, bool wt, dim3 grid, int threads, size_t lds, const LenPlan *dp,
+static hipError_t colfwd_launch(bool lg3, bool wt, int cs, dim3 grid, int threads, size_t lds, const LenPlan *dp,
                                 const JobArgs &ja, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const dim3 block((unsigned)threads);
-#define PA_CF(LG, WTV) hipExtLaunchKernelGGL((k_colfwd<LG, WTV>), grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja)
-    if (lg3) {
-        if (wt) PA_CF(3, true); else PA_CF(3, false);
-    } else {
-        if (wt) PA_CF(4, true); else PA_CF(4, false);
-    }
-#undef PA_CF
-    return hipGetLastError();
+    const void *fn = colfwd_fn(lg3, wt, cs);
+    if (!fn) return hipErrorInvalidConfiguration;
+    void *args[] = {(void *)&dp, (void *)&ja};
+    return hipExtLaunchKernel(fn, grid, dim3((unsigned)threads), args, lds, s, e0, e1, 0);
 }
 
 hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const JobArgs &ja, int njobs,
@@ -1309,8 +1410,9 @@ hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const J
         return hipErrorInvalidConfiguration;
     // write-through stores unless the launch writes more than kColWtBytes
     const bool wt = (double)nsrc * (double)njobs * 4.0 * (double)hp.L <= (double)kColWtBytes;
-    return colfwd_launch(col_max_lg(hp) <= 3, wt, dim3((unsigned)hp.ntiles, (unsigned)nsrc, (unsigned)njobs),
-                         hp.col_threads, lds, dp, ja, s, e0, e1);
+    return colfwd_launch(col_max_lg(hp) <= 3, wt, col_shape_id(hp),
+                         dim3((unsigned)hp.ntiles, (unsigned)nsrc, (unsigned)njobs), hp.col_threads, lds, dp, ja, s,
+                         e0, e1);
 }
 
 hipError_t launch_colfwd_flat(const FlatLaunch &fl, const LenPlan *plans, const JobArgs &ja, hipStream_t s, hipEvent_t e0,
@@ -1321,7 +1423,7 @@ hipError_t launch_colfwd_flat(const FlatLaunch &fl, const LenPlan *plans, const 
     if (fl.lds > (size_t)limit || !ja.seg || !ja.table || fl.nwg == 0 || (fl.variant != 3 && fl.variant != 4))
         return hipErrorInvalidConfiguration;
     const bool wt = fl.bytes_written <= kColWtBytes;
-    return colfwd_launch(fl.variant == 3, wt, dim3(fl.nwg), fl.threads, fl.lds, plans, ja, s, e0, e1);
+    return colfwd_launch(fl.variant == 3, wt, 0, dim3(fl.nwg), fl.threads, fl.lds, plans, ja, s, e0, e1);
 }
 
 static hipError_t rowconv_regs(int fk, int sh, int *regs) {
@@ -1426,19 +1528,14 @@ hipError_t launch_rowconv_flat(const FlatLaunch &fl, const LenPlan *plans, int m
     return rowconv_launch(fl.variant, 0, dim3(fl.nwg), threads, fl.lds, plans, mode, ja, s, e0, e1);
 }
 
-static hipError_t colinv_launch(bool lg3, dim3 grid, int threads, size_t lds, const LenPlan *dp, const JobArgs &ja,
-                                hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const dim3 block((unsigned)threads);
-    // the residue-storing form only for a single diagnostic job
+static hipError_t colinv_launch(bool lg3, int cs, dim3 grid, int threads, size_t lds, const LenPlan *dp,
+                                const JobArgs &ja, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    // the residue-storing form only for a single diagnostic job (general kernel)
     const bool res = !ja.table && ja.one.res_out;
-#define PA_CI(LG, R) hipExtLaunchKernelGGL((k_colinv<LG, R>), grid, block, (uint32_t)lds, s, e0, e1, 0, dp, ja)
-    if (lg3) {
-        if (res) PA_CI(3, true); else PA_CI(3, false);
-    } else {
-        if (res) PA_CI(4, true); else PA_CI(4, false);
-    }
-#undef PA_CI
-    return hipGetLastError();
+    const void *fn = colinv_fn(lg3, res, res ? 0 : cs);
+    if (!fn) return hipErrorInvalidConfiguration;
+    void *args[] = {(void *)&dp, (void *)&ja};
+    return hipExtLaunchKernel(fn, grid, dim3((unsigned)threads), args, lds, s, e0, e1, 0);
 }
 
 hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const JobArgs &ja, int njobs, hipStream_t s,
@@ -1448,8 +1545,8 @@ hipError_t launch_colinv(const LenPlan &hp, const LenPlan *dp, const JobArgs &ja
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)hp.col_lds * sizeof(int);
     if (lds > (size_t)limit || njobs < 1 || njobs > 65535 || ja.seg) return hipErrorInvalidConfiguration;
-    return colinv_launch(col_max_lg(hp) <= 3, dim3((unsigned)hp.ntiles, (unsigned)njobs), hp.col_threads, lds, dp,
-                         ja, s, e0, e1);
+    return colinv_launch(col_max_lg(hp) <= 3, col_shape_id(hp), dim3((unsigned)hp.ntiles, (unsigned)njobs),
+                         hp.col_threads, lds, dp, ja, s, e0, e1);
 }
 
 hipError_t launch_colinv_flat(const FlatLaunch &fl, const LenPlan *plans, const JobArgs &ja, hipStream_t s, hipEvent_t e0,
@@ -1459,7 +1556,7 @@ hipError_t launch_colinv_flat(const FlatLaunch &fl, const LenPlan *plans, const 
     if (e != hipSuccess) return e;
     if (fl.lds > (size_t)limit || !ja.seg || !ja.table || fl.nwg == 0 || (fl.variant != 3 && fl.variant != 4))
         return hipErrorInvalidConfiguration;
-    return colinv_launch(fl.variant == 3, dim3(fl.nwg), fl.threads, fl.lds, plans, ja, s, e0, e1);
+    return colinv_launch(fl.variant == 3, 0, dim3(fl.nwg), fl.threads, fl.lds, plans, ja, s, e0, e1);
 }
 
 // Workgroups per CU of a column-pass launch (the kernels' VGPR counts and
@@ -1471,8 +1568,7 @@ int col_wgs_per_cu(bool inverse, int lg, int threads, size_t lds) {
     int &rc = regs_cache[inverse ? 1 : 0][lg];
     if (rc == 0) {
         hipFuncAttributes a{};
-        const void *fn = inverse ? (lg == 3 ? (const void *)k_colinv<3, false> : (const void *)k_colinv<4, false>)
-                                 : (lg == 3 ? (const void *)k_colfwd<3, false> : (const void *)k_colfwd<4, false>);
+        const void *fn = inverse ? colinv_fn(lg == 3, false, 0) : colfwd_fn(lg == 3, false, 0);
         if (hipFuncGetAttributes(&a, fn) != hipSuccess) return 0;
         rc = a.numRegs > 0 ? a.numRegs : 128;
     }

@@ -1,0 +1,120 @@
+"""Kernels compiled for fixed transform shapes, against the oracle.
+
+The row kernel and the two column kernels have forms compiled for the row
+and column transforms of the default geometries of the lengths
+2^18 .. 27 * 2^19.  Each fixed shape runs here at the smallest length that
+uses it, on the plain path (seed and key rows in one row kernel), the plan
+path (key row against a resident spectrum, after the spectrum-building mode
+of the same kernel) and a batched call, and must give the oracle's bits
+(Sec. 2.3 Eq. (4): the product of the Toeplitz matrix and the key).  The
+same length under a geometry that no fixed kernel covers runs the general
+kernels and must give the same bits.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1809_07592_amd as pa
+from paper_1809_07592_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def shape_lengths():
+    """Smallest supported length per fixed row shape and per fixed column
+    shape (default geometry), as (L, row shape, column shape)."""
+    lens = set()
+    seen_row, seen_col = set(), set()
+    for L in pa.supported_lengths():
+        d = pa.plan_info(L)
+        if d["row_shape"] and d["row_shape"] not in seen_row:
+            seen_row.add(d["row_shape"])
+            lens.add(L)
+        if d["col_shape"] and d["col_shape"] not in seen_col:
+            seen_col.add(d["col_shape"])
+            lens.add(L)
+    return [(L, pa.plan_info(L)["row_shape"], pa.plan_info(L)["col_shape"]) for L in sorted(lens)]
+
+
+SHAPES = shape_lengths()
+
+
+def block_for(L):
+    """(n, m) whose transform length is L: m = n/4 up to about 1.2e6 bits,
+    a 20,000-bit window beyond (the oracle's cost grows with n * m)."""
+    small = L <= 3 * 2**19
+    n = (L - 256) * 4 // 5 if small else L - 20_000 - 256
+    m = n // 4 if small else 20_000
+    assert pa.transform_len(n, m) == L, (L, n, m)
+    return n, m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def host(t, m):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)[: wl.words(m)]
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build()
+
+
+def test_every_fixed_shape_is_exercised():
+    assert len({r for _, r, _ in SHAPES}) >= 10 and len({c for _, _, c in SHAPES}) >= 4
+    for L, r, c in SHAPES:
+        assert r or c, L
+
+
+@pytest.mark.parametrize("L,sh,cs", SHAPES, ids=[f"L{L}_row{r}_col{c}" for L, r, c in SHAPES])
+def test_fixed_shapes_match_oracle(L, sh, cs):
+    n, m = block_for(L)
+    d = pa.plan_info(L)
+    print("L=%d R=%d C=%d row shape %d column shape %d: n=%d m=%d" % (L, d["rows"], d["cols"], sh, cs, n, m),
+          flush=True)
+    key, seed = wl.key_and_seed(60 + sh, n, m, 0)
+    want = oracle.toeplitz_hash(key, n, seed, m)
+    dk, ds = dev(key), dev(seed)
+    # plain path
+    assert np.array_equal(host(pa.toeplitz_hash(dk, n, ds, m), m), want), "plain"
+    # plan path: the spectrum built by the row kernel's seed mode, then the key
+    with pa.Plan(ds, n + m - 1, transform_len=L) as plan:
+        assert np.array_equal(host(plan.hash(dk, n, m), m), want), "plan"
+    # batched: this block and a second one of the same length
+    key2, seed2 = wl.key_and_seed(60 + sh, n, m, 1)
+    want2 = oracle.toeplitz_hash(key2, n, seed2, m)
+    outs = [torch.zeros(wl.words(m), dtype=torch.int64, device="cuda") for _ in range(2)]
+    pa.toeplitz_hash_batched([(dk, n, ds, m, outs[0]), (dev(key2), n, dev(seed2), m, outs[1])])
+    assert np.array_equal(host(outs[0], m), want), "batched 0"
+    assert np.array_equal(host(outs[1], m), want2), "batched 1"
+
+
+@pytest.mark.parametrize("a,w,general", [(7, 16, "row"), (8, 32, "column"), (0, 0, "")])
+def test_general_kernels_at_a_fixed_shape_length(a, w, general):
+    # L = 3 * 2^19: under R = 128 its rows of 12,288 values have no fixed
+    # row kernel; with 32-column tiles no fixed column kernel applies; the
+    # default geometry has both
+    L = 3 * 2**19
+    d = pa.plan_info(L, a, w)
+    assert (d["row_shape"] == 0) == (general == "row") and (d["col_shape"] == 0) == (general == "column")
+    n, m = block_for(L)
+    key, seed = wl.key_and_seed(71, n, m, 0)
+    want = oracle.toeplitz_hash(key, n, seed, m)
+    dk, ds = dev(key), dev(seed)
+    try:
+        pa.tune_set(L, 0, a, w)
+        assert np.array_equal(host(pa.toeplitz_hash(dk, n, ds, m), m), want)
+        pa.tune_set(L, 1, a, w)
+        outs = [torch.zeros(wl.words(m), dtype=torch.int64, device="cuda") for _ in range(2)]
+        pa.toeplitz_hash_batched([(dk, n, ds, m, o) for o in outs])
+        for o in outs:
+            assert np.array_equal(host(o, m), want)
+    finally:
+        pa.tune_set(L, 0, 0, 0)
+        pa.tune_set(L, 1, 0, 0)

@@ -69,11 +69,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str = "plain"):
+def load_traffic(kernel: str, workload: str = "plain", geometry=None):
     """Measured bytes per launch leaving the L2 (rocprofv3 FETCH_SIZE and
     WRITE_SIZE, calibrated by a copy) for one pass of a profiled workload
     ("plain", "batched" or "large"), if the counters were taken on the
-    current kernel source (else None)."""
+    current kernel source and, when `geometry` ([log2 R, W, row_first,
+    row_threads] in effect) is given, in that geometry (else None)."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
@@ -84,20 +85,31 @@ def load_traffic(kernel: str, workload: str = "plain"):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    k = d.get("workloads", {}).get(workload, {}).get("kernels", {}).get(kernel)
+    wd = d.get("workloads", {}).get(workload, {})
+    if geometry is not None and wd.get("geometry") is not None and list(wd["geometry"]) != list(geometry):
+        return None
+    k = wd.get("kernels", {}).get(kernel)
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def kernel_figures(prof: dict, workload: str) -> dict:
+def geometry_in_effect(pa, L: int, batch_class: int) -> list:
+    """[log2 R, W, row_first, row_threads] the library uses for L."""
+    g = pa.tune_get_geometry(L, batch_class)
+    return [g["log2_rows"], g["tile_width"], g["row_first"], g["row_threads"]]
+
+
+def kernel_figures(prof: dict, workload: str, geometry=None) -> dict:
     """Per-pass figures from the library's profiler (HIP events recorded by
     each launch on its stream): average duration, algorithmic bytes and fp64
-    operations per launch, and their fractions of the HBM and fp64 peaks."""
+    operations per launch, and their fractions of the HBM and fp64 peaks;
+    the measured traffic of the committed counter profile when it was taken
+    on the same kernels in the same geometry."""
     out = {}
     for name, st in prof.items():
         avg_s = st["avg_ms"] * 1e-3
         b = st["alg_bytes"] / st["launches"]
         o = st["alg_ops"] / st["launches"]
-        t = load_traffic(name, workload)
+        t = load_traffic(name, workload, geometry)
         out[name] = {"avg_us": st["avg_ms"] * 1e3, "launches": st["launches"], "alg_bytes_per_launch": b,
                      "alg_ops_per_launch": o, "hbm_GBs": b / avg_s / 1e9, "hbm_frac": b / avg_s / 1e9 / HBM_PEAK_GBS,
                      "fp64_Tops": o / avg_s / 1e12, "alu_frac": o / avg_s / 1e12 / FP64_VALU_PEAK_TOPS,
@@ -283,7 +295,7 @@ def large_block_run(pa, wl, torch, np, stream, steps, tune):
     g = pa.plan_info(L, *pa.tune_get(L, 0))
     res = {"value": n / (ms * 1e-3) / 1e9, "unit": "Gb/s", "ms_per_block": ms, "n": n, "m": m, "transform_len": L,
            "rows": g["rows"], "cols": g["cols"], "row_round_size": g["row_round_size"],
-           "kernels": kernel_figures(prof, "large")}
+           "kernels": kernel_figures(prof, "large", geometry_in_effect(pa, L, 0))}
     return res, (k, s, n, m, out.cpu().numpy().view(np.uint64)[: wl.words(m)].copy())
 
 
@@ -581,7 +593,7 @@ def main():
     torch.cuda.synchronize()
     prof = pa.profile_collect()
     pa.profile_enable(False)
-    kernels = kernel_figures(prof, "plain")
+    kernels = kernel_figures(prof, "plain", geometry_in_effect(pa, L, 0))
     for name, st in prof.items():
         kernels[name]["share_of_step"] = st["total_ms"] / st["launches"] / ms
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
@@ -628,7 +640,7 @@ def main():
         torch.cuda.synchronize()
         bprof = pa.profile_collect()
         pa.profile_enable(False)
-        bk = kernel_figures(bprof, "batched")
+        bk = kernel_figures(bprof, "batched", geometry_in_effect(pa, L, 1))
         batched = {"value": args.batch * n / (bms * 1e-3) / 1e9, "unit": "Gb/s", "blocks": args.batch,
                    "ms_per_batch": bms, "kernels": bk,
                    "speedup_vs_plain": args.batch * n / (bms * 1e-3) / 1e9 / value,

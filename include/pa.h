@@ -315,9 +315,12 @@ size_t pa_workspace_bytes(uint64_t n, uint64_t m);
  *   repetitions each after one warm-up (median of HIP-event time): every
  *   valid (log2_rows, tile_width), then every first-round split of the row
  *   transform at the fastest of those, then every fixed row workgroup size
- *   at the fastest so far.  It installs the fastest geometry for the class
- *   of `count` (1: class 0, else class 1) -- the default unless another is
- *   at least 2% faster -- and fills *result.  Allocates and frees its own
+ *   at the fastest so far.  When the fastest is not the default, the two
+ *   are timed again three times each, alternately, and the mean of those
+ *   decides: the geometry installed for the class of `count` (1: class 0,
+ *   else class 1) is the default unless the other is at least 2% faster
+ *   there.  Fills *result (best_us and default_us: the means of the
+ *   alternate timings when they took place).  Allocates and frees its own
  *   device buffers (count * (8 L + bits) bytes; at most 16 GiB, else
  *   PA_ERR_INVALID_ARG) and synchronizes `stream`.  With PA_TUNE_CACHE set
  *   to a file name, it then writes the table to that file (keeping other

@@ -481,7 +481,8 @@ def serving_run(pa, wl, torch, np, count, load, budget_bytes=16 << 30, streams=4
 
 def only_run(pa, wl, torch, np, args):
     """One workload, for profilers: the same inputs, autotuning and launch
-    form as the full run, --steps timed steps after --warmup."""
+    form as the full run, --steps timed steps after --warmup, then --steps
+    more with the library's per-launch event timing (printed per pass)."""
     stream = torch.cuda.current_stream()
     if args.only in ("plain", "batched", "large"):
         n, m = (12_800_000, 1_280_000) if args.only == "large" else (N_BITS, M_BITS)
@@ -513,8 +514,18 @@ def only_run(pa, wl, torch, np, args):
         geo = {"lengths": len({pa.transform_len(sh.n, sh.m) for sh in shapes})}
         bits = sum(sh.n for sh in shapes)
     ms, _ = time_steps(step, args.steps, args.warmup, torch)
+    # the same steps again with the library's per-launch events, so that a
+    # profiler's kernel trace of this process can be set beside them
+    pa.profile_collect()
+    pa.profile_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = pa.profile_collect()
+    pa.profile_enable(False)
     print(json.dumps({"only": args.only, "ms_per_step": ms, "Gbs": bits / (ms * 1e-3) / 1e9, "geometry": geo,
-                      "steps": args.steps, "kernel_source_hash": kernel_source_hash()}))
+                      "steps": args.steps, "kernel_source_hash": kernel_source_hash(),
+                      "event_avg_us": {k: v["avg_ms"] * 1e3 for k, v in prof.items()}}))
 
 
 def main():

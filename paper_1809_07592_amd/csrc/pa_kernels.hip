@@ -347,14 +347,18 @@ __device__ __forceinline__ int inv_off_of(const CXDesc &x, int s) { return x.inv
 // immediate offset (a run-time stride costs an integer add per access),
 // and the seed and key rows share that base.  Shape 0 is the general
 // kernel, which reads the descriptor from the plan.  The shapes are those
-// of the default geometries of the lengths 2^18 .. 27 * 2^19 (column
-// shapes with tiles of kColShapeW columns, the default width).
+// of the default geometries of every length from 2^16 up (column shapes
+// with tiles of kColShapeW columns, the default width).
 struct ShapeSpec {
     int N, nrounds;
     int n3[kMaxRounds], n2[kMaxRounds];
 };
 constexpr ShapeSpec kRowShapeSpec[] = {
     {0, 0, {}, {}},
+    {1024, 4, {0, 0, 0, 0}, {2, 3, 3, 2}},        // 4 8 8 4
+    {1152, 4, {2, 0, 0, 0}, {0, 3, 2, 2}},        // 9 8 4 4
+    {1536, 4, {1, 0, 0, 0}, {1, 3, 3, 2}},        // 6 8 8 4
+    {1728, 4, {2, 1, 0, 0}, {0, 1, 3, 2}},        // 9 6 8 4
     {2048, 4, {0, 0, 0, 0}, {2, 3, 3, 3}},        // 4 8 8 8
     {2304, 4, {2, 0, 0, 0}, {0, 3, 3, 2}},        // 9 8 8 4
     {3072, 4, {1, 0, 0, 0}, {1, 3, 3, 3}},        // 6 8 8 8
@@ -365,9 +369,11 @@ constexpr ShapeSpec kRowShapeSpec[] = {
     {6912, 5, {2, 1, 0, 0, 0}, {0, 1, 3, 2, 2}},  // 9 6 8 4 4
     {9216, 5, {2, 0, 0, 0, 0}, {0, 3, 3, 2, 2}},  // 9 8 8 4 4
     {13824, 5, {2, 1, 0, 0, 0}, {0, 1, 3, 3, 2}}, // 9 6 8 8 4
+    {27648, 5, {2, 1, 0, 0, 0}, {0, 1, 3, 3, 3}}, // 9 6 8 8 8
 };
 constexpr ShapeSpec kColShapeSpec[] = {
     {0, 0, {}, {}},
+    {64, 2, {0, 0}, {3, 3}},          // 8 8
     {128, 2, {0, 0}, {3, 4}},         // 8 16
     {256, 2, {0, 0}, {4, 4}},         // 16 16
     {512, 3, {0, 0, 0}, {3, 3, 3}},   // 8 8 8

@@ -1,8 +1,8 @@
 """Kernels compiled for fixed transform shapes, against the oracle.
 
 The row kernel and the two column kernels have forms compiled for the row
-and column transforms of the default geometries of the lengths
-2^18 .. 27 * 2^19.  Each fixed shape runs here at the smallest length that
+and column transforms of the default geometries of every length from 2^16
+up.  Each fixed shape runs here at the smallest length that
 uses it, on the plain path (seed and key rows in one row kernel), the plan
 path (key row against a resident spectrum, after the spectrum-building mode
 of the same kernel) and a batched call, and must give the oracle's bits
@@ -67,7 +67,7 @@ def _gpu():
 
 
 def test_every_fixed_shape_is_exercised():
-    assert len({r for _, r, _ in SHAPES}) >= 10 and len({c for _, _, c in SHAPES}) >= 4
+    assert len({r for _, r, _ in SHAPES}) >= 15 and len({c for _, _, c in SHAPES}) >= 5
     for L, r, c in SHAPES:
         assert r or c, L
 

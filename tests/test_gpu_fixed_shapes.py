@@ -118,3 +118,35 @@ def test_general_kernels_at_a_fixed_shape_length(a, w, general):
     finally:
         pa.tune_set(L, 0, 0, 0)
         pa.tune_set(L, 1, 0, 0)
+
+
+def extreme_blocks(L, m):
+    """The largest and the smallest n with transform length L for an m that
+    ends inside a word: the output window then ends on L's last word, or
+    the key just exceeds the next shorter length."""
+    words_m = (m + 63) // 64
+    n_max = L - 64 * words_m + 1
+    shorter = max([x for x in pa.supported_lengths() if x < L], default=0)
+    n_min = max(m, 64 * (shorter // 64 - words_m) + 2)
+    out = []
+    for n in (n_max, n_min):
+        if n >= m and pa.transform_len(n, m) == L:
+            out.append(n)
+    return out
+
+
+@pytest.mark.parametrize("L,sh,cs", SHAPES, ids=[f"L{L}_row{r}_col{c}" for L, r, c in SHAPES])
+def test_fixed_shapes_at_the_ends_of_each_length(L, sh, cs):
+    m = 1_037
+    ns = extreme_blocks(L, m)
+    assert ns, L
+    for n in ns:
+        print("L=%d n=%d m=%d" % (L, n, m), flush=True)
+        key, seed = wl.key_and_seed(80 + sh, n, m, cs)
+        want = oracle.toeplitz_hash(key, n, seed, m)
+        dk, ds = dev(key), dev(seed)
+        assert np.array_equal(host(pa.toeplitz_hash(dk, n, ds, m), m), want), ("plain", n)
+        outs = [torch.zeros(wl.words(m), dtype=torch.int64, device="cuda") for _ in range(2)]
+        pa.toeplitz_hash_batched([(dk, n, ds, m, o) for o in outs])
+        for o in outs:
+            assert np.array_equal(host(o, m), want), ("batched", n)

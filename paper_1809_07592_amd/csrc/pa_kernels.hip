@@ -26,6 +26,7 @@
 
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "pa_internal.h"
@@ -348,10 +349,12 @@ __device__ __forceinline__ int inv_off_of(const CXDesc &x, int s) { return x.inv
 // and the seed and key rows share that base.  Shape 0 is the general
 // kernel, which reads the descriptor from the plan.  The shapes are those
 // of the default geometries of every length from 2^16 up (column shapes
-// with tiles of kColShapeW columns, the default width).
+// with tiles of 16 columns, the default width), and the wider column tiles
+// that batches of the shorter lengths may be tuned to.
 struct ShapeSpec {
     int N, nrounds;
     int n3[kMaxRounds], n2[kMaxRounds];
+    int W;  // column shapes: the tile width
 };
 constexpr ShapeSpec kRowShapeSpec[] = {
     {0, 0, {}, {}},
@@ -372,14 +375,16 @@ constexpr ShapeSpec kRowShapeSpec[] = {
     {27648, 5, {2, 1, 0, 0, 0}, {0, 1, 3, 3, 3}}, // 9 6 8 8 8
 };
 constexpr ShapeSpec kColShapeSpec[] = {
-    {0, 0, {}, {}},
-    {64, 2, {0, 0}, {3, 3}},          // 8 8
-    {128, 2, {0, 0}, {3, 4}},         // 8 16
-    {256, 2, {0, 0}, {4, 4}},         // 16 16
-    {512, 3, {0, 0, 0}, {3, 3, 3}},   // 8 8 8
-    {1024, 3, {0, 0, 0}, {3, 4, 3}},  // 8 16 8
+    {0, 0, {}, {}, 0},
+    {64, 2, {0, 0}, {3, 3}, 16},          // 8 8
+    {128, 2, {0, 0}, {3, 4}, 16},         // 8 16
+    {256, 2, {0, 0}, {4, 4}, 16},         // 16 16
+    {512, 3, {0, 0, 0}, {3, 3, 3}, 16},   // 8 8 8
+    {1024, 3, {0, 0, 0}, {3, 4, 3}, 16},  // 8 16 8
+    {128, 2, {0, 0}, {3, 4}, 64},         // 8 16, 64-column tiles
+    {256, 2, {0, 0}, {4, 4}, 64},         // 16 16, 64-column tiles
+    {256, 2, {0, 0}, {4, 4}, 32},         // 16 16, 32-column tiles
 };
-constexpr int kColShapeW = 16;
 
 enum { TAB_ROW = 0, TAB_COL = 1 };
 constexpr int kNumRowShapes = (int)(sizeof(kRowShapeSpec) / sizeof(kRowShapeSpec[0]));
@@ -409,6 +414,7 @@ struct FixedX {
     static constexpr int last_lg = kKindN2[shape_desc(TAB, SH).round[nrounds > 0 ? nrounds - 1 : 0].kind];
     static constexpr int lds_ints = N + (N >> lgpad);
     static constexpr int k3 = shape_spec(TAB, SH).n3[0] + shape_spec(TAB, SH).n3[1];
+    static constexpr int W = shape_spec(TAB, SH).W;  // column shapes
     // product of the radices before stage s (radix-3 stages first); the
     // forward table holds before(s) * (r - 1) factors per stage and the
     // inverse table N / before(s + 1) * (r - 1), so both offsets are
@@ -458,14 +464,17 @@ constexpr bool fixed_shapes_valid() {
 static_assert(fixed_shapes_valid<TAB_ROW, 1>() && fixed_shapes_valid<TAB_COL, 1>(),
               "a fixed shape has no valid descriptor");
 
-static int shape_id(int tab, const XDesc &x) {
+// The fixed shape of table tab whose descriptor equals x field by field
+// (and, for a column shape, whose tile width is W), or 0.
+static int shape_id(int tab, const XDesc &x, int W = 0) {
     for (int i = 1; i < num_shapes(tab); ++i) {
+        if (tab == TAB_COL && shape_spec(tab, i).W != W) continue;
         const XDesc s = shape_desc(tab, i);
         bool same = s.N == x.N && s.nstages == x.nstages && s.nrounds == x.nrounds && s.lgpad == x.lgpad;
         for (int r = 0; same && r < s.nrounds; ++r) {
-            const RoundDesc &a = s.round[r], &b = x.round[r];
-            same = a.kind == b.kind && a.s0 == b.s0 && a.jl_log2 == b.jl_log2 && a.J == b.J && a.M == b.M &&
-                   a.ngroups == b.ngroups;
+            const RoundDesc &p = s.round[r], &q = x.round[r];
+            same = p.kind == q.kind && p.s0 == q.s0 && p.jl_log2 == q.jl_log2 && p.J == q.J && p.M == q.M &&
+                   p.ngroups == q.ngroups;
         }
         for (int st = 0; same && st < s.nstages; ++st) same = s.fwd_off[st] == x.fwd_off[st] && s.inv_off[st] == x.inv_off[st];
         if (same) return i;
@@ -475,7 +484,7 @@ static int shape_id(int tab, const XDesc &x) {
 
 int row_shape_id(const XDesc &x) { return shape_id(TAB_ROW, x); }
 
-int col_shape_id(const LenPlan &hp) { return hp.W == kColShapeW ? shape_id(TAB_COL, hp.col) : 0; }
+int col_shape_id(const LenPlan &hp) { return shape_id(TAB_COL, hp.col, hp.W); }
 
 // Rounds that keep a scheduling fence between stages: the row pass's
 // mixed first rounds of 9 and of 18 to 27 values, where hoisting every
@@ -828,7 +837,7 @@ __device__ __forceinline__ void col_round(const CXDesc &xd, const ctwpair *ftw, 
         using RD = FixedRound<TAB_COL, CS, R::value>;
         static_assert(kKindN3[RD::kind] == 0, "column transforms are radix-2");
         round_io<MODE, 0, kKindN2[RD::kind], FIRST, LAST, 1, false, LND>(RD{}, FixedCol<CS>{}, ftw, itw,
-                                                                         log2_exact(kColShapeW), pre, load, mid,
+                                                                         log2_exact(FixedCol<CS>::W), pre, load, mid,
                                                                          store);
     }
 }
@@ -872,8 +881,10 @@ __global__ void __launch_bounds__(512) k_colfwd(const LenPlan *__restrict__ plan
     const uint32_t *base = (const uint32_t *)(src ? job.seed : job.key) + (koff >> 5);
     const rsrc_t bits = make_rsrc(base, (uint32_t)(((uint32_t)nbits + (uint32_t)ro + 31) / 32 * 4));
     const rsrc_t out = make_rsrc(src ? job.S : job.A, (uint32_t)(lp.L * 4));
-    const int W = CS ? kColShapeW : lp.W, wsh = CS ? log2_exact(kColShapeW) : __builtin_ctz((unsigned)W), C = lp.C;
-    const int c0 = xcd_tile((int)tile, lp.ntiles) * W;
+    const int W = CS ? FixedCol<CS>::W : lp.W, wsh = CS ? log2_exact(FixedCol<CS>::W) : __builtin_ctz((unsigned)W),
+              C = lp.C;
+    // a fixed shape's tiles may be wider than the plan's (C / W of them)
+    const int c0 = xcd_tile((int)tile, CS ? C >> wsh : lp.ntiles) * W;
     int *lds = pa_lds;
     auto pre = [&](int, int, int) PA_INLINE { return NoCtx{}; };
     auto mid = [&](const auto &, auto &, Geo) PA_INLINE {};
@@ -1152,7 +1163,8 @@ __global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan
     const int32_t *A = job.A;
     uint64_t *out = job.out;
     const uint32_t off0 = job.off0, m = job.m;
-    const int W = CS ? kColShapeW : lp.W, wsh = CS ? log2_exact(kColShapeW) : __builtin_ctz((unsigned)W), C = lp.C;
+    const int W = CS ? FixedCol<CS>::W : lp.W, wsh = CS ? log2_exact(FixedCol<CS>::W) : __builtin_ctz((unsigned)W),
+              C = lp.C;
     const int c0 = xcd_tile((int)tile, lp.ntiles) * W;
     int *lds = pa_lds;
     const rsrc_t ain = make_rsrc(A, (uint32_t)(lp.L * 4));
@@ -1331,6 +1343,11 @@ static const void *colinv_fn(bool lg3, bool res, int cs) {
 
 static int g_lds_limit[64];
 
+// The forward column pass's wide tiles, and the fewest workgroups (four
+// per CU) for which a launch uses them.
+constexpr int kWideColW = 64;
+constexpr uint64_t kWideColMinWgs = 1024;
+
 // Largest column-pass output (bytes per launch) written with write-through
 // stores: short launches end sooner without dirty lines to write back; a
 // large batch's column pass streams faster through the write-back L2.
@@ -1416,6 +1433,24 @@ hipError_t launch_colfwd(const LenPlan &hp, const LenPlan *dp, int nsrc, const J
         return hipErrorInvalidConfiguration;
     // write-through stores unless the launch writes more than kColWtBytes
     const bool wt = (double)nsrc * (double)njobs * 4.0 * (double)hp.L <= (double)kColWtBytes;
+    // A launch with many tiles runs the forward pass over 64-column tiles
+    // when a kernel is compiled for them, whatever the plan's width: P1
+    // writes the R x C layout, which does not depend on the tiling, so the
+    // passes may tile it differently.  (256 blocks at n = 10^6: 14% off the
+    // forward pass; P3 is faster with the narrow tiles.)
+    const int wide = shape_id(TAB_COL, hp.col, kWideColW);
+    if (wide && hp.W < kWideColW &&
+        (uint64_t)(hp.C / kWideColW) * (uint64_t)nsrc * (uint64_t)njobs >= kWideColMinWgs) {
+        int items = 0;
+        for (int r = 0; r < hp.col.nrounds; ++r)
+            items = std::max(items, hp.col.round[r].ngroups * kWideColW);
+        const int threads = std::min(512, (items + 63) / 64 * 64);
+        const size_t wlds = (size_t)(hp.R + (hp.R >> hp.col.lgpad)) * kWideColW * sizeof(int);
+        if (wlds <= (size_t)limit)
+            return colfwd_launch(false, wt, wide,
+                                 dim3((unsigned)(hp.C / kWideColW), (unsigned)nsrc, (unsigned)njobs), threads, wlds,
+                                 dp, ja, s, e0, e1);
+    }
     return colfwd_launch(col_max_lg(hp) <= 3, wt, col_shape_id(hp),
                          dim3((unsigned)hp.ntiles, (unsigned)nsrc, (unsigned)njobs), hp.col_threads, lds, dp, ja, s,
                          e0, e1);

@@ -282,8 +282,10 @@ def test_default_geometries_run_fixed_row_kernels(lib):
             assert col_shape_of.setdefault(key, d["col_shape"]) == d["col_shape"], key
     assert len(set(shape_of.values())) == len(shape_of) >= 15
     assert len(set(col_shape_of.values())) == len(col_shape_of) >= 5
-    # tiles of 32 columns: the general column kernels
-    assert pa.plan_info(3 * 2**19, log2_rows=8, tile_width=32)["col_shape"] == 0
+    # R = 512 with 32-column tiles: the general column kernels; R = 256
+    # with 64-column tiles (a batch tuning choice): a fixed one
+    assert pa.plan_info(3 * 2**19, log2_rows=9, tile_width=32)["col_shape"] == 0
+    assert pa.plan_info(3 * 2**19, log2_rows=8, tile_width=64)["col_shape"] != 0
     # R = 128 gives rows of 12288 values: no fixed kernel
     assert pa.plan_info(3 * 2**19, log2_rows=7)["row_shape"] == 0
     # the same row transform inside another length uses the same kernel

@@ -95,11 +95,11 @@ def test_fixed_shapes_match_oracle(L, sh, cs):
     assert np.array_equal(host(outs[1], m), want2), "batched 1"
 
 
-@pytest.mark.parametrize("a,w,general", [(7, 16, "row"), (8, 32, "column"), (0, 0, "")])
+@pytest.mark.parametrize("a,w,general", [(7, 16, "row"), (9, 32, "column"), (0, 0, "")])
 def test_general_kernels_at_a_fixed_shape_length(a, w, general):
     # L = 3 * 2^19: under R = 128 its rows of 12,288 values have no fixed
-    # row kernel; with 32-column tiles no fixed column kernel applies; the
-    # default geometry has both
+    # row kernel; R = 512 with 32-column tiles has no fixed column kernel;
+    # the default geometry has both
     L = 3 * 2**19
     d = pa.plan_info(L, a, w)
     assert (d["row_shape"] == 0) == (general == "row") and (d["col_shape"] == 0) == (general == "column")
@@ -150,3 +150,50 @@ def test_fixed_shapes_at_the_ends_of_each_length(L, sh, cs):
         pa.toeplitz_hash_batched([(dk, n, ds, m, o) for o in outs])
         for o in outs:
             assert np.array_equal(host(o, m), want), ("batched", n)
+
+
+WIDE = [(L, a, w) for L, a, w in [(393216, 7, 64), (1572864, 8, 64), (1572864, 8, 32)]]
+
+
+@pytest.mark.parametrize("L,a,w", WIDE, ids=[f"L{L}_R{2**a}_W{w}" for L, a, w in WIDE])
+def test_wide_tile_column_shapes_match_oracle(L, a, w):
+    # column kernels compiled for 32- and 64-column tiles, which batches of
+    # these lengths may be tuned to
+    assert pa.plan_info(L, a, w)["col_shape"] != 0
+    n, m = block_for(L)
+    key, seed = wl.key_and_seed(90 + w, n, m, a)
+    want = oracle.toeplitz_hash(key, n, seed, m)
+    dk, ds = dev(key), dev(seed)
+    try:
+        for cls in (0, 1):
+            pa.tune_set(L, cls, a, w)
+        assert np.array_equal(host(pa.toeplitz_hash(dk, n, ds, m), m), want)
+        outs = [torch.zeros(wl.words(m), dtype=torch.int64, device="cuda") for _ in range(3)]
+        pa.toeplitz_hash_batched([(dk, n, ds, m, o) for o in outs])
+        for o in outs:
+            assert np.array_equal(host(o, m), want)
+    finally:
+        for cls in (0, 1):
+            pa.tune_set(L, cls, 0, 0)
+
+
+@pytest.mark.parametrize("L", [393216, 1572864])
+def test_many_block_forward_pass_on_wide_tiles(L):
+    # a batch with at least 1024 forward tiles of 64 columns runs the
+    # forward column pass on them (the plan's tiles are 16 columns wide;
+    # the inverse pass keeps those)
+    d = pa.plan_info(L)
+    assert d["tile_width"] == 16 and pa.plan_info(L, 0, 64)["col_shape"] != 0
+    count = -(-1024 // (2 * d["cols"] // 64))
+    m = 20_037
+    n = int(L * 0.9)
+    assert pa.transform_len(n, m) == L
+    blocks, want = [], []
+    for i in range(count):
+        key, seed = wl.key_and_seed(95, n, m, i)
+        want.append(oracle.toeplitz_hash(key, n, seed, m))
+        blocks.append((dev(key), n, dev(seed), m, torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")))
+    print("L=%d: %d blocks" % (L, count), flush=True)
+    pa.toeplitz_hash_batched(blocks)
+    for i, b in enumerate(blocks):
+        assert np.array_equal(host(b[4], m), want[i]), i

@@ -11,7 +11,10 @@ the timed regions (--no-tune keeps the defaults).
 
 Also reported on the same JSON line:
   * batched: 256 blocks of the same shape in one pa_toeplitz_hash_batched
-    call (aggregate input Gb/s);
+    call (aggregate input Gb/s), each with its own seed;
+  * batched_shared_seed: the same keys with one seed shared by all blocks
+    (one Toeplitz matrix per distinct (n, m)), whose spectrum the library
+    builds once per call;
   * batched_uneven: 256 blocks with n log-uniform in [2^18, 2^22] and
     m/n uniform in [0.05, 0.5], own seed each, one batched call (and the
     same call captured once as a graph and replayed: graph_Gbs);
@@ -32,8 +35,9 @@ Also reported on the same JSON line:
     with each launch on its own stream, over a repeat of the timed steps
     (algorithmic bytes and fp64 operations per launch / average duration);
   * parity: the timed outputs of the headline block, the small and the
-    large block and every block of the 256-block batch, compared word for word with
-    the CPU oracle;
+    large block, every block of the 256-block batch, every 16th of the
+    shared-seed batch and every 8th of the uneven batch, compared word for
+    word with the CPU oracle;
   * cpu_baseline: the CPU oracle (packed AND + popcount parity) timed on
     this host's cores on full blocks of the same workload.
 
@@ -623,6 +627,7 @@ def main():
     # batched: args.batch blocks of the same shape in one submission
     batched = None
     batched_io = []
+    shared, shared_io = None, []
     if args.batch > 0:
         blocks = []
         for i in range(args.batch):
@@ -658,6 +663,32 @@ def main():
                    "graph_Gbs": args.batch * n / (gms * 1e-3) / 1e9, "graph_ms_per_batch": gms}
         del blocks
         progress("batched: %.3f ms per %d blocks, %.2f Gb/s" % (bms, args.batch, batched["value"]))
+
+        # the same blocks with one seed shared by all of them (one Toeplitz
+        # matrix per distinct (n, m), the uneven configuration's rule): the
+        # library builds the seed's spectrum once per call and runs every key
+        # against it
+        shared_seed = wl.random_bits(n + m - 1, wl.rng(4, wl.ROLE_SEED, 1 << 20))
+        dss = torch.from_numpy(shared_seed.view(np.int64)).cuda()
+        sblocks = [(torch.from_numpy(io[0].view(np.int64)).cuda(), n, dss, m,
+                    torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")) for io in batched_io]
+
+        def sstep():
+            pa.toeplitz_hash_batched(sblocks, stream=stream)
+
+        sms, _ = time_steps(sstep, bsteps, 2, torch)
+        pa.profile_enable(True)
+        sstep()
+        torch.cuda.synchronize()
+        sprof = pa.profile_collect()
+        pa.profile_enable(False)
+        shared_io = [(batched_io[i][0], shared_seed, n, m, sblocks[i][4].cpu().numpy().view(np.uint64)[: wl.words(m)].copy())
+                     for i in range(0, args.batch, 16)]
+        shared = {"value": args.batch * n / (sms * 1e-3) / 1e9, "unit": "Gb/s", "blocks": args.batch,
+                  "ms_per_batch": sms, "speedup_vs_own_seeds": bms / sms,
+                  "kernels": {k: {"avg_us": v["avg_ms"] * 1e3, "launches": v["launches"]} for k, v in sprof.items()}}
+        del sblocks, dss
+        progress("batched, one shared seed: %.3f ms per %d blocks, %.2f Gb/s" % (sms, args.batch, shared["value"]))
 
     uneven, uneven_io = (batched_uneven_run(pa, wl, torch, np, args.batch, stream, not args.no_tune)
                          if args.batch > 0 else (None, []))
@@ -701,6 +732,8 @@ def main():
     cases = {"small_block_n262144": [small_io], "large_block_n12800000": [large_io]}
     if batched_io:
         cases["batched_256_n1e6"] = batched_io
+    if shared_io:
+        cases["batched_256_n1e6_shared_seed_every_16th_block"] = shared_io
     if uneven_io:
         cases["batched_uneven_every_8th_block"] = uneven_io
     parity = oracle_parity(cases)
@@ -725,7 +758,7 @@ def main():
         "wall_s_timed_region": wall,
         "parity": parity_ok, "parity_detail": parity,
         "roofline": roofline, "roofline_hbm": roofline_hbm, "kernels": kernels,
-        "batched": batched, "batched_uneven": uneven, "large_block": large, "small_block": small, "modified_toeplitz": modified,
+        "batched": batched, "batched_shared_seed": shared, "batched_uneven": uneven, "large_block": large, "small_block": small, "modified_toeplitz": modified,
         "plan_path": planr, "fft_pair": fftp,
         "serving": serving,
         "tuning": tuning, "copy_bandwidth": copy, "alu_probe": alu, "launch_probe": launch, "phase_probe": phase,

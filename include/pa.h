@@ -117,6 +117,12 @@ typedef struct pa_block {
  * over up to four concurrent stream lanes (default); PA_BATCH_FORM=flat
  * instead runs each pass as launches over flat workgroup lists that span
  * all lengths (fewer launches, no overlap between lengths).
+ * Shared seeds (default form): blocks of one transform length whose
+ * seed_bits pointer and seed bit count (n + m - 1) are the same use one
+ * seed spectrum, built once in the call, and run only their keys' passes
+ * against it; the result is the same, the seed's own passes are saved, and
+ * the workspace holds 4 L bytes per such block plus 4 L per shared seed
+ * (8 L per block otherwise).  The library matches pointers, not contents.
  */
 pa_status pa_toeplitz_hash_batched(const pa_block *blocks, uint32_t count,
                                    void *stream);
@@ -131,7 +137,9 @@ pa_status pa_toeplitz_hash_batched(const pa_block *blocks, uint32_t count,
  * key_bits: n bits; v_bits: n-1 bits (device, ceil((n-1)/64) words);
  * out_bits: m bits, tail zero.  Requires 1 <= m < n (V needs a column);
  * otherwise PA_ERR_INVALID_ARG.  Conventions as for pa_toeplitz_hash.
- * The batched form takes pa_block descriptors whose seed_bits field holds v.
+ * The batched form takes pa_block descriptors whose seed_bits field holds v
+ * (blocks sharing a v pointer and n share its spectrum, as shared seeds do
+ * in pa_toeplitz_hash_batched).
  */
 pa_status pa_modified_toeplitz_hash(const uint64_t *key_bits, uint64_t n,
                                     const uint64_t *v_bits, uint64_t m,
@@ -162,7 +170,8 @@ pa_status pa_graph_create(const pa_block *blocks, uint32_t count, int modified, 
 pa_status pa_graph_launch(pa_graph_t graph, void *stream);
 /* Points the graph at other buffers without capturing again: `blocks`
  * must form the same length groups as at creation (same count, and per
- * transform length the same number of blocks; shapes within a group may
+ * transform length the same number of blocks with their own seeds and the
+ * same numbers of blocks per shared seed; shapes within a group may
  * differ), else PA_ERR_INVALID_ARG.  The new job table is copied on
  * `stream`, so replays launched on that stream afterwards use it. */
 pa_status pa_graph_update(pa_graph_t graph, const pa_block *blocks, uint32_t count, void *stream);

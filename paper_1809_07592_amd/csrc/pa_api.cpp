@@ -732,17 +732,42 @@ pa_status prepare_batch(const pa_block *blocks, uint32_t count, bool modified, B
     std::map<uint64_t, std::vector<uint32_t>> groups;
     for (uint32_t i = 0; i < count; ++i) groups[bp->block_len[i]].push_back(i);
     bp->groups.clear();
+    size_t njob_descs = count;
     for (auto &g : groups) {
         BatchPrep::Group gr;
         gr.L = g.first;
         gr.members = g.second;
         PA_TRY(plan_for(g.first, g.second.size() > 1 ? 1 : 0, &gr.plan));
+        if (form == kFormLanes) {
+            // seeds shared by several members of the group (same device
+            // pointer and bit count, so the same spectrum), in first-use order
+            std::map<std::pair<const uint64_t *, uint64_t>, size_t> seen;
+            std::vector<std::vector<uint32_t>> by_seed;
+            for (uint32_t i : gr.members) {
+                const pa_block &b = blocks[i];
+                const auto key = std::make_pair(b.seed_bits, modified ? b.n - 1 : b.n + b.m - 1);
+                auto it = seen.find(key);
+                if (it == seen.end()) {
+                    seen.emplace(key, by_seed.size());
+                    by_seed.push_back({i});
+                } else {
+                    by_seed[it->second].push_back(i);
+                }
+            }
+            for (auto &v : by_seed) {
+                if (v.size() > 1) gr.shared.push_back(std::move(v));
+                else gr.plain.push_back(v[0]);
+            }
+            njob_descs += gr.shared.size();
+        } else {
+            gr.plain = gr.members;
+        }
         bp->groups.push_back(std::move(gr));
     }
     bp->launches.clear();
     size_t region = 0;
     if (form == kFormLanes) {
-        region = (size_t)count * sizeof(pa::JobDesc);
+        region = njob_descs * sizeof(pa::JobDesc);
     } else {
         // the plans first, then per launch its job table and segment array
         bp->plans_off = 0;
@@ -817,30 +842,61 @@ pa_status prepare_batch(const pa_block *blocks, uint32_t count, bool modified, B
         PA_TRY(add(2, form_classes(p2, roww)));
         PA_TRY(add(3, form_classes(p3, colw(true))));
     }
-    // workspace: the table region, then 8L bytes (A and S) per block
+    // workspace: the table region, then 8L bytes (A and S) per plain-path
+    // block, 4L (A) per block sharing a seed and 4L per shared spectrum
     bp->table_bytes = (region + 255) / 256 * 256;
     bp->total_bytes = bp->table_bytes;
-    for (uint32_t i = 0; i < count; ++i) bp->total_bytes += (size_t)(8 * bp->block_len[i]);
+    for (const auto &g : bp->groups) {
+        bp->total_bytes += (size_t)(8 * g.L) * g.plain.size();
+        for (const auto &sh : g.shared) bp->total_bytes += (size_t)(4 * g.L) * (sh.size() + 1);
+    }
     return PA_OK;
 }
 
 // Job descriptors for workspace `ws` (which must hold bp.total_bytes).
 void build_table(BatchPrep &bp, void *ws) {
-    // A and S of every block, in group order
+    // per group: A and S of every plain-path block, A of every block that
+    // shares a seed, then each shared seed's spectrum
     std::vector<pa::JobDesc> desc(bp.blocks.size());
     int32_t *next = (int32_t *)((char *)ws + bp.table_bytes);
     bp.table.clear();
-    size_t first = 0;
+    auto job = [&](uint32_t i, int32_t *A, int32_t *S) {
+        const pa_block &b = bp.blocks[i];
+        return bp.modified ? modified_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, A, S)
+                           : plain_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, A, S);
+    };
     for (auto &g : bp.groups) {
-        g.first = first;
-        for (uint32_t i : g.members) {
-            const pa_block &b = bp.blocks[i];
-            desc[i] = bp.modified ? modified_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, next, next + g.L)
-                                  : plain_job(b.key_bits, b.n, b.seed_bits, b.m, b.out_bits, next, next + g.L);
+        g.first = bp.table.size();
+        for (uint32_t i : g.plain) {
+            desc[i] = job(i, next, next + g.L);
             next += 2 * g.L;
             bp.table.push_back(desc[i]);
         }
-        first += g.members.size();
+        g.first_shared = bp.table.size();
+        std::vector<int32_t *> spec(g.shared.size());
+        for (size_t k = 0; k < g.shared.size(); ++k) {
+            spec[k] = next;
+            next += g.L;
+        }
+        for (size_t k = 0; k < g.shared.size(); ++k)
+            for (uint32_t i : g.shared[k]) {
+                desc[i] = job(i, next, nullptr);
+                desc[i].seed = nullptr;
+                desc[i].Shat = spec[k];
+                next += g.L;
+                bp.table.push_back(desc[i]);
+            }
+        g.first_spec = bp.table.size();
+        for (size_t k = 0; k < g.shared.size(); ++k) {
+            // the spectrum job: the seed as P1's only source, in place
+            const pa_block &b = bp.blocks[g.shared[k][0]];
+            pa::JobDesc j{};
+            j.key = b.seed_bits;
+            j.n = (uint32_t)(bp.modified ? b.n - 1 : b.n + b.m - 1);
+            j.A = spec[k];
+            j.S = spec[k];
+            bp.table.push_back(j);
+        }
     }
     bp.blob.assign(bp.table_bytes, 0);
     if (bp.form == kFormLanes) {
@@ -948,9 +1004,8 @@ pa_status launch_batch(const BatchPrep &bp, void *ws, hipStream_t s) {
     hipStream_t lane_s[1 + kSideStreams];
     PA_TRY(fork_lanes(s, lanes, lane_s));
     pa_status st = PA_OK;
-    for (int gi : order) {
-        const BatchPrep::Group &g = bp.groups[gi];
-        const size_t first = g.first, n = g.members.size();
+    // jobs [first, first + n) of the table in launches of at most 65535
+    auto chunks = [&](size_t first, size_t n, auto &&run) {
         for (size_t off = 0; off < n && st == PA_OK; off += 65535) {
             const int nj = (int)std::min<size_t>(65535, n - off);
             pa::JobArgs ja{};
@@ -958,10 +1013,33 @@ pa_status launch_batch(const BatchPrep &bp, void *ws, hipStream_t s) {
             double in_b = 0, out_b = 0;
             for (size_t k = first + off; k < first + off + (size_t)nj; ++k) {
                 const pa::JobDesc &j = bp.table[k];
-                in_b += words8(j.n) + words8(j.seed_bits) + (bp.modified ? words8(j.m) : 0.0);
-                out_b += words8(j.m);
+                in_b += words8(j.n) + (j.seed ? words8(j.seed_bits) : 0.0) + (j.xor_src ? words8(j.m) : 0.0);
+                out_b += j.out ? words8(j.m) : 0.0;
             }
-            st = run_plain(g.plan, ja, nj, in_b, out_b, lane_s[lane_of[gi]]);
+            st = run(ja, nj, in_b, out_b);
+        }
+    };
+    for (int gi : order) {
+        const BatchPrep::Group &g = bp.groups[gi];
+        const hipStream_t ls = lane_s[lane_of[gi]];
+        chunks(g.first, g.plain.size(), [&](const pa::JobArgs &ja, int nj, double in_b, double out_b) {
+            return run_plain(g.plan, ja, nj, in_b, out_b, ls);
+        });
+        if (!g.shared.empty()) {
+            // the shared seeds' spectra, then their members' key path
+            size_t nsh = 0;
+            for (const auto &sh : g.shared) nsh += sh.size();
+            chunks(g.first_spec, g.shared.size(), [&](const pa::JobArgs &ja, int nj, double in_b, double) {
+                PA_HIP(p1(g.plan, 1, ja, nj, in_b, ls), "launch P1 (seed)");
+                PA_HIP(p2(g.plan, 1, ja, nj, ls), "launch P2 (seed)");
+                return PA_OK;
+            });
+            chunks(g.first_shared, nsh, [&](const pa::JobArgs &ja, int nj, double in_b, double out_b) {
+                PA_HIP(p1(g.plan, 1, ja, nj, in_b, ls), "launch P1");
+                PA_HIP(p2(g.plan, 0, ja, nj, ls), "launch P2");
+                PA_HIP(p3(g.plan, ja, nj, out_b, ls), "launch P3");
+                return PA_OK;
+            });
         }
         if (st != PA_OK) break;
     }

@@ -25,8 +25,9 @@ struct pa_graph_s {
     uint32_t count = 0;
     bool modified = false;
     BatchForm form = kFormLanes;  // launch form captured
-    // length-group signature the launches were captured for: (L, blocks)
-    std::vector<std::pair<uint64_t, size_t>> groups;
+    // group layouts the launches were captured for (length, plain-path
+    // blocks, blocks per shared seed)
+    std::vector<std::vector<uint64_t>> groups;
 };
 
 namespace {
@@ -64,7 +65,7 @@ pa_status pa_graph_create(const pa_block *blocks, uint32_t count, int modified, 
     g->count = count;
     g->modified = modified != 0;
     g->form = bp.form;
-    for (const auto &gr : bp.groups) g->groups.push_back({gr.L, gr.members.size()});
+    for (const auto &gr : bp.groups) g->groups.push_back(gr.layout());
     auto bail = [&](pa_status st) {
         destroy_graph(g);
         return st;
@@ -127,11 +128,12 @@ pa_status pa_graph_update(pa_graph_t graph, const pa_block *blocks, uint32_t cou
     BatchPrep bp;
     PA_TRY(prepare_batch(blocks, count, graph->modified, &bp, graph->form));
     bool same = bp.groups.size() == graph->groups.size();
-    for (size_t i = 0; same && i < bp.groups.size(); ++i)
-        same = bp.groups[i].L == graph->groups[i].first && bp.groups[i].members.size() == graph->groups[i].second;
-    if (!same) return fail(PA_ERR_INVALID_ARG, "blocks need other transform lengths than the graph was built for");
-    // Same groups give the same table layout (descriptors and 2L residues
-    // per block, in group order); the captured launches keep their plans.
+    for (size_t i = 0; same && i < bp.groups.size(); ++i) same = bp.groups[i].layout() == graph->groups[i];
+    if (!same)
+        return fail(PA_ERR_INVALID_ARG,
+                    "blocks need other transform lengths, or share seeds otherwise, than the graph was built for");
+    // Same group layouts give the same table layout (descriptors, residues
+    // and spectra in group order); the captured launches keep their plans.
     build_table(bp, graph->buf);
     return stage_upload((hipStream_t)stream, graph->buf, bp.blob.data(), bp.blob.size());
 }

@@ -108,6 +108,22 @@ struct BatchPrep {
         PlanRef plan{};
         std::vector<uint32_t> members;  // block indices
         size_t first = 0;               // first table entry (after build_table)
+        // Lanes form: members whose seed (device pointer and bit count) no
+        // other member shares run the plain path (plain); members that
+        // share one run the key path against its spectrum, built once
+        // (shared[k]: the members of shared seed k).  Table order per
+        // group: plain jobs, shared members' jobs, one spectrum job per
+        // shared seed.  The flat form puts every member in plain.
+        std::vector<uint32_t> plain;
+        std::vector<std::vector<uint32_t>> shared;
+        size_t first_shared = 0, first_spec = 0;
+        // the group's layout (L, plain count, shared seed sizes), which a
+        // captured graph's launches depend on
+        std::vector<uint64_t> layout() const {
+            std::vector<uint64_t> v{L, plain.size()};
+            for (const auto &sh : shared) v.push_back(sh.size());
+            return v;
+        }
     };
     struct PassLaunch {
         int pass = 0;                   // 1, 2, 3

@@ -57,6 +57,14 @@ __device__ __forceinline__ double reduce_sym(double a) {
     return a - qp;
 }
 
+// Parity of a's representative in [0, P) (a an exact integer, |a| <= 22 P):
+// the symmetric remainder r has the representative r or r + P, and P is
+// odd, so the parity is r's, flipped exactly when r < 0.
+__device__ __forceinline__ unsigned canonical_parity(double a) {
+    const unsigned r = (unsigned)(int)reduce_sym(a);
+    return (r ^ (r >> 31)) & 1u;
+}
+
 // Raw buffer access: base and size in an SGPR resource, 32-bit byte offset
 // per lane (one VGPR instead of a 64-bit address), hardware range check
 // (out-of-range loads return 0, stores are dropped).
@@ -1226,7 +1234,7 @@ __global__ void __launch_bounds__(512) k_colinv(const LenPlan *__restrict__ plan
 #pragma unroll
         for (int l = 0; l < RHO; ++l) {
             const int pos = pos0 + l * jc;
-            mask[l] = __ballot((((int)canonical(v[l]) & 1) != 0) && pos >= 0 && pos < mm);
+            mask[l] = __ballot(canonical_parity(v[l]) != 0 && pos >= 0 && pos < mm);
         }
         if (g.c == 0) {
             if (W == 64) {

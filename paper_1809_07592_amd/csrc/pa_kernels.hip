@@ -1516,7 +1516,7 @@ static hipError_t row_threads_for(int fk, int sh, int plan_threads, size_t rows,
     hipError_t e = rowconv_regs(fk, sh, &regs);
     if (e != hipSuccess) return e;
     int best = 0;
-    for (int t : {512, 768, 1024}) {
+    for (int t : {256, 512, 768, 1024}) {
         if (t > plan_threads) continue;
         const int w = resident_waves(t, regs, lds, limit);
         if (w > best) {

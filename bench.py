@@ -686,7 +686,7 @@ def main():
                      for i in range(0, args.batch, 16)]
         shared = {"value": args.batch * n / (sms * 1e-3) / 1e9, "unit": "Gb/s", "blocks": args.batch,
                   "ms_per_batch": sms, "speedup_vs_own_seeds": bms / sms,
-                  "kernels": {k: {"avg_us": v["avg_ms"] * 1e3, "launches": v["launches"]} for k, v in sprof.items()}}
+                  "kernels": kernel_figures(sprof, "batched_shared_seed", geometry_in_effect(pa, L, 1))}
         del sblocks, dss
         progress("batched, one shared seed: %.3f ms per %d blocks, %.2f Gb/s" % (sms, args.batch, shared["value"]))
 

@@ -104,6 +104,23 @@ def test_batched_matches_single_and_oracle():
             assert np.array_equal(host(pa.modified_toeplitz_hash(blocks[i][0], n, blocks[i][2], m), m), want)
 
 
+def test_large_batch_on_wide_forward_tiles_matches_oracle():
+    # 16 blocks of n = 10^6 at L = 2^20 give the forward column pass 2048
+    # tiles of 64 columns, so it runs on wide tiles, reading each key suffix
+    # from bit m; each block equals the oracle
+    n, m = 1_000_000, 250_000
+    d = pa.plan_info(pa.transform_len(n - m, m))
+    assert 2 * (d["cols"] // 64) * 16 >= 1024 and pa.plan_info(d["transform_len"], 0, 64)["col_shape"] != 0
+    ins, blocks = [], []
+    for i in range(16):
+        key, v = inputs(57, n, m, i)
+        ins.append((key, v))
+        blocks.append((dev(key), n, dev(v), m, torch.zeros(wl.words(m), dtype=torch.int64, device="cuda")))
+    outs = pa.modified_toeplitz_hash_batched(blocks)
+    for i, (key, v) in enumerate(ins):
+        assert np.array_equal(host(outs[i], m), oracle.modified_toeplitz_hash(key, n, v, m)), i
+
+
 def test_transform_is_shorter_than_plain():
     # the Toeplitz part spans (n - m) + m = n instead of n + m
     assert pa.transform_len(1_000_000 - 250_000, 250_000) == 2**20 < pa.transform_len(1_000_000, 250_000)

@@ -35,13 +35,28 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    """Always recompiles libpa.so (atomically replaces the old file)."""
+    """Always recompiles libpa.so (atomically replaces the old file): every
+    source to an object in parallel, then one link."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    with tempfile.TemporaryDirectory(prefix="pa_build_") as objdir:
+        def compile_one(src):
+            obj = os.path.join(objdir, src + ".o")
+            cmd = [hipcc()] + compile_flags + inc + ["-c", os.path.join(CSRC, src), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.check_call(cmd)
+            return obj
+        workers = max(1, min(len(SOURCES), os.cpu_count() or 4, 16))
+        with ThreadPoolExecutor(workers) as ex:
+            objs = list(ex.map(compile_one, SOURCES))
+        link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.check_call(link)
     os.replace(tmp, LIB)
     return LIB
 
